@@ -1,0 +1,24 @@
+"""CPU oracle for the consensus-ADMM (CADMM) trajectory sweep.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, links or runs
+anything in this package: only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may use it.  It shares no code, tables or
+helpers with the HIP library; the two meet only at the seeded inputs drawn by
+``paper_2507_10290_amd.workloads``.
+
+Everything here is plain float64 PyTorch-on-CPU (so ``torch.autograd`` gives
+the oracle's own gradients), written in the paper's variables and order:
+
+* ``polynomial``  — the basis beta^(o)(t), the cost Gram matrix Q(T), the
+  boundary map M(T) and the knot-state map (Sec. III-D.1).
+* ``cadmm``       — Algorithm 1 with the closed-form local update, keeping the
+  paper's variables c, z, u, s, v, phi, w as they are printed.
+* ``minimal``     — the same iteration with the slack/dual pairs folded into
+  one value per constraint row (used only to pin that algebra).
+* ``references``  — direct solutions the iteration must converge to: the
+  global KKT system, the square optimality-condition system, and a
+  general-purpose constrained solve.
+
+Functions whose result no independent check pins say "parity unpinned" in
+their docstring.
+"""
