@@ -1,0 +1,167 @@
+/*
+ * top.h -- C ABI of the MI355X consensus-ADMM (CADMM) trajectory sweep.
+ *
+ * The library solves, for a batch of independent trajectories, the
+ * piecewise-polynomial minimum-effort problem of the TOP paper (arXiv
+ * 2507.10290): Sec. III-A states the problem (cost int sigma^(p)T sigma^(p),
+ * end states sigma_0 / sigma_N, continuity between segments), Sec. III-B
+ * turns it into a consensus problem over knot states z with scaled duals u,
+ * Sec. III-C adds the corridor (linear inequalities with slack s and dual v)
+ * and the velocity ball (quadratic inequality with split phi and dual w), and
+ * Sec. III-D.1 gives the per-segment closed-form update rules (eqs.
+ * QpSubProblem, UpdateZ, UpdateU, NonNegativeProject, UpdateV,
+ * DynamicProject, UpdateCloseW).  Each call of top_iterate runs k passes of
+ * Algorithm 1's loop body with fixed rho over every segment of every
+ * trajectory.
+ *
+ * Conventions
+ *   - Trajectories are given in CSR form: trajectory b owns segments
+ *     seg_offsets[b] .. seg_offsets[b+1]-1 (S = seg_offsets[B] in total) and
+ *     the S+B waypoint rows seg_offsets[b]+b .. seg_offsets[b+1]+b.
+ *   - Arrays marked [dev] are device pointers, valid on the stream passed to
+ *     top_create; arrays marked [host] are host pointers.  All [dev] inputs
+ *     are float64 whatever the iterate precision.
+ *   - Inputs are read during top_create only; the library keeps its own
+ *     copies (in the iterate precision, or float64 where noted) and owns all
+ *     device memory it allocates, which top_destroy releases.  The caller owns
+ *     every output buffer.
+ *   - Every call that launches work is asynchronous on the handle's stream:
+ *     outputs are ready once that stream has been synchronised.
+ *   - A handle is not thread-safe; use one handle per host thread.
+ *   - Errors: every call returns a top_status.  Argument errors are reported
+ *     before any work is queued and leave the handle unchanged.  A non-finite
+ *     iterate is flagged on the device and reported by top_sync_status.
+ *     top_last_error() gives a thread-local message for the last failure.
+ */
+#ifndef TOP_H_
+#define TOP_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct top_problem top_problem;
+
+typedef enum top_status {
+  TOP_OK = 0,
+  TOP_E_INVALID = -1,      /* an argument is null, out of range or not finite          */
+  TOP_E_HIP = -3,          /* a HIP runtime call failed                                 */
+  TOP_E_STATE = -4,        /* the call is not valid in the handle's current state       */
+  TOP_E_NONFINITE = -5,    /* an iterate became NaN or infinite                         */
+  TOP_E_UNSUPPORTED = -6,  /* the option combination is not implemented                */
+  TOP_E_NOMEM = -7         /* a host or device allocation failed                        */
+} top_status;
+
+enum { TOP_FP32 = 0, TOP_FP64 = 1 };
+
+/* Problem and execution options (host struct, copied by top_create). */
+typedef struct top_options {
+  int32_t order;             /* p: 3 = minimum jerk (quintic), 4 = minimum snap (septic) (Sec. III-A) */
+  int32_t n_cont;            /* s: derivative orders 0..s-1 shared at interior knots, s in {p, p+1};
+                                0 selects s = p (Sec. III-B, eq. Consensus_problem)                   */
+  int32_t fix_interior;      /* 1: interior knot positions are pinned to the waypoints;
+                                0: they are averaged like the other orders (Sec. III-D.2)              */
+  int32_t n_samples;         /* M: constraint samples per segment at t_j = j T/(M+1), j = 1..M;
+                                only 8 is built (0 selects 8) (Sec. III-D.1)                          */
+  int32_t precision;         /* TOP_FP32 or TOP_FP64 iterates; the per-segment factorisation and all
+                                reductions are float64 in both                                       */
+  int32_t checkpoint_every;  /* m > 0 records the state every m sweeps so top_backward can run;
+                                0 records nothing                                                     */
+  int32_t max_taped_iters;   /* sweeps the tape can hold when checkpoint_every > 0                    */
+  int32_t tile_lanes;        /* segments per workgroup tile, a multiple of 64 in [64, 1024];
+                                0 picks the default (or the tuned value after top_tune)               */
+  int32_t halo;              /* sweeps per launch for trajectories longer than a tile (their halo
+                                width); 0 picks the default                                           */
+  int32_t use_graph;         /* 1: replay each top_iterate(k) launch sequence as a cached hipGraph    */
+} top_options;
+
+/* Fill *opt with the defaults: p = 3, s = p, pinned interior, M = 8, FP32, no tape, graph on. */
+void top_default_options(top_options* opt);
+
+/* Create a problem and run Init (Algorithm 1) on `stream`.
+ *   n_traj       B >= 1
+ *   seg_offsets  [host] int64 [B+1], seg_offsets[0] = 0, strictly increasing (every trajectory
+ *                has at least one segment)
+ *   waypoints    [dev] [S+B][3] path points P (Alg. 1 input)
+ *   durations    [dev] [S] segment durations T_i > 0 (Sec. III-A)
+ *   bc           [dev] [B][2][p][3] end states sigma_0, sigma_N (position and derivatives up to
+ *                p-1, eq. start_points_constraints), or NULL for rest at the end waypoints.  The
+ *                position rows must equal the end waypoints when fix_interior is set.
+ *   box_lo/hi    [dev] [S][3] axis-aligned corridor per segment (the K = 6 polytope of
+ *                Sec. III-D.1), or both NULL for no corridor; lo < hi
+ *   vmax         [dev] [B] velocity-norm bound per trajectory (Sec. III-C.2), > 0, or NULL
+ *   rho          [dev] [B] penalty per trajectory, > 0
+ *   opt          [host] options, NULL for the defaults
+ *   stream       HIP stream all work of this handle is queued on (0 = the null stream)
+ *   out          receives the handle; set to NULL on failure
+ * Blocks once, to validate the device inputs. */
+top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
+                      const double* durations, const double* bc, const double* box_lo,
+                      const double* box_hi, const double* vmax, const double* rho,
+                      const top_options* opt, hipStream_t stream, top_problem** out);
+
+/* Queue k >= 0 more sweeps (Algorithm 1 loop body with fixed rho: ClosedFormSolve,
+ * UpdateConsensus, UpdateResidual, ProjectNonNeg, UpdateDual).  Asynchronous. */
+top_status top_iterate(top_problem* h, int32_t k);
+
+/* [dev] float64 [B] outputs: ||r_p|| and ||r_d|| of the last sweep (eqs. splitting_primal_residual
+ * and splitting_dual_residual, the dual residual read per segment as rho M~(T_i)^T (z~^{k+1}-z~^k)).
+ * Either pointer may be NULL.  TOP_E_STATE before the first sweep. */
+top_status top_residuals(const top_problem* h, double* r_primal, double* r_dual);
+
+/* [dev] float64 [B]: the objective sum_i c_i^T Q~(T_i) c_i of the last local solves (Sec. III-D.1). */
+top_status top_cost(const top_problem* h, double* cost);
+
+/* [dev] float64 [S][3][2p]: the last local solves c_i (the output C of Algorithm 1), monomial
+ * coefficients in ascending powers of the segment-local time; after 0 sweeps, the Init guess. */
+top_status top_coeffs(const top_problem* h, double* coeffs);
+
+/* Reverse-mode derivative of sum_b dcost[b] * J_b (J from top_cost after all sweeps so far) with
+ * respect to the waypoints and durations, through Init and every sweep; corridor, vmax, rho and bc
+ * are held constant.  Needs checkpoint_every > 0 and at most max_taped_iters sweeps so far.
+ *   dcost       [dev] float64 [B]
+ *   dwaypoints  [dev] float64 [S+B][3] (overwritten), or NULL
+ *   ddurations  [dev] float64 [S] (overwritten), or NULL
+ * TOP_E_STATE without a tape or after too many sweeps. */
+top_status top_backward(top_problem* h, const double* dcost, double* dwaypoints, double* ddurations);
+
+/* Time the candidate tile shapes on this problem (k_probe sweeps each, on scratch state, leaving the
+ * iterate untouched), keep the fastest and remember it for problems of the same shape class.
+ * Blocks.  A tile shape given explicitly in the options is not overridden. */
+top_status top_tune(top_problem* h, int32_t k_probe);
+
+/* Block on the stream; TOP_E_NONFINITE if any sweep so far produced a non-finite value. */
+top_status top_sync_status(top_problem* h);
+
+/* Execution plan actually in use (host struct). */
+typedef struct top_plan_info {
+  int32_t tile_lanes;        /* lanes (segments) per workgroup tile                         */
+  int32_t n_tiles;           /* workgroups per launch                                       */
+  int32_t halo;              /* sweeps per launch when some trajectory is split, else 0     */
+  int32_t n_traj;
+  int64_t n_seg;
+  int64_t used_lanes;        /* lanes holding a segment, halo copies included               */
+  int32_t precision;
+  int32_t order;
+  int32_t n_cont;
+  int32_t iters_done;        /* sweeps run since top_create                                 */
+} top_plan_info;
+
+top_status top_get_plan(const top_problem* h, top_plan_info* info);
+
+/* Release the handle and every device buffer it owns (waits for its stream first). NULL is a no-op. */
+void top_destroy(top_problem* h);
+
+/* Thread-local text of the last error reported by this library on the calling thread. */
+const char* top_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TOP_H_ */

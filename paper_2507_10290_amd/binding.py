@@ -1,0 +1,268 @@
+"""ctypes binding of libtop.so (include/top.h): argument marshalling only.
+
+Every step of the sweep runs in the HIP library; PyTorch only supplies device
+memory and the stream.  Importing this module does not touch the GPU; the
+first call loads ``libtop.so`` from this package directory and raises if it
+is missing (build it with ``python -m paper_2507_10290_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtop.so")
+
+TOP_OK = 0
+TOP_E_INVALID = -1
+TOP_E_HIP = -3
+TOP_E_STATE = -4
+TOP_E_NONFINITE = -5
+TOP_E_UNSUPPORTED = -6
+TOP_E_NOMEM = -7
+TOP_FP32 = 0
+TOP_FP64 = 1
+
+STATUS_NAMES = {0: "TOP_OK", -1: "TOP_E_INVALID", -3: "TOP_E_HIP", -4: "TOP_E_STATE",
+                -5: "TOP_E_NONFINITE", -6: "TOP_E_UNSUPPORTED", -7: "TOP_E_NOMEM"}
+
+# Every entry point declared in include/top.h.
+EXPORTED = ["top_default_options", "top_create", "top_iterate", "top_residuals", "top_cost",
+            "top_coeffs", "top_backward", "top_tune", "top_sync_status", "top_get_plan",
+            "top_destroy", "top_last_error"]
+
+
+class TopOptions(ctypes.Structure):
+    _fields_ = [("order", ctypes.c_int32), ("n_cont", ctypes.c_int32), ("fix_interior", ctypes.c_int32),
+                ("n_samples", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("checkpoint_every", ctypes.c_int32), ("max_taped_iters", ctypes.c_int32),
+                ("tile_lanes", ctypes.c_int32), ("halo", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+
+
+class TopPlanInfo(ctypes.Structure):
+    _fields_ = [("tile_lanes", ctypes.c_int32), ("n_tiles", ctypes.c_int32), ("halo", ctypes.c_int32),
+                ("n_traj", ctypes.c_int32), ("n_seg", ctypes.c_int64), ("used_lanes", ctypes.c_int64),
+                ("precision", ctypes.c_int32), ("order", ctypes.c_int32), ("n_cont", ctypes.c_int32),
+                ("iters_done", ctypes.c_int32)]
+
+
+class TopError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if libtop.so has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2507_10290_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64p, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p
+    L.top_default_options.argtypes = [ctypes.POINTER(TopOptions)]
+    L.top_default_options.restype = None
+    L.top_create.argtypes = [i32, i64p, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(TopOptions), vp,
+                             ctypes.POINTER(vp)]
+    L.top_create.restype = ctypes.c_int
+    L.top_iterate.argtypes = [vp, i32]
+    L.top_iterate.restype = ctypes.c_int
+    L.top_residuals.argtypes = [vp, dp, dp]
+    L.top_residuals.restype = ctypes.c_int
+    L.top_cost.argtypes = [vp, dp]
+    L.top_cost.restype = ctypes.c_int
+    L.top_coeffs.argtypes = [vp, dp]
+    L.top_coeffs.restype = ctypes.c_int
+    L.top_backward.argtypes = [vp, dp, dp, dp]
+    L.top_backward.restype = ctypes.c_int
+    L.top_tune.argtypes = [vp, i32]
+    L.top_tune.restype = ctypes.c_int
+    L.top_sync_status.argtypes = [vp]
+    L.top_sync_status.restype = ctypes.c_int
+    L.top_get_plan.argtypes = [vp, ctypes.POINTER(TopPlanInfo)]
+    L.top_get_plan.restype = ctypes.c_int
+    L.top_destroy.argtypes = [vp]
+    L.top_destroy.restype = None
+    L.top_last_error.argtypes = []
+    L.top_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != TOP_OK:
+        raise TopError(status, lib().top_last_error().decode(errors="replace"))
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _dev(x, device):
+    """float64, contiguous, on the device (torch is only the allocator here)."""
+    import torch
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64))
+    return x.to(device=device, dtype=torch.float64).contiguous()
+
+
+def default_options() -> TopOptions:
+    o = TopOptions()
+    lib().top_default_options(ctypes.byref(o))
+    return o
+
+
+# ---------------------------------------------------------------------------
+# Thin functions with the C names (handles are integers).
+# ---------------------------------------------------------------------------
+
+def top_create(seg_offsets: Sequence[int], waypoints, durations, rho, *, bc=None, box_lo=None,
+               box_hi=None, vmax=None, options: Optional[TopOptions] = None, stream: int = 0) -> int:
+    """Device tensors (float64) in, handle out.  seg_offsets is a host int64 sequence."""
+    offs = np.ascontiguousarray(np.asarray(seg_offsets, dtype=np.int64))
+    h = ctypes.c_void_p()
+    st = lib().top_create(int(offs.shape[0] - 1), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                          _ptr(waypoints), _ptr(durations), _ptr(bc), _ptr(box_lo), _ptr(box_hi),
+                          _ptr(vmax), _ptr(rho), None if options is None else ctypes.byref(options),
+                          ctypes.c_void_p(stream), ctypes.byref(h))
+    _check(st)
+    return h.value
+
+
+def top_iterate(h: int, k: int) -> None:
+    _check(lib().top_iterate(ctypes.c_void_p(h), int(k)))
+
+
+def top_residuals(h: int, r_primal, r_dual) -> None:
+    _check(lib().top_residuals(ctypes.c_void_p(h), _ptr(r_primal), _ptr(r_dual)))
+
+
+def top_cost(h: int, cost) -> None:
+    _check(lib().top_cost(ctypes.c_void_p(h), _ptr(cost)))
+
+
+def top_coeffs(h: int, coeffs) -> None:
+    _check(lib().top_coeffs(ctypes.c_void_p(h), _ptr(coeffs)))
+
+
+def top_backward(h: int, dcost, dwaypoints, ddurations) -> None:
+    _check(lib().top_backward(ctypes.c_void_p(h), _ptr(dcost), _ptr(dwaypoints), _ptr(ddurations)))
+
+
+def top_tune(h: int, k_probe: int) -> None:
+    _check(lib().top_tune(ctypes.c_void_p(h), int(k_probe)))
+
+
+def top_sync_status(h: int) -> None:
+    _check(lib().top_sync_status(ctypes.c_void_p(h)))
+
+
+def top_get_plan(h: int) -> dict:
+    info = TopPlanInfo()
+    _check(lib().top_get_plan(ctypes.c_void_p(h), ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in TopPlanInfo._fields_}
+
+
+def top_destroy(h: int) -> None:
+    lib().top_destroy(ctypes.c_void_p(h))
+
+
+# ---------------------------------------------------------------------------
+# Convenience wrapper.
+# ---------------------------------------------------------------------------
+
+class TopProblem:
+    """A batch of trajectories on one GPU, owned by one library handle."""
+
+    def __init__(self, seg_offsets, waypoints, durations, rho, *, order: int = 3, n_cont: int = 0,
+                 bc=None, box_lo=None, box_hi=None, vmax=None, precision: str = "fp32",
+                 fix_interior: bool = True, checkpoint_every: int = 0, max_taped_iters: int = 0,
+                 tile_lanes: int = 0, halo: int = 0, use_graph: bool = True, device: str = "cuda:0",
+                 stream=None):
+        import torch
+        self.device = torch.device(device)
+        self.seg_offsets = np.asarray(seg_offsets, dtype=np.int64)
+        self.B = int(self.seg_offsets.shape[0] - 1)
+        self.S = int(self.seg_offsets[-1])
+        self.order = int(order)
+        self.n = 2 * self.order
+        o = default_options()
+        o.order = self.order
+        o.n_cont = int(n_cont)
+        o.fix_interior = 1 if fix_interior else 0
+        o.precision = TOP_FP64 if precision == "fp64" else TOP_FP32
+        o.checkpoint_every = int(checkpoint_every)
+        o.max_taped_iters = int(max_taped_iters)
+        o.tile_lanes = int(tile_lanes)
+        o.halo = int(halo)
+        o.use_graph = 1 if use_graph else 0
+        self.options = o
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        args = [_dev(x, self.device) for x in (waypoints, durations, rho, bc, box_lo, box_hi, vmax)]
+        self.h = top_create(self.seg_offsets, args[0], args[1], args[2], bc=args[3], box_lo=args[4],
+                            box_hi=args[5], vmax=args[6], options=o, stream=self.stream.cuda_stream)
+
+    @classmethod
+    def from_workload(cls, w, **kw):
+        kw.setdefault("precision", w.precision)
+        return cls(w.seg_offsets, w.waypoints, w.durations, w.rho, order=w.order, n_cont=w.n_cont,
+                   bc=w.bc, box_lo=w.box_lo, box_hi=w.box_hi, vmax=w.vmax,
+                   fix_interior=w.fix_interior, **kw)
+
+    def _empty(self, *shape):
+        import torch
+        return torch.empty(*shape, dtype=torch.float64, device=self.device)
+
+    def iterate(self, k: int) -> "TopProblem":
+        top_iterate(self.h, k)
+        return self
+
+    def residuals(self):
+        rp, rd = self._empty(self.B), self._empty(self.B)
+        top_residuals(self.h, rp, rd)
+        return rp, rd
+
+    def cost(self):
+        J = self._empty(self.B)
+        top_cost(self.h, J)
+        return J
+
+    def coeffs(self):
+        c = self._empty(self.S, 3, self.n)
+        top_coeffs(self.h, c)
+        return c
+
+    def backward(self, dcost):
+        dcost = _dev(dcost, self.device)
+        dP, dT = self._empty(self.S + self.B, 3), self._empty(self.S)
+        top_backward(self.h, dcost, dP, dT)
+        return dP, dT
+
+    def tune(self, k_probe: int = 20) -> dict:
+        top_tune(self.h, k_probe)
+        return self.plan()
+
+    def sync_status(self) -> None:
+        top_sync_status(self.h)
+
+    def plan(self) -> dict:
+        return top_get_plan(self.h)
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            top_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

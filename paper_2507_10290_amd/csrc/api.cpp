@@ -1,0 +1,657 @@
+// C ABI of the CADMM sweep library: argument checks, device buffers, the tile
+// planner, launch sequencing (optionally replayed as hipGraphs), the tile
+// autotuner and the output queries.  See include/top.h for the contract.
+#include "top.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "common.h"
+
+namespace {
+
+thread_local std::string g_err = "";
+
+top_status fail(top_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define TOP_HIP(call)                                                                     \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(TOP_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+int max_tile(const top::Variant& v) { return v.prec == 0 ? (v.p == 3 ? 512 : 256) : 256; }
+
+struct Plan {
+  int W = 0;
+  int n_tiles = 0;
+  int halo = 0;          // > 0 when some trajectory is split across tiles
+  int64_t used = 0;
+  std::vector<int32_t> lanes;
+};
+
+// Pack whole trajectories of at most W segments into W-lane tiles (first-fit decreasing); split
+// longer ones into tiles whose core segments are flanked by up to `halo` copied neighbours.
+Plan make_plan(const std::vector<int64_t>& off, int W, int halo) {
+  Plan pl;
+  pl.W = W;
+  const int B = (int)off.size() - 1;
+  std::vector<int> shorts, longs;
+  for (int b = 0; b < B; ++b) ((off[b + 1] - off[b]) <= W ? shorts : longs).push_back(b);
+  std::stable_sort(shorts.begin(), shorts.end(), [&](int x, int y) {
+    return (off[x + 1] - off[x]) > (off[y + 1] - off[y]);
+  });
+  std::vector<int> fill;
+  std::vector<std::vector<int>> bins;
+  int first_open = 0;  // bins before this index are full to within the smallest length seen
+  for (int b : shorts) {
+    const int len = (int)(off[b + 1] - off[b]);
+    int k = -1;
+    for (int i = first_open; i < (int)bins.size(); ++i)
+      if (fill[i] + len <= W) { k = i; break; }
+    if (k < 0) {
+      k = (int)bins.size();
+      bins.emplace_back();
+      fill.push_back(0);
+    }
+    bins[k].push_back(b);
+    fill[k] += len;
+    while (first_open < (int)bins.size() && fill[first_open] == W) ++first_open;
+  }
+  for (size_t i = 0; i < bins.size(); ++i) {
+    std::vector<int32_t> t(W, -1);
+    int pos = 0;
+    for (int b : bins[i])
+      for (int64_t s = off[b]; s < off[b + 1]; ++s) t[pos++] = (int32_t)s;
+    pl.used += pos;
+    pl.lanes.insert(pl.lanes.end(), t.begin(), t.end());
+  }
+  if (!longs.empty()) pl.halo = halo;
+  for (int b : longs) {
+    const int64_t N = off[b + 1] - off[b];
+    int64_t c0 = 0;
+    while (c0 < N) {
+      const int64_t left = c0 > 0 ? halo : 0;
+      int64_t c1;
+      if (c0 - left + W >= N) c1 = N;
+      else c1 = c0 + W - left - halo;
+      const int64_t l0 = c0 - left, l1 = std::min<int64_t>(N, c1 + halo);
+      std::vector<int32_t> t(W, -1);
+      for (int64_t s = l0; s < l1; ++s) {
+        const int64_t seg = off[b] + s;
+        t[s - l0] = (int32_t)seg | ((s < c0 || s >= c1) ? top::kHaloBit : 0);
+      }
+      pl.used += l1 - l0;
+      pl.lanes.insert(pl.lanes.end(), t.begin(), t.end());
+      c0 = c1;
+    }
+  }
+  pl.n_tiles = (int)(pl.lanes.size() / W);
+  return pl;
+}
+
+// Shape class of a problem for the tuning cache.
+std::string shape_key(const top::Variant& v, const std::vector<int64_t>& off) {
+  int64_t mx = 0;
+  for (size_t b = 0; b + 1 < off.size(); ++b) mx = std::max(mx, off[b + 1] - off[b]);
+  const int64_t S = off.back();
+  auto lg = [](int64_t x) { int r = 0; while (x > 1) { x >>= 1; ++r; } return r; };
+  char buf[128];
+  snprintf(buf, sizeof buf, "v1:prec%d:p%d:s%d:box%d:vel%d:logS%d:logmax%d", v.prec, v.p, v.s, v.box,
+           v.vel, lg(S), lg(mx));
+  return buf;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;  // shape -> (W, halo)
+bool g_tune_loaded = false;
+
+void tune_cache_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("TOP_TUNE_CACHE");
+  if (path == nullptr) return;
+  FILE* f = std::fopen(path, "r");
+  if (f == nullptr) return;
+  char key[160];
+  int W, h;
+  while (std::fscanf(f, "%159s %d %d", key, &W, &h) == 3) g_tune[key] = {W, h};
+  std::fclose(f);
+}
+
+void tune_cache_store() {
+  const char* path = std::getenv("TOP_TUNE_CACHE");
+  if (path == nullptr) return;
+  FILE* f = std::fopen(path, "w");
+  if (f == nullptr) return;
+  for (auto& kv : g_tune) std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+  std::fclose(f);
+}
+
+}  // namespace
+
+struct top_problem {
+  top_options opt{};
+  top::Variant v{};
+  int B = 0;
+  int64_t S = 0, ld = 0;
+  int nf = 0;
+  size_t rsz = 4;
+  std::vector<int64_t> off;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  std::vector<void*> allocs;
+  // device buffers
+  void *Hr = nullptr, *iT = nullptr, *lo = nullptr, *hi = nullptr, *vmax = nullptr, *bcL = nullptr;
+  void* state[2] = {nullptr, nullptr};
+  void *cbuf = nullptr, *zold = nullptr, *scratch = nullptr;
+  uint8_t* flags = nullptr;
+  int32_t* traj = nullptr;
+  double *Tdev = nullptr, *rho_seg = nullptr, *part = nullptr, *out = nullptr;
+  int64_t* off_dev = nullptr;
+  int* flag_dev = nullptr;
+  int32_t* lanes_dev = nullptr;
+  size_t lanes_cap = 0;
+  Plan plan;
+  int cur = 0;
+  int iters_done = 0;
+  bool have_sweep = false;
+  bool explicit_tile = false;
+  // tape: slot j holds the state before sweep j * checkpoint_every
+  void* tape = nullptr;
+  int tape_slots = 0;
+  std::map<std::tuple<int, int>, hipGraphExec_t> graphs;
+  std::vector<hipGraph_t> graph_defs;
+
+  template <typename T>
+  top_status alloc(T** p, size_t bytes) {
+    void* q = nullptr;
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(&q, bytes);
+    if (e != hipSuccess) return fail(TOP_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    allocs.push_back(q);
+    *p = reinterpret_cast<T*>(q);
+    return TOP_OK;
+  }
+
+  top_status upload_plan(const Plan& pl) {
+    const size_t bytes = pl.lanes.size() * sizeof(int32_t);
+    if (bytes > lanes_cap) {
+      void* q = nullptr;
+      hipError_t e = hipMalloc(&q, bytes);
+      if (e != hipSuccess) return fail(TOP_E_NOMEM, "hipMalloc(%zu) failed", bytes);
+      if (lanes_dev != nullptr) {
+        TOP_HIP(hipStreamSynchronize(stream));
+        (void)hipFree(lanes_dev);
+      }
+      lanes_dev = static_cast<int32_t*>(q);
+      lanes_cap = bytes;
+    }
+    TOP_HIP(hipMemcpyAsync(lanes_dev, pl.lanes.data(), bytes, hipMemcpyHostToDevice, stream));
+    TOP_HIP(hipStreamSynchronize(stream));
+    return TOP_OK;
+  }
+
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+    for (auto g : graph_defs) (void)hipGraphDestroy(g);
+    graph_defs.clear();
+  }
+
+  template <typename R>
+  top::SweepArgs<R> sweep_args(const Plan& pl) const {
+    top::SweepArgs<R> a{};
+    a.k.Hr = (const R*)Hr;
+    a.k.iT = (const R*)iT;
+    a.k.lo = (const R*)lo;
+    a.k.hi = (const R*)hi;
+    a.k.vmax = (const R*)vmax;
+    a.k.flags = flags;
+    a.k.traj = traj;
+    a.k.bcL = (const R*)bcL;
+    a.k.ld = ld;
+    a.lane_seg = lanes_dev;
+    a.W = pl.W;
+    a.fixpos = opt.fix_interior;
+    a.c_out = (R*)cbuf;
+    a.zold_out = (R*)zold;
+    return a;
+  }
+
+  template <typename R>
+  top_status launch_one(const Plan& pl, const void* in, void* outp, int n, bool fin, hipStream_t st) {
+    top::SweepArgs<R> a = sweep_args<R>(pl);
+    a.st_in = (const R*)in;
+    a.st_out = (R*)outp;
+    a.iters = n;
+    a.final_out = fin ? 1 : 0;
+    hipError_t e = top::launch_sweep<R>(v, a, pl.n_tiles, st);
+    if (e != hipSuccess) return fail(TOP_E_HIP, "sweep launch failed: %s", hipGetErrorString(e));
+    return TOP_OK;
+  }
+
+  top_status sweep_launch(const Plan& pl, const void* in, void* outp, int n, bool fin, hipStream_t st) {
+    return v.prec == 0 ? launch_one<float>(pl, in, outp, n, fin, st) : launch_one<double>(pl, in, outp, n, fin, st);
+  }
+
+  template <typename R>
+  top_status finalize_t(double* coeffs, bool with_res, bool write_part, hipStream_t st) {
+    top::FinalArgs<R> a{};
+    a.c = (const R*)cbuf;
+    a.state = (const R*)state[cur];
+    a.zold = (const R*)zold;
+    a.bcL = (const R*)bcL;
+    a.T = Tdev;
+    a.rho = rho_seg;
+    a.flags = flags;
+    a.traj = traj;
+    a.S = S;
+    a.ld = ld;
+    a.part = write_part ? part : nullptr;
+    a.coeffs = coeffs;
+    a.nonfinite = flag_dev;
+    a.with_res = with_res ? 1 : 0;
+    hipError_t e = top::launch_finalize<R>(v, a, st);
+    if (e != hipSuccess) return fail(TOP_E_HIP, "finalize launch failed: %s", hipGetErrorString(e));
+    return TOP_OK;
+  }
+
+  top_status finalize(double* coeffs, bool with_res, bool write_part, hipStream_t st) {
+    return v.prec == 0 ? finalize_t<float>(coeffs, with_res, write_part, st)
+                       : finalize_t<double>(coeffs, with_res, write_part, st);
+  }
+
+  // Sweeps per launch for the remaining count.
+  int chunk(int remaining, int done) const {
+    int n = remaining;
+    if (plan.halo > 0) n = std::min(n, plan.halo);
+    if (tape != nullptr) n = std::min(n, opt.checkpoint_every - (done % opt.checkpoint_every));
+    return n;
+  }
+
+  // The launch sequence of k sweeps starting from buffer `c0` and sweep index `done0`.
+  top_status enqueue(int k, int c0, int done0, hipStream_t st) {
+    int remaining = k, c = c0, done = done0;
+    const size_t sbytes = (size_t)nf * ld * rsz;
+    while (remaining > 0) {
+      const int n = chunk(remaining, done);
+      const bool fin = (n == remaining);
+      top_status s = sweep_launch(plan, state[c], state[c ^ 1], n, fin, st);
+      if (s != TOP_OK) return s;
+      c ^= 1;
+      remaining -= n;
+      done += n;
+      if (tape != nullptr && done % opt.checkpoint_every == 0) {
+        const int slot = done / opt.checkpoint_every;
+        if (slot < tape_slots)
+          TOP_HIP(hipMemcpyAsync((char*)tape + (size_t)slot * sbytes, state[c], sbytes,
+                                 hipMemcpyDeviceToDevice, st));
+      }
+    }
+    // residual and cost partials of the last sweep, reduced per trajectory
+    const int save = cur;
+    cur = c;
+    top_status s = finalize(nullptr, true, true, st);
+    cur = save;
+    if (s != TOP_OK) return s;
+    hipError_t e = top::launch_reduce(part, S, off_dev, B, out, st);
+    if (e != hipSuccess) return fail(TOP_E_HIP, "reduce launch failed: %s", hipGetErrorString(e));
+    return TOP_OK;
+  }
+};
+
+extern "C" {
+
+void top_default_options(top_options* opt) {
+  if (opt == nullptr) return;
+  std::memset(opt, 0, sizeof *opt);
+  opt->order = 3;
+  opt->n_cont = 0;
+  opt->fix_interior = 1;
+  opt->n_samples = 8;
+  opt->precision = TOP_FP32;
+  opt->checkpoint_every = 0;
+  opt->max_taped_iters = 0;
+  opt->tile_lanes = 0;
+  opt->halo = 0;
+  opt->use_graph = 1;
+}
+
+const char* top_last_error(void) { return g_err.c_str(); }
+
+void top_destroy(top_problem* h) {
+  if (h == nullptr) return;
+  (void)hipStreamSynchronize(h->stream);
+  h->drop_graphs();
+  if (h->cap_stream != nullptr) (void)hipStreamDestroy(h->cap_stream);
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->lanes_dev != nullptr) (void)hipFree(h->lanes_dev);
+  delete h;
+}
+
+top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
+                      const double* durations, const double* bc, const double* box_lo,
+                      const double* box_hi, const double* vmax, const double* rho,
+                      const top_options* opt_in, hipStream_t stream, top_problem** out) {
+  if (out == nullptr) return fail(TOP_E_INVALID, "out is NULL");
+  *out = nullptr;
+  top_options opt;
+  if (opt_in != nullptr) opt = *opt_in; else top_default_options(&opt);
+  if (n_traj < 1) return fail(TOP_E_INVALID, "n_traj must be >= 1 (got %d)", n_traj);
+  if (seg_offsets == nullptr) return fail(TOP_E_INVALID, "seg_offsets is NULL");
+  if (waypoints == nullptr || durations == nullptr || rho == nullptr)
+    return fail(TOP_E_INVALID, "waypoints, durations and rho are required");
+  if ((box_lo == nullptr) != (box_hi == nullptr)) return fail(TOP_E_INVALID, "give both box_lo and box_hi, or neither");
+  if (seg_offsets[0] != 0) return fail(TOP_E_INVALID, "seg_offsets[0] must be 0");
+  for (int b = 0; b < n_traj; ++b)
+    if (seg_offsets[b + 1] <= seg_offsets[b])
+      return fail(TOP_E_INVALID, "trajectory %d has no segment (seg_offsets must increase strictly)", b);
+  const int64_t S = seg_offsets[n_traj];
+  if (S + n_traj >= (int64_t)top::kHaloBit) return fail(TOP_E_UNSUPPORTED, "too many segments (%lld)", (long long)S);
+  if (opt.order != 3 && opt.order != 4) return fail(TOP_E_UNSUPPORTED, "order must be 3 or 4 (got %d)", opt.order);
+  const int s = opt.n_cont == 0 ? opt.order : opt.n_cont;
+  if (s != opt.order && s != opt.order + 1)
+    return fail(TOP_E_UNSUPPORTED, "n_cont must be p or p+1 (got %d for p = %d)", s, opt.order);
+  if (opt.n_samples == 0) opt.n_samples = top::kSamples;
+  if (opt.n_samples != top::kSamples) return fail(TOP_E_UNSUPPORTED, "only n_samples = 8 is built (got %d)", opt.n_samples);
+  if (opt.precision != TOP_FP32 && opt.precision != TOP_FP64) return fail(TOP_E_INVALID, "precision must be TOP_FP32 or TOP_FP64");
+  if (opt.fix_interior != 0 && opt.fix_interior != 1) return fail(TOP_E_INVALID, "fix_interior must be 0 or 1");
+  if (opt.checkpoint_every < 0 || (opt.checkpoint_every > 0 && opt.max_taped_iters < 1))
+    return fail(TOP_E_INVALID, "checkpoint_every >= 0, and max_taped_iters >= 1 when it is > 0");
+  top::Variant v{opt.precision == TOP_FP64 ? 1 : 0, opt.order, s, box_lo != nullptr, vmax != nullptr};
+  if (opt.tile_lanes != 0 && (opt.tile_lanes < 64 || opt.tile_lanes > max_tile(v) || opt.tile_lanes % 64 != 0))
+    return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, %d] (got %d)", max_tile(v), opt.tile_lanes);
+  if (opt.halo < 0) return fail(TOP_E_INVALID, "halo must be >= 0");
+
+  top_problem* h = new (std::nothrow) top_problem();
+  if (h == nullptr) return fail(TOP_E_NOMEM, "host allocation failed");
+  h->opt = opt;
+  h->opt.n_cont = s;
+  h->v = v;
+  h->B = n_traj;
+  h->S = S;
+  h->ld = (S + 63) / 64 * 64;
+  h->rsz = v.prec == 0 ? sizeof(float) : sizeof(double);
+  h->off.assign(seg_offsets, seg_offsets + n_traj + 1);
+  h->stream = stream;
+  top::Layout L{v.p, v.s, v.box, v.vel};
+  h->nf = L.nf();
+
+  auto bail = [&](top_status st) { top_destroy(h); return st; };
+  const size_t R = h->rsz, ld = (size_t)h->ld;
+  top_status st;
+  if ((st = h->alloc(&h->Hr, L.nh() * ld * R)) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->iT, ld * R)) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->lo, 3 * ld * R)) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->hi, 3 * ld * R)) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->vmax, ld * R)) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->bcL, (size_t)n_traj * 3 * s * R)) != TOP_OK) return bail(st);
+  for (int q = 0; q < 2; ++q)
+    if ((st = h->alloc(&h->state[q], (size_t)h->nf * ld * R)) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->cbuf, 3 * (size_t)L.n() * ld * R)) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->zold, 3 * (size_t)s * ld * R)) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->flags, ld)) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->traj, ld * sizeof(int32_t))) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->Tdev, ld * sizeof(double))) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->rho_seg, ld * sizeof(double))) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->part, 3 * (size_t)S * sizeof(double))) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->out, 3 * (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->off_dev, (size_t)(n_traj + 1) * sizeof(int64_t))) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->flag_dev, 2 * sizeof(int))) != TOP_OK) return bail(st);
+  if (opt.checkpoint_every > 0) {
+    h->tape_slots = opt.max_taped_iters / opt.checkpoint_every + 1;
+    if ((st = h->alloc(&h->tape, (size_t)h->tape_slots * h->nf * ld * R)) != TOP_OK) return bail(st);
+  }
+  {
+    hipError_t e = hipMemcpyAsync(h->off_dev, seg_offsets, (n_traj + 1) * sizeof(int64_t),
+                                  hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "copy of seg_offsets failed: %s", hipGetErrorString(e)));
+    const int zero2[2] = {0, 0};
+    e = hipMemcpyAsync(h->flag_dev, zero2, sizeof zero2, hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "flag reset failed: %s", hipGetErrorString(e)));
+  }
+  top::SetupArgs sa{waypoints, durations, bc, box_lo, box_hi, vmax, rho, h->off_dev, n_traj, S, opt.fix_interior};
+  {
+    hipError_t e = top::launch_validate(sa, v.p, h->flag_dev, stream);
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "validation launch failed: %s", hipGetErrorString(e)));
+    int bad[2] = {0, 0};
+    e = hipMemcpyAsync(bad, h->flag_dev, sizeof bad, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "validation failed: %s", hipGetErrorString(e)));
+    if (bad[0] != 0) {
+      std::string what;
+      if (bad[0] & 1) what += " durations (need finite T > 0);";
+      if (bad[0] & 2) what += " box (need finite lo < hi);";
+      if (bad[0] & 4) what += " waypoints (need finite);";
+      if (bad[0] & 8) what += " rho (need finite > 0);";
+      if (bad[0] & 16) what += " vmax (need finite > 0);";
+      if (bad[0] & 32) what += " bc (need finite);";
+      return bail(fail(TOP_E_INVALID, "invalid input:%s", what.c_str()));
+    }
+  }
+  {
+    hipError_t e;
+    if (v.prec == 0) {
+      top::SetupOut<float> o{(float*)h->Hr, (float*)h->iT, (float*)h->lo, (float*)h->hi, (float*)h->vmax,
+                             h->flags, h->traj, (float*)h->bcL, (float*)h->state[0], (float*)h->cbuf,
+                             h->ld, h->Tdev, h->rho_seg};
+      e = top::launch_setup<float>(v, sa, o, stream);
+    } else {
+      top::SetupOut<double> o{(double*)h->Hr, (double*)h->iT, (double*)h->lo, (double*)h->hi, (double*)h->vmax,
+                              h->flags, h->traj, (double*)h->bcL, (double*)h->state[0], (double*)h->cbuf,
+                              h->ld, h->Tdev, h->rho_seg};
+      e = top::launch_setup<double>(v, sa, o, stream);
+    }
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "setup launch failed: %s", hipGetErrorString(e)));
+  }
+  if (h->tape != nullptr) {
+    hipError_t e = hipMemcpyAsync(h->tape, h->state[0], (size_t)h->nf * ld * R, hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "tape copy failed: %s", hipGetErrorString(e)));
+  }
+  // cost of the Init guess (residuals stay undefined until the first sweep)
+  if ((st = h->finalize(nullptr, false, true, stream)) != TOP_OK) return bail(st);
+  {
+    hipError_t e = top::launch_reduce(h->part, S, h->off_dev, n_traj, h->out, stream);
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "reduce launch failed: %s", hipGetErrorString(e)));
+  }
+  // execution plan: explicit, tuned for this shape class, or the default
+  int W = opt.tile_lanes, halo = opt.halo;
+  h->explicit_tile = W != 0;
+  if (W == 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load();
+    auto it = g_tune.find(shape_key(v, h->off));
+    if (it != g_tune.end() && it->second.first <= max_tile(v)) {
+      W = it->second.first;
+      if (halo == 0) halo = it->second.second;
+    }
+  }
+  if (W == 0) W = max_tile(v);
+  if (halo == 0) halo = std::max(1, std::min(32, W / 8));
+  if (2 * halo >= W) return bail(fail(TOP_E_INVALID, "halo %d too large for %d-lane tiles", halo, W));
+  h->plan = make_plan(h->off, W, halo);
+  if ((st = h->upload_plan(h->plan)) != TOP_OK) return bail(st);
+  *out = h;
+  return TOP_OK;
+}
+
+top_status top_iterate(top_problem* h, int32_t k) {
+  if (h == nullptr) return fail(TOP_E_INVALID, "handle is NULL");
+  if (k < 0) return fail(TOP_E_INVALID, "k must be >= 0 (got %d)", k);
+  if (k == 0) return TOP_OK;
+  if (h->tape != nullptr && h->iters_done + k > h->opt.max_taped_iters)
+    return fail(TOP_E_STATE, "the tape holds %d sweeps; %d done, %d more asked", h->opt.max_taped_iters,
+                h->iters_done, k);
+  // The sequence only depends on (k, start buffer) unless a tape is written.
+  const bool graph = h->opt.use_graph != 0 && h->tape == nullptr;
+  if (!graph) {
+    top_status s = h->enqueue(k, h->cur, h->iters_done, h->stream);
+    if (s != TOP_OK) return s;
+  } else {
+    auto key = std::make_tuple(k, h->cur);
+    auto it = h->graphs.find(key);
+    if (it == h->graphs.end()) {
+      if (h->cap_stream == nullptr) TOP_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+      TOP_HIP(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+      top_status s = h->enqueue(k, h->cur, h->iters_done, h->cap_stream);
+      hipGraph_t g = nullptr;
+      hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+      if (s != TOP_OK) { if (g) (void)hipGraphDestroy(g); return s; }
+      if (e != hipSuccess) return fail(TOP_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+      hipGraphExec_t ex = nullptr;
+      e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+      if (e != hipSuccess) { (void)hipGraphDestroy(g); return fail(TOP_E_HIP, "graph instantiate failed: %s", hipGetErrorString(e)); }
+      h->graph_defs.push_back(g);
+      it = h->graphs.emplace(key, ex).first;
+    }
+    TOP_HIP(hipGraphLaunch(it->second, h->stream));
+  }
+  // advance the host-side bookkeeping exactly as enqueue did
+  int remaining = k, done = h->iters_done;
+  while (remaining > 0) {
+    const int n = h->chunk(remaining, done);
+    h->cur ^= 1;
+    remaining -= n;
+    done += n;
+  }
+  h->iters_done = done;
+  h->have_sweep = true;
+  return TOP_OK;
+}
+
+top_status top_residuals(const top_problem* h, double* r_primal, double* r_dual) {
+  if (h == nullptr) return fail(TOP_E_INVALID, "handle is NULL");
+  if (!h->have_sweep) return fail(TOP_E_STATE, "no sweep has run yet");
+  if (r_primal != nullptr)
+    TOP_HIP(hipMemcpyAsync(r_primal, h->out + h->B, h->B * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  if (r_dual != nullptr)
+    TOP_HIP(hipMemcpyAsync(r_dual, h->out + 2 * h->B, h->B * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  return TOP_OK;
+}
+
+top_status top_cost(const top_problem* h, double* cost) {
+  if (h == nullptr || cost == nullptr) return fail(TOP_E_INVALID, "handle and cost must be non-NULL");
+  TOP_HIP(hipMemcpyAsync(cost, h->out, h->B * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
+  return TOP_OK;
+}
+
+top_status top_coeffs(const top_problem* h, double* coeffs) {
+  if (h == nullptr || coeffs == nullptr) return fail(TOP_E_INVALID, "handle and coeffs must be non-NULL");
+  return const_cast<top_problem*>(h)->finalize(coeffs, false, false, h->stream);
+}
+
+top_status top_backward(top_problem* h, const double* dcost, double* dwaypoints, double* ddurations) {
+  if (h == nullptr || dcost == nullptr) return fail(TOP_E_INVALID, "handle and dcost must be non-NULL");
+  if (h->tape == nullptr) return fail(TOP_E_STATE, "no tape: create with checkpoint_every > 0");
+  (void)dwaypoints;
+  (void)ddurations;
+  return fail(TOP_E_UNSUPPORTED, "top_backward is not built in this library version");
+}
+
+top_status top_sync_status(top_problem* h) {
+  if (h == nullptr) return fail(TOP_E_INVALID, "handle is NULL");
+  int flag[2] = {0, 0};
+  TOP_HIP(hipMemcpyAsync(flag, h->flag_dev, sizeof flag, hipMemcpyDeviceToHost, h->stream));
+  TOP_HIP(hipStreamSynchronize(h->stream));
+  if (flag[0] != 0) return fail(TOP_E_NONFINITE, "a sweep produced a non-finite value");
+  return TOP_OK;
+}
+
+top_status top_get_plan(const top_problem* h, top_plan_info* info) {
+  if (h == nullptr || info == nullptr) return fail(TOP_E_INVALID, "handle and info must be non-NULL");
+  info->tile_lanes = h->plan.W;
+  info->n_tiles = h->plan.n_tiles;
+  info->halo = h->plan.halo;
+  info->n_traj = h->B;
+  info->n_seg = h->S;
+  info->used_lanes = h->plan.used;
+  info->precision = h->opt.precision;
+  info->order = h->opt.order;
+  info->n_cont = h->opt.n_cont;
+  info->iters_done = h->iters_done;
+  return TOP_OK;
+}
+
+top_status top_tune(top_problem* h, int32_t k_probe) {
+  if (h == nullptr) return fail(TOP_E_INVALID, "handle is NULL");
+  if (k_probe < 1) return fail(TOP_E_INVALID, "k_probe must be >= 1");
+  if (h->explicit_tile) return TOP_OK;
+  if (h->scratch == nullptr) {
+    top_status s = h->alloc(&h->scratch, (size_t)h->nf * h->ld * h->rsz);
+    if (s != TOP_OK) return s;
+  }
+  int64_t mx = 0;
+  for (int b = 0; b < h->B; ++b) mx = std::max(mx, h->off[b + 1] - h->off[b]);
+  std::vector<std::pair<int, int>> cands;
+  for (int W = 64; W <= max_tile(h->v); W *= 2) {
+    if (mx <= W) cands.push_back({W, 0});
+    else
+      for (int halo : {8, 16, 32})
+        if (4 * halo <= W) cands.push_back({W, halo});
+  }
+  hipEvent_t e0, e1;
+  TOP_HIP(hipEventCreate(&e0));
+  TOP_HIP(hipEventCreate(&e1));
+  float best = 1e30f;
+  std::pair<int, int> bestc = {h->plan.W, h->plan.halo};
+  for (auto c : cands) {
+    Plan pl = make_plan(h->off, c.first, c.second > 0 ? c.second : 1);
+    top_status s = h->upload_plan(pl);
+    if (s != TOP_OK) return s;
+    float tbest = 1e30f;
+    for (int rep = 0; rep < 3; ++rep) {
+      TOP_HIP(hipEventRecord(e0, h->stream));
+      int remaining = k_probe;
+      while (remaining > 0) {
+        const int n = pl.halo > 0 ? std::min(remaining, pl.halo) : remaining;
+        // probe sweeps read the live state and write scratch; the iterate is not advanced
+        s = h->sweep_launch(pl, h->state[h->cur], h->scratch, n, false, h->stream);
+        if (s != TOP_OK) return s;
+        remaining -= n;
+      }
+      TOP_HIP(hipEventRecord(e1, h->stream));
+      TOP_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      TOP_HIP(hipEventElapsedTime(&ms, e0, e1));
+      tbest = std::min(tbest, ms);
+    }
+    if (tbest < best) {
+      best = tbest;
+      bestc = {c.first, pl.halo};
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->plan = make_plan(h->off, bestc.first, bestc.second > 0 ? bestc.second : std::max(1, std::min(32, bestc.first / 8)));
+  top_status s = h->upload_plan(h->plan);
+  if (s != TOP_OK) return s;
+  h->drop_graphs();
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[shape_key(h->v, h->off)] = {h->plan.W, h->plan.halo};
+    tune_cache_store();
+  }
+  return TOP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,170 @@
+// Shared definitions of the CADMM sweep library: constants of the
+// normalised-time basis, the state layout, and launcher declarations.
+//
+// Basis.  A segment of duration T is stored as c~_j = c_j T^j, so that
+// sigma(tau T) = sum_j c~_j tau^j for tau in [0, 1].  In this basis the
+// constraint sample rows of Sec. III-D.1 (positions beta(t_s) and velocities
+// beta'(t_s) at t_s = tau_s T, tau_s = s/(M+1)) become the T-independent
+// vectors tau_s^j and (1/T) j tau_s^(j-1), the boundary rows of M(T) become
+// T^-o times fixed integer vectors, and the cost Gram matrix becomes
+// T^(1-2p) Q(1).  All fixed vectors are compile-time constants below.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+
+namespace top {
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i = Begin..End-1, so that every index
+// (and every table value derived from it) is a constant expression.
+template <int Begin, int End, typename F>
+__host__ __device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (Begin < End) {
+    f(std::integral_constant<int, Begin>{});
+    static_for<Begin + 1, End>(f);
+  }
+}
+
+constexpr int kSamples = 8;      // M, constraint samples per segment
+constexpr int kMaxWaves = 16;    // 1024-lane workgroups at most
+constexpr int32_t kHaloBit = 1 << 30;
+constexpr int32_t kSegMask = kHaloBit - 1;
+
+enum : uint8_t { kFirst = 1, kLast = 2 };
+
+__host__ __device__ constexpr double cfact(int o) { return o <= 1 ? 1.0 : o * cfact(o - 1); }
+// j! / (j - o)!: factor of the o-th derivative on t^j
+__host__ __device__ constexpr double cfall(int o, int j) { return j < o ? 0.0 : cfact(j) / cfact(j - o); }
+__host__ __device__ constexpr double cpow(double x, int e) { return e <= 0 ? 1.0 : x * cpow(x, e - 1); }
+// sample instant tau_s = (s+1)/(M+1), s = 0..M-1
+__host__ __device__ constexpr double ctau(int s) { return double(s + 1) / double(kSamples + 1); }
+// position row of sample s, coefficient j: tau_s^j
+__host__ __device__ constexpr double cpos(int s, int j) { return cpow(ctau(s), j); }
+// velocity row of sample s (before the 1/T factor): j tau_s^(j-1)
+__host__ __device__ constexpr double cvel(int s, int j) { return j == 0 ? 0.0 : j * cpow(ctau(s), j - 1); }
+// Q(1) entry for cost order p: [j!/(j-p)!][k!/(k-p)!] / (j+k-2p+1), zero below order p
+__host__ __device__ constexpr double cgram(int p, int j, int k) {
+  return (j < p || k < p) ? 0.0 : cfall(p, j) * cfall(p, k) / double(j + k - 2 * p + 1);
+}
+// Coefficients of the rest-to-rest unit step of degree 2p-1 in tau (derivatives 1..p-1 vanish at
+// both ends): 10 t^3 - 15 t^4 + 6 t^5 for p = 3 and 35 t^4 - 84 t^5 + 70 t^6 - 20 t^7 for p = 4.
+__host__ __device__ constexpr double cstep(int p, int j) {
+  return p == 3 ? (j == 3 ? 10.0 : j == 4 ? -15.0 : j == 5 ? 6.0 : 0.0)
+                : (j == 4 ? 35.0 : j == 5 ? -84.0 : j == 6 ? 70.0 : j == 7 ? -20.0 : 0.0);
+}
+// packed upper-triangle index of a symmetric n x n matrix
+__host__ __device__ constexpr int tri(int n, int i, int j) {
+  return i <= j ? i * n - i * (i - 1) / 2 + (j - i) : j * n - j * (j - 1) / 2 + (i - j);
+}
+
+// Field offsets of the per-segment iterate state (structure of arrays, one row of ld values per
+// field).  z holds the segment's end knot; its start knot is the previous segment's end knot, or
+// the trajectory's start state.  y packs each box slack/dual pair, g each velocity split/dual pair.
+struct Layout {
+  int p, s, box, vel;
+  __host__ __device__ int n() const { return 2 * p; }
+  __host__ __device__ int nh() const { return n() * (n() + 1) / 2; }
+  __host__ __device__ int zR() const { return 0; }
+  __host__ __device__ int uL() const { return 3 * s; }
+  __host__ __device__ int uR() const { return 6 * s; }
+  __host__ __device__ int yh() const { return 9 * s; }
+  __host__ __device__ int yl() const { return 9 * s + (box ? 3 * kSamples : 0); }
+  __host__ __device__ int g() const { return 9 * s + (box ? 6 * kSamples : 0); }
+  __host__ __device__ int nf() const { return g() + (vel ? 3 * kSamples : 0); }
+};
+
+// Read-only per-segment constants, all [.][ld] structure of arrays in the iterate precision.
+template <typename R>
+struct SegConsts {
+  const R* Hr;          // [nh] packed rho * Htilde^-1 (symmetric)
+  const R* iT;          // 1/T
+  const R* lo;          // [3] corridor
+  const R* hi;          // [3]
+  const R* vmax;        // velocity bound of the segment's trajectory
+  const uint8_t* flags; // kFirst | kLast
+  const int32_t* traj;  // trajectory of the segment
+  const R* bcL;         // [B][3][s] start-knot state of each trajectory
+  int64_t ld;
+};
+
+template <typename R>
+struct SweepArgs {
+  SegConsts<R> k;
+  const int32_t* lane_seg;  // [n_tiles * W] segment of each lane, | kHaloBit for halo copies, -1 idle
+  int W;
+  const R* st_in;
+  R* st_out;
+  int iters;                // sweeps in this launch
+  int fixpos;
+  int final_out;            // write c~ and the end knot before its last update, at the last sweep
+  R* c_out;                 // [3n][ld]
+  R* zold_out;              // [3s][ld]
+};
+
+struct Variant {
+  int prec;  // 0 fp32, 1 fp64
+  int p, s, box, vel;
+};
+
+template <typename R>
+hipError_t launch_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
+
+// One-time setup (precompute + Init), float64 arithmetic, output in R.
+struct SetupArgs {
+  const double* waypoints;   // [S+B][3]
+  const double* durations;   // [S]
+  const double* bc;          // [B][2][p][3] or null
+  const double* box_lo;      // [S][3] or null
+  const double* box_hi;
+  const double* vmax;        // [B] or null
+  const double* rho;         // [B]
+  const int64_t* seg_off;    // [B+1] device copy
+  int B;
+  int64_t S;
+  int fixpos;
+};
+
+template <typename R>
+struct SetupOut {
+  R* Hr; R* iT; R* lo; R* hi; R* vmax; uint8_t* flags; int32_t* traj; R* bcL;
+  R* state; R* c; int64_t ld;
+  double* Tdev;              // [S] float64 copy of T (finalize)
+  double* rho_seg;           // [S] float64 rho of the segment's trajectory (finalize)
+};
+
+template <typename R>
+hipError_t launch_setup(const Variant& v, const SetupArgs& a, const SetupOut<R>& o, hipStream_t st);
+
+hipError_t launch_validate(const SetupArgs& a, int p, int* bad, hipStream_t st);
+
+// Finalize: per-segment float64 partials (cost, primal gap^2, dual^2) and monomial coefficients.
+template <typename R>
+struct FinalArgs {
+  const R* c;           // [3n][ld]
+  const R* state;       // current state [nf][ld]
+  const R* zold;        // [3s][ld]
+  const R* bcL;
+  const double* T;      // [S]
+  const double* rho;    // [S]
+  const uint8_t* flags;
+  const int32_t* traj;
+  int64_t S, ld;
+  double* part;         // [3][S] cost, rp^2, rd^2
+  double* coeffs;       // [S][3][n] or null
+  int* nonfinite;
+  int with_res;
+};
+
+template <typename R>
+hipError_t launch_finalize(const Variant& v, const FinalArgs<R>& a, hipStream_t st);
+
+// Per-trajectory sums of the partials in a fixed order: out[0][b] = cost, out[1][b] = ||r_p||,
+// out[2][b] = ||r_d|| (square roots taken).
+hipError_t launch_reduce(const double* part, int64_t S, const int64_t* seg_off, int B, double* out,
+                         hipStream_t st);
+
+hipError_t launch_copy_rows(const double* src, double* dst, int B, hipStream_t st);
+
+}  // namespace top

@@ -1,0 +1,133 @@
+// Outputs of a run, in float64: monomial coefficients, and per-segment
+// partial sums of the objective and of the squared stopping residuals
+// (Sec. III-D.3), reduced per trajectory in a fixed order.
+#include "common.h"
+
+namespace top {
+
+template <typename R, int P, int S>
+__global__ void finalize_kernel(FinalArgs<R> a) {
+  constexpr int N = 2 * P;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.S) return;
+  const int64_t ld = a.ld;
+  const double T = a.T[i];
+  const double iT = 1.0 / T;
+  const uint8_t fl = a.flags[i];
+  const bool first = fl & kFirst, last = fl & kLast;
+  double iTp[N], Tp[N];
+  iTp[0] = 1.0;
+  Tp[0] = 1.0;
+  for (int o = 1; o < N; ++o) { iTp[o] = iTp[o - 1] * iT; Tp[o] = Tp[o - 1] * T; }
+  double c[3][N];
+  for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+    for (int j = 0; j < N; ++j) c[ax][j] = (double)a.c[(int64_t)(ax * N + j) * ld + i];
+
+  // objective: sum_a c^T Q(T) c = T^(1-2p) sum_a c~^T Q(1) c~
+  double J = 0.0;
+  for (int ax = 0; ax < 3; ++ax) {
+    double q = 0.0;
+#pragma unroll
+    for (int j = P; j < N; ++j)
+#pragma unroll
+      for (int k = P; k < N; ++k) q += cgram(P, j, k) * c[ax][j] * c[ax][k];
+    J += q;
+  }
+  J *= iTp[2 * P - 1];
+  if (a.coeffs != nullptr) {
+    for (int ax = 0; ax < 3; ++ax)
+#pragma unroll
+      for (int j = 0; j < N; ++j) a.coeffs[(i * 3 + ax) * N + j] = c[ax][j] * iTp[j];
+  }
+  double rp2 = 0.0, rd2 = 0.0;
+  if (a.with_res) {
+    // primal: gaps of orders 0..s-1 between this segment's end and the next one's start
+    if (!last) {
+      const double iTn = 1.0 / a.T[i + 1];
+      double iTnp = 1.0;
+      for (int o = 0; o < S; ++o) {
+        for (int ax = 0; ax < 3; ++ax) {
+          double xr = 0.0;
+#pragma unroll
+          for (int j = 0; j < N; ++j) xr += cfall(o, j) * c[ax][j];
+          xr *= iTp[o];
+          const double xl = cfact(o) * (double)a.c[(int64_t)(ax * N + o) * ld + i + 1] * iTnp;
+          rp2 += (xr - xl) * (xr - xl);
+        }
+        iTnp *= iTn;
+      }
+    }
+    // dual: rho M(T)^T (z~^{k+1} - z~^k), per axis, monomial basis
+    const double rho = a.rho[i];
+    for (int ax = 0; ax < 3; ++ax) {
+      double dL[S], dR[S];
+      for (int o = 0; o < S; ++o) {
+        const int64_t f = (int64_t)(ax * S + o) * ld;
+        dL[o] = first ? 0.0 : (double)a.state[f + i - 1] - (double)a.zold[f + i - 1];
+        dR[o] = last ? 0.0 : (double)a.state[f + i] - (double)a.zold[f + i];
+      }
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        double v = (j < S) ? cfact(j) * dL[j] : 0.0;
+        for (int o = 0; o < S && o <= j; ++o) v += cfall(o, j) * Tp[j - o] * dR[o];
+        v *= rho;
+        rd2 += v * v;
+      }
+    }
+  }
+  if (a.part != nullptr) {
+    a.part[i] = J;
+    a.part[a.S + i] = rp2;
+    a.part[2 * a.S + i] = rd2;
+    if (!isfinite(J) || !isfinite(rp2) || !isfinite(rd2)) atomicOr(a.nonfinite, 1);
+  }
+}
+
+template <typename R>
+hipError_t launch_finalize(const Variant& v, const FinalArgs<R>& a, hipStream_t st) {
+  const int bs = 256;
+  const dim3 grid((unsigned)((a.S + bs - 1) / bs)), block(bs);
+  if (v.p == 3 && v.s == 3) hipLaunchKernelGGL((finalize_kernel<R, 3, 3>), grid, block, 0, st, a);
+  else if (v.p == 3 && v.s == 4) hipLaunchKernelGGL((finalize_kernel<R, 3, 4>), grid, block, 0, st, a);
+  else if (v.p == 4 && v.s == 4) hipLaunchKernelGGL((finalize_kernel<R, 4, 4>), grid, block, 0, st, a);
+  else if (v.p == 4 && v.s == 5) hipLaunchKernelGGL((finalize_kernel<R, 4, 5>), grid, block, 0, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template hipError_t launch_finalize<float>(const Variant&, const FinalArgs<float>&, hipStream_t);
+template hipError_t launch_finalize<double>(const Variant&, const FinalArgs<double>&, hipStream_t);
+
+// One 64-lane wave per trajectory; lane l sums segments l, l+64, ... in order, then a fixed
+// shuffle tree: the result does not depend on how the sweep was tiled.
+__global__ void reduce_kernel(const double* part, int64_t S, const int64_t* off, int B, double* out) {
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  if (b >= B) return;
+  const int64_t s0 = off[b], s1 = off[b + 1];
+  for (int q = 0; q < 3; ++q) {
+    double acc = 0.0;
+    for (int64_t i = s0 + lane; i < s1; i += 64) acc += part[q * S + i];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
+    if (lane == 0) out[(int64_t)q * B + b] = (q == 0) ? acc : sqrt(acc);
+  }
+}
+
+hipError_t launch_reduce(const double* part, int64_t S, const int64_t* off, int B, double* out,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(B), dim3(64), 0, st, part, S, off, B, out);
+  return hipGetLastError();
+}
+
+__global__ void copy_kernel(const double* src, double* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+hipError_t launch_copy_rows(const double* src, double* dst, int n, hipStream_t st) {
+  hipLaunchKernelGGL(copy_kernel, dim3((n + 255) / 256), dim3(256), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace top

@@ -1,0 +1,247 @@
+// One-time per-segment work: input validation, the float64 precompute of
+// rho * Htilde^-1 (the inverse in eq. QpSubProblem, in the normalised-time
+// basis), and Init of Algorithm 1.
+//
+// Init (the paper only says that Init sets up every variable): each segment
+// starts on its chord as the rest-to-rest step polynomial of degree 2p-1;
+// interior knots hold the waypoint position with zero higher derivatives; the
+// end knots hold the trajectory's end states; all scaled duals are zero; the
+// box slack starts at max(0, b - A^o c^0) with a zero dual, stored as
+// y = min(0, A^o c^0 - b); the velocity split starts at Proj(A^v c^0) with a
+// zero dual, stored as g = Proj(A^v c^0).
+#include "common.h"
+
+namespace top {
+
+__global__ void validate_kernel(SetupArgs a, int p, int* bad) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int flag = 0;
+  if (i < a.S) {
+    const double T = a.durations[i];
+    if (!(T > 0.0) || !isfinite(T)) flag |= 1;
+    if (a.box_lo != nullptr) {
+      for (int c = 0; c < 3; ++c) {
+        const double lo = a.box_lo[i * 3 + c], hi = a.box_hi[i * 3 + c];
+        if (!isfinite(lo) || !isfinite(hi) || !(lo < hi)) flag |= 2;
+      }
+    }
+  }
+  if (i < a.S + a.B) {
+    for (int c = 0; c < 3; ++c)
+      if (!isfinite(a.waypoints[i * 3 + c])) flag |= 4;
+  }
+  if (i < a.B) {
+    const double r = a.rho[i];
+    if (!(r > 0.0) || !isfinite(r)) flag |= 8;
+    if (a.vmax != nullptr) {
+      const double v = a.vmax[i];
+      if (!(v > 0.0) || !isfinite(v)) flag |= 16;
+    }
+    if (a.bc != nullptr) {
+      for (int q = 0; q < 2 * p * 3; ++q)
+        if (!isfinite(a.bc[i * 2 * p * 3 + q])) flag |= 32;
+    }
+  }
+  if (flag) atomicOr(bad, flag);
+}
+
+hipError_t launch_validate(const SetupArgs& a, int p, int* bad, hipStream_t st) {
+  const int64_t n = a.S + a.B;
+  const int bs = 256;
+  const int64_t nb = (n + bs - 1) / bs;
+  hipLaunchKernelGGL(validate_kernel, dim3((unsigned)nb), dim3(bs), 0, st, a, p, bad);
+  return hipGetLastError();
+}
+
+// End state (order o, axis c) of trajectory b at its start (side 0) or end (side 1).
+__device__ inline double end_state(const SetupArgs& a, int P, int b, int side, int o, int c, int64_t wp_row) {
+  if (a.bc != nullptr) return a.bc[(((int64_t)b * 2 + side) * P + o) * 3 + c];
+  return o == 0 ? a.waypoints[wp_row * 3 + c] : 0.0;
+}
+
+template <typename R, int P, int S, bool BOX, bool VEL>
+__global__ void setup_kernel(SetupArgs a, SetupOut<R> out) {
+  constexpr int N = 2 * P;
+  constexpr int M = kSamples;
+  constexpr int F_ZR = 0, F_UL = 3 * S, F_UR = 6 * S, F_YH = 9 * S;
+  constexpr int F_YL = F_YH + (BOX ? 3 * M : 0);
+  constexpr int F_G = 9 * S + (BOX ? 6 * M : 0);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.S) return;
+  const int64_t ld = out.ld;
+
+  // trajectory of segment i: last b with seg_off[b] <= i
+  int lo_b = 0, hi_b = a.B;  // invariant seg_off[lo_b] <= i < seg_off[hi_b]
+  while (hi_b - lo_b > 1) {
+    const int mid = (lo_b + hi_b) / 2;
+    if (a.seg_off[mid] <= i) lo_b = mid; else hi_b = mid;
+  }
+  const int b = lo_b;
+  const bool first = i == a.seg_off[b];
+  const bool last = i == a.seg_off[b + 1] - 1;
+  const double T = a.durations[i];
+  const double iT = 1.0 / T;
+  const double rho = a.rho[b];
+  double iTp[N];
+  iTp[0] = 1.0;
+  for (int o = 1; o < N; ++o) iTp[o] = iTp[o - 1] * iT;
+
+  // ---- Htilde = 2 T^(1-2p) Q(1) + rho [boundary rows + box rows + velocity rows]
+  double H[N][N];
+  const double sq = 2.0 * iTp[2 * P - 1];
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int k = 0; k < N; ++k) H[j][k] = sq * cgram(P, j, k);
+  const int nL = first ? P : S;
+  const int nR = last ? P : S;
+  for (int o = 0; o < nL; ++o) {
+    const double v = cfact(o) * iTp[o];
+    H[o][o] += rho * v * v;
+  }
+  for (int o = 0; o < nR; ++o) {
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int k = 0; k < N; ++k) H[j][k] += rho * (cfall(o, j) * iTp[o]) * (cfall(o, k) * iTp[o]);
+  }
+  if (BOX) {
+#pragma unroll
+    for (int s = 0; s < M; ++s)
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int k = 0; k < N; ++k) H[j][k] += rho * 2.0 * cpos(s, j) * cpos(s, k);
+  }
+  if (VEL) {
+#pragma unroll
+    for (int s = 0; s < M; ++s)
+#pragma unroll
+      for (int j = 0; j < N; ++j)
+#pragma unroll
+        for (int k = 0; k < N; ++k) H[j][k] += rho * iT * iT * cvel(s, j) * cvel(s, k);
+  }
+  // Cholesky H = L L^T (lower triangle of H overwritten by L)
+  for (int j = 0; j < N; ++j) {
+    double d = H[j][j];
+    for (int k = 0; k < j; ++k) d -= H[j][k] * H[j][k];
+    d = sqrt(d);
+    H[j][j] = d;
+    for (int r = j + 1; r < N; ++r) {
+      double v = H[r][j];
+      for (int k = 0; k < j; ++k) v -= H[r][k] * H[j][k];
+      H[r][j] = v / d;
+    }
+  }
+  // Linv = L^-1 (lower), then Hinv = Linv^T Linv
+  double Li[N][N];
+  for (int c = 0; c < N; ++c) {
+    for (int r = 0; r < N; ++r) {
+      if (r < c) { Li[r][c] = 0.0; continue; }
+      double v = (r == c) ? 1.0 : 0.0;
+      for (int k = c; k < r; ++k) v -= H[r][k] * Li[k][c];
+      Li[r][c] = v / H[r][r];
+    }
+  }
+  for (int r = 0; r < N; ++r) {
+    for (int c = r; c < N; ++c) {
+      double v = 0.0;
+      for (int k = c; k < N; ++k) v += Li[k][r] * Li[k][c];
+      out.Hr[(int64_t)tri(N, r, c) * ld + i] = (R)(rho * v);
+    }
+  }
+
+  // ---- per-segment constants
+  out.iT[i] = (R)iT;
+  out.flags[i] = (uint8_t)((first ? kFirst : 0) | (last ? kLast : 0));
+  out.traj[i] = b;
+  out.Tdev[i] = T;
+  out.rho_seg[i] = rho;
+  const double vmax = (a.vmax != nullptr) ? a.vmax[b] : 1.0;
+  out.vmax[i] = (R)vmax;
+  const int64_t w0 = i + b, w1 = i + b + 1;  // waypoint rows of the segment's two ends
+  double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int c = 0; c < 3; ++c) {
+    if (BOX) { lo[c] = a.box_lo[i * 3 + c]; hi[c] = a.box_hi[i * 3 + c]; }
+    out.lo[c * ld + i] = (R)lo[c];
+    out.hi[c * ld + i] = (R)hi[c];
+  }
+
+  // ---- Init: chord step polynomial in the normalised basis
+  double ct[3][N];
+  for (int c = 0; c < 3; ++c) {
+    const double p0 = a.waypoints[w0 * 3 + c], p1 = a.waypoints[w1 * 3 + c];
+#pragma unroll
+    for (int j = 0; j < N; ++j) ct[c][j] = (p1 - p0) * cstep(P, j);
+    ct[c][0] += p0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) out.c[(int64_t)(c * N + j) * ld + i] = (R)ct[c][j];
+  }
+  R* st = out.state;
+  for (int c = 0; c < 3; ++c) {
+    for (int o = 0; o < S; ++o) {
+      double z;
+      if (last) z = (o < P) ? end_state(a, P, b, 1, o, c, w1) : 0.0;
+      else z = (o == 0) ? a.waypoints[w1 * 3 + c] : 0.0;
+      st[(int64_t)(F_ZR + c * S + o) * ld + i] = (R)z;
+      st[(int64_t)(F_UL + c * S + o) * ld + i] = (R)0;
+      st[(int64_t)(F_UR + c * S + o) * ld + i] = (R)0;
+      if (first) out.bcL[((int64_t)b * 3 + c) * S + o] = (R)((o < P) ? end_state(a, P, b, 0, o, c, w0) : 0.0);
+    }
+  }
+  if (BOX) {
+    for (int c = 0; c < 3; ++c) {
+#pragma unroll
+      for (int s = 0; s < M; ++s) {
+        double pv = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) pv += cpos(s, j) * ct[c][j];
+        st[(int64_t)(F_YH + c * M + s) * ld + i] = (R)fmin(0.0, pv - hi[c]);
+        st[(int64_t)(F_YL + c * M + s) * ld + i] = (R)fmin(0.0, lo[c] - pv);
+      }
+    }
+  }
+  if (VEL) {
+#pragma unroll
+    for (int s = 0; s < M; ++s) {
+      double v[3];
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 1; j < N; ++j) acc += cvel(s, j) * ct[c][j];
+        v[c] = acc * iT;
+      }
+      const double n2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+      const double f = fmin(1.0, vmax / sqrt(n2));
+      for (int c = 0; c < 3; ++c) st[(int64_t)(F_G + c * M + s) * ld + i] = (R)(f * v[c]);
+    }
+  }
+}
+
+template <typename R>
+hipError_t launch_setup(const Variant& v, const SetupArgs& a, const SetupOut<R>& o, hipStream_t st) {
+  const int bs = 128;
+  const dim3 grid((unsigned)((a.S + bs - 1) / bs)), block(bs);
+#define TOP_SETUP_CASE(P_, S_, B_, V_)                                                   \
+  if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_) {            \
+    hipLaunchKernelGGL((setup_kernel<R, P_, S_, B_, V_>), grid, block, 0, st, a, o);    \
+    return hipGetLastError();                                                          \
+  }
+#define TOP_SETUP_PS(P_, S_)                                                             \
+  TOP_SETUP_CASE(P_, S_, true, true)                                                     \
+  TOP_SETUP_CASE(P_, S_, true, false)                                                    \
+  TOP_SETUP_CASE(P_, S_, false, true)                                                    \
+  TOP_SETUP_CASE(P_, S_, false, false)
+  TOP_SETUP_PS(3, 3)
+  TOP_SETUP_PS(3, 4)
+  TOP_SETUP_PS(4, 4)
+  TOP_SETUP_PS(4, 5)
+#undef TOP_SETUP_PS
+#undef TOP_SETUP_CASE
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_setup<float>(const Variant&, const SetupArgs&, const SetupOut<float>&, hipStream_t);
+template hipError_t launch_setup<double>(const Variant&, const SetupArgs&, const SetupOut<double>&, hipStream_t);
+
+}  // namespace top

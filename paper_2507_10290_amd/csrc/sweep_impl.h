@@ -1,0 +1,345 @@
+// The fused CADMM sweep kernel (Sec. III-D.1 update rules, one pass of
+// Algorithm 1's loop body per sweep), resident form.
+//
+// Mapping: one segment per lane; a workgroup tile holds up to W consecutive
+// segments of one or more trajectories (whole trajectories packed, or a core
+// range of one long trajectory plus `halo` copied neighbours on each side).
+// The tile loads its segments' state once, runs `iters` sweeps with the state
+// in registers, and stores the core segments' state once.  A sweep of a
+// segment needs only its own state and, for the knot average, the end states
+// of its two neighbours, so the halo copies absorb the one-segment-per-sweep
+// spread of information from outside the tile.
+//
+// Per sweep and segment (normalised-time basis, see common.h), per axis a:
+//   r~  = sum_o o! T^-o (zL_o - uL_o) e_o + sum_o T^-o (zR_o - uR_o) f_o
+//       + sum_s tau_s (hi + lo - |y^hi_s| + |y^lo_s|)          [box rows, folded slack/dual]
+//       + T^-1 sum_s tau'_s (2 Proj(g_s) - g_s)_a              [velocity rows, folded split/dual]
+//   c~  = (rho Htilde^-1) r~                                   [eq. QpSubProblem]
+//   y^hi_s <- tau_s.c~ - hi + max(0, y^hi_s),  y^lo_s <- lo - tau_s.c~ + max(0, y^lo_s)
+//                                                              [eqs. NonNegativeProject, UpdateV]
+//   g_s  <- T^-1 tau'_s.c~ + g_s - Proj(g_s)                   [eqs. DynamicProject, UpdateCloseW]
+//   xL_o = o! T^-o c~_o, xR_o = T^-o f_o.c~                    [end states, beta~ of eq. UpdateZ]
+// then, at each interior knot, z = (xR_i + xL_{i+1}) / 2 on the free orders [eq. UpdateZ] and
+// u += x - z on both ends [eq. UpdateU].  The identities behind the folded pairs are
+// b - s - v = b - |y| with y = A^o c - b + v, and phi - w = 2 Proj(g) - g with g = A^v c + w.
+#pragma once
+
+#include "common.h"
+
+namespace top {
+
+template <typename R>
+__device__ inline R inv_sqrt(R x);
+template <>
+__device__ inline float inv_sqrt<float>(float x) { return rsqrtf(x); }
+template <>
+__device__ inline double inv_sqrt<double>(double x) { return 1.0 / sqrt(x); }
+
+template <typename R, int P, int S, bool BOX, bool VEL>
+struct Lane {
+  static constexpr int N = 2 * P;
+  static constexpr int NH = N * (N + 1) / 2;
+  static constexpr int M = kSamples;
+  static constexpr int MB = BOX ? M : 1;
+  static constexpr int MV = VEL ? M : 1;
+  // state
+  R zL[3][S], zR[3][S], uL[3][S], uR[3][S], yh[3][MB], yl[3][MB], g[3][MV];
+  // constants
+  R H[NH], iT, iTp[S], lo[3], hi[3], vm;
+  bool first, last, has_left, has_right, fixpos;
+};
+
+// One sweep of one lane's segment.  With FINAL the local solve c~ and the end knot before its
+// update are returned through cfin / zfin.
+template <bool FINAL, typename R, int P, int S, bool BOX, bool VEL>
+__device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh)[3 * S],
+                                           R (*xl_sh)[3 * S], int wl, int wid, int nw,
+                                           R (&cfin)[3][2 * P], R (&zfin)[3][S]) {
+  using LT = Lane<R, P, S, BOX, VEL>;
+  constexpr int N = LT::N;
+  constexpr int M = LT::M;
+  constexpr int MV = LT::MV;
+
+  // velocity projection factors: Proj(g) = f g with f = min(1, vmax / ||g||)
+  R f[MV];
+#pragma unroll
+  for (int s = 0; s < MV; ++s) {
+    if constexpr (VEL) {
+      const R n2 = L.g[0][s] * L.g[0][s] + L.g[1][s] * L.g[1][s] + L.g[2][s] * L.g[2][s];
+      f[s] = fmin(R(1), L.vm * inv_sqrt<R>(n2));
+    } else {
+      f[s] = R(1);
+    }
+  }
+
+  R xL[3][S], xR[3][S];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R r[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) r[j] = R(0);
+    static_for<0, S>([&](auto o) {
+      const R wl_ = (L.zL[a][o] - L.uL[a][o]) * L.iTp[o];
+      constexpr R kf = R(cfact(o));
+      r[o] += kf * wl_;
+      const R wr_ = (L.zR[a][o] - L.uR[a][o]) * L.iTp[o];
+      static_for<o, N>([&](auto j) {
+        constexpr R k = R(cfall(o, j));
+        r[j] += k * wr_;
+      });
+    });
+    if constexpr (BOX) {
+      const R hl = L.hi[a] + L.lo[a];
+      static_for<0, M>([&](auto s) {
+        const R b = hl - fabs(L.yh[a][s]) + fabs(L.yl[a][s]);
+        static_for<0, N>([&](auto j) {
+          constexpr R k = R(cpos(s, j));
+          r[j] += k * b;
+        });
+      });
+    }
+    if constexpr (VEL) {
+      static_for<0, M>([&](auto s) {
+        const R b = (R(2) * f[s] - R(1)) * L.g[a][s] * L.iT;
+        static_for<1, N>([&](auto j) {
+          constexpr R k = R(cvel(s, j));
+          r[j] += k * b;
+        });
+      });
+    }
+    R c[N];
+    static_for<0, N>([&](auto i) {
+      R acc = R(0);
+      static_for<0, N>([&](auto j) { acc += L.H[tri(N, i, j)] * r[j]; });
+      c[i] = acc;
+    });
+    if constexpr (BOX) {
+      static_for<0, M>([&](auto s) {
+        R pv = R(0);
+        static_for<0, N>([&](auto j) {
+          constexpr R k = R(cpos(s, j));
+          pv += k * c[j];
+        });
+        L.yh[a][s] = pv - L.hi[a] + fmax(R(0), L.yh[a][s]);
+        L.yl[a][s] = L.lo[a] - pv + fmax(R(0), L.yl[a][s]);
+      });
+    }
+    if constexpr (VEL) {
+      static_for<0, M>([&](auto s) {
+        R vv = R(0);
+        static_for<1, N>([&](auto j) {
+          constexpr R k = R(cvel(s, j));
+          vv += k * c[j];
+        });
+        L.g[a][s] = vv * L.iT + (R(1) - f[s]) * L.g[a][s];
+      });
+    }
+    static_for<0, S>([&](auto o) {
+      constexpr R kf = R(cfact(o));
+      xL[a][o] = kf * c[o] * L.iTp[o];
+      R acc = R(0);
+      static_for<o, N>([&](auto j) {
+        constexpr R k = R(cfall(o, j));
+        acc += k * c[j];
+      });
+      xR[a][o] = acc * L.iTp[o];
+    });
+    if constexpr (FINAL) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) cfin[a][j] = c[j];
+    }
+  }
+
+  // ---- knot exchange: neighbours inside the wave by shuffles, across waves through LDS
+  if (wl == 63) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = 0; o < S; ++o) xr_sh[wid][a * S + o] = xR[a][o];
+  }
+  if (wl == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = 0; o < S; ++o) xl_sh[wid][a * S + o] = xL[a][o];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int o = 0; o < S; ++o) {
+      R xp = __shfl_up(xR[a][o], 1);
+      R xn = __shfl_down(xL[a][o], 1);
+      if (wl == 0 && wid > 0) xp = xr_sh[wid - 1][a * S + o];
+      if (wl == 63 && wid < nw - 1) xn = xl_sh[wid + 1][a * S + o];
+      xp = L.has_left ? xp : xL[a][o];
+      xn = L.has_right ? xn : xR[a][o];
+      if constexpr (FINAL) zfin[a][o] = L.zR[a][o];
+      const bool free_o = (o > 0) || !L.fixpos;
+      const R zr_new = R(0.5) * (xR[a][o] + xn);
+      const R zl_new = R(0.5) * (xp + xL[a][o]);
+      L.zR[a][o] = (!L.last && free_o) ? zr_new : L.zR[a][o];
+      L.zL[a][o] = (!L.first && free_o) ? zl_new : L.zL[a][o];
+      const R du_l = xL[a][o] - L.zL[a][o];
+      const R du_r = xR[a][o] - L.zR[a][o];
+      L.uL[a][o] += (o < P || !L.first) ? du_l : R(0);
+      L.uR[a][o] += (o < P || !L.last) ? du_r : R(0);
+    }
+  }
+}
+
+template <typename R, int P, int S, bool BOX, bool VEL, int LB>
+__global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
+  using LT = Lane<R, P, S, BOX, VEL>;
+  constexpr int N = LT::N;
+  constexpr int NH = LT::NH;
+  constexpr int M = LT::M;
+  constexpr int F_ZR = 0, F_UL = 3 * S, F_UR = 6 * S, F_YH = 9 * S;
+  constexpr int F_YL = F_YH + (BOX ? 3 * M : 0);
+  constexpr int F_G = 9 * S + (BOX ? 6 * M : 0);
+
+  __shared__ R xr_sh[2][kMaxWaves][3 * S];
+  __shared__ R xl_sh[2][kMaxWaves][3 * S];
+
+  const int W = A.W;
+  const int lane = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * W;
+  const int64_t ld = A.k.ld;
+  const int32_t ent = A.lane_seg[base + lane];
+  const bool active = ent >= 0;
+  const bool core = active && !(ent & kHaloBit);
+  const int64_t seg = active ? (int64_t)(ent & kSegMask) : 0;
+  const uint8_t fl = active ? A.k.flags[seg] : (uint8_t)(kFirst | kLast);
+
+  LT L;
+  L.first = fl & kFirst;
+  L.last = fl & kLast;
+  L.has_left = false;
+  L.has_right = false;
+  if (active && !L.first && lane > 0) {
+    const int32_t e = A.lane_seg[base + lane - 1];
+    L.has_left = e >= 0 && (int64_t)(e & kSegMask) == seg - 1;
+  }
+  if (active && !L.last && lane < W - 1) {
+    const int32_t e = A.lane_seg[base + lane + 1];
+    L.has_right = e >= 0 && (int64_t)(e & kSegMask) == seg + 1;
+  }
+  L.fixpos = A.fixpos != 0;
+
+  // ---- per-segment constants
+#pragma unroll
+  for (int h = 0; h < NH; ++h) L.H[h] = active ? A.k.Hr[h * ld + seg] : R(0);
+  L.iT = active ? A.k.iT[seg] : R(1);
+  L.vm = (VEL && active) ? A.k.vmax[seg] : R(1);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    L.lo[a] = (BOX && active) ? A.k.lo[a * ld + seg] : R(0);
+    L.hi[a] = (BOX && active) ? A.k.hi[a * ld + seg] : R(0);
+  }
+  L.iTp[0] = R(1);
+#pragma unroll
+  for (int o = 1; o < S; ++o) L.iTp[o] = L.iTp[o - 1] * L.iT;
+
+  // ---- state
+  const R* in = A.st_in;
+  const int tr = active ? A.k.traj[seg] : 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int o = 0; o < S; ++o) {
+      const int f = a * S + o;
+      L.zR[a][o] = active ? in[(F_ZR + f) * ld + seg] : R(0);
+      L.uL[a][o] = active ? in[(F_UL + f) * ld + seg] : R(0);
+      L.uR[a][o] = active ? in[(F_UR + f) * ld + seg] : R(0);
+      L.zL[a][o] = !active ? R(0)
+                 : L.first ? A.k.bcL[((int64_t)tr * 3 + a) * S + o]
+                           : in[(F_ZR + f) * ld + seg - 1];
+    }
+#pragma unroll
+    for (int s = 0; s < LT::MB; ++s) {
+      L.yh[a][s] = (BOX && active) ? in[(F_YH + a * M + s) * ld + seg] : R(0);
+      L.yl[a][s] = (BOX && active) ? in[(F_YL + a * M + s) * ld + seg] : R(0);
+    }
+#pragma unroll
+    for (int s = 0; s < LT::MV; ++s) L.g[a][s] = (VEL && active) ? in[(F_G + a * M + s) * ld + seg] : R(0);
+  }
+
+  const int wl = lane & 63, wid = lane >> 6, nw = W >> 6;
+  // A wave with no segment only has to keep the workgroup's barrier count (one per sweep).
+  if (__ballot(active) == 0) {
+    for (int it = 0; it < A.iters; ++it) __syncthreads();
+    return;
+  }
+  R cfin[3][N], zfin[3][S];
+  const int n_plain = A.final_out ? A.iters - 1 : A.iters;
+  int it = 0;
+  for (; it < n_plain; ++it)
+    sweep_once<false>(L, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
+  if (A.final_out && A.iters > 0) {
+    sweep_once<true>(L, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
+    if (core) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) A.c_out[(a * N + j) * ld + seg] = cfin[a][j];
+#pragma unroll
+        for (int o = 0; o < S; ++o) A.zold_out[(a * S + o) * ld + seg] = zfin[a][o];
+      }
+    }
+  }
+
+  if (core) {
+    R* out = A.st_out;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int o = 0; o < S; ++o) {
+        const int f = a * S + o;
+        out[(F_ZR + f) * ld + seg] = L.zR[a][o];
+        out[(F_UL + f) * ld + seg] = L.uL[a][o];
+        out[(F_UR + f) * ld + seg] = L.uR[a][o];
+      }
+      if constexpr (BOX) {
+#pragma unroll
+        for (int s = 0; s < M; ++s) {
+          out[(F_YH + a * M + s) * ld + seg] = L.yh[a][s];
+          out[(F_YL + a * M + s) * ld + seg] = L.yl[a][s];
+        }
+      }
+      if constexpr (VEL) {
+#pragma unroll
+        for (int s = 0; s < M; ++s) out[(F_G + a * M + s) * ld + seg] = L.g[a][s];
+      }
+    }
+  }
+}
+
+// LB3 / LB4: largest tile (launch bound) for the quintic / septic kernels.
+template <typename R, int LB3, int LB4>
+hipError_t dispatch_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st) {
+  const int lb = (v.p == 3) ? LB3 : LB4;
+  if (a.W <= 0 || a.W > lb || (a.W & 63) != 0 || n_tiles <= 0) return hipErrorInvalidValue;
+  dim3 grid(n_tiles), block(a.W);
+#define TOP_SWEEP_CASE(P_, S_, B_, V_, LB_)                                                   \
+  if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_) {                 \
+    hipLaunchKernelGGL((sweep_kernel<R, P_, S_, B_, V_, LB_>), grid, block, 0, st, a);       \
+    return hipGetLastError();                                                               \
+  }
+#define TOP_SWEEP_PS(P_, S_, LB_)                                                             \
+  TOP_SWEEP_CASE(P_, S_, true, true, LB_)                                                     \
+  TOP_SWEEP_CASE(P_, S_, true, false, LB_)                                                    \
+  TOP_SWEEP_CASE(P_, S_, false, true, LB_)                                                    \
+  TOP_SWEEP_CASE(P_, S_, false, false, LB_)
+  TOP_SWEEP_PS(3, 3, LB3)
+  TOP_SWEEP_PS(3, 4, LB3)
+  TOP_SWEEP_PS(4, 4, LB4)
+  TOP_SWEEP_PS(4, 5, LB4)
+#undef TOP_SWEEP_PS
+#undef TOP_SWEEP_CASE
+  return hipErrorInvalidValue;
+}
+
+// Largest tile the kernel of this variant accepts.
+inline int max_tile_lanes(const Variant& v) { return v.prec == 0 ? (v.p == 3 ? 512 : 256) : 256; }
+
+}  // namespace top

@@ -1,0 +1,97 @@
+"""The C-ABI library loads and exports every entry point include/top.h declares (no GPU needed).
+
+Host-side argument checks run before any HIP call, so their error codes are
+tested here too.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2507_10290_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "top.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(top_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = binding.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(binding.EXPORTED) == names
+
+
+def test_default_options_and_error_text():
+    o = binding.default_options()
+    assert (o.order, o.n_cont, o.fix_interior, o.n_samples, o.precision, o.use_graph) == (3, 0, 1, 8, 0, 1)
+    assert isinstance(binding.lib().top_last_error(), bytes)
+
+
+def _create(n_traj, offs, opts=None, with_ptrs=True):
+    L = binding.lib()
+    offs = np.asarray(offs, dtype=np.int64)
+    h = ctypes.c_void_p()
+    fake = 0x1000 if with_ptrs else None   # never dereferenced: host checks fail first
+    st = L.top_create(n_traj, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), fake, fake, None, None,
+                      None, None, fake, None if opts is None else ctypes.byref(opts), None, ctypes.byref(h))
+    return st, h.value, L.top_last_error().decode()
+
+
+def test_host_argument_errors():
+    st, h, msg = _create(0, [0])
+    assert st == binding.TOP_E_INVALID and h is None and "n_traj" in msg
+    st, h, msg = _create(2, [0, 3, 3])
+    assert st == binding.TOP_E_INVALID and "no segment" in msg
+    st, h, msg = _create(1, [1, 3])
+    assert st == binding.TOP_E_INVALID
+    st, h, msg = _create(1, [0, 3], with_ptrs=False)
+    assert st == binding.TOP_E_INVALID and "required" in msg
+    o = binding.default_options()
+    o.order = 5
+    st, h, msg = _create(1, [0, 3], o)
+    assert st == binding.TOP_E_UNSUPPORTED and "order" in msg
+    o = binding.default_options()
+    o.n_cont = 5
+    st, h, msg = _create(1, [0, 3], o)
+    assert st == binding.TOP_E_UNSUPPORTED and "n_cont" in msg
+    o = binding.default_options()
+    o.n_samples = 6
+    st, h, msg = _create(1, [0, 3], o)
+    assert st == binding.TOP_E_UNSUPPORTED
+    o = binding.default_options()
+    o.tile_lanes = 100
+    st, h, msg = _create(1, [0, 3], o)
+    assert st == binding.TOP_E_INVALID and "tile_lanes" in msg
+    o = binding.default_options()
+    o.checkpoint_every = 5
+    o.max_taped_iters = 0
+    st, h, msg = _create(1, [0, 3], o)
+    assert st == binding.TOP_E_INVALID
+
+
+def test_null_handle_calls():
+    L = binding.lib()
+    assert L.top_iterate(None, 3) == binding.TOP_E_INVALID
+    assert L.top_residuals(None, None, None) == binding.TOP_E_INVALID
+    assert L.top_cost(None, None) == binding.TOP_E_INVALID
+    assert L.top_coeffs(None, None) == binding.TOP_E_INVALID
+    assert L.top_sync_status(None) == binding.TOP_E_INVALID
+    assert L.top_tune(None, 3) == binding.TOP_E_INVALID
+    L.top_destroy(None)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    monkeypatch.setattr(binding, "_lib", None)
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "libtop.so"))
+    with pytest.raises(ImportError, match="missing"):
+        binding.lib()

@@ -1,0 +1,221 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on the same seeded inputs.
+
+Tolerances: float64 iterates 1e-10 relative (per-trajectory Frobenius norm of
+the coefficients, and the cost); float32 iterates 1e-4 on coefficients and
+1e-3 on the cost.  At full benchmark sizes the oracle checks samples: whole
+trajectories of the batched workload, and light-cone windows of the long
+trajectory (a segment's iterate after K sweeps depends only on segments
+within K of it).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2507_10290_amd.workloads import make_config, random_walk_batch
+from tests._harness import gpu_available, per_traj_rel, rel, run_gpu, run_oracle
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+TOL = {"fp64": (1e-10, 1e-10), "fp32": (1e-4, 1e-3)}
+
+
+def _check(w, K, precision, **kw):
+    print(f"[parity] {w.name} S={w.n_seg} B={w.n_traj} K={K} {precision} {kw}", flush=True)
+    cg, Jg, rpg, rdg = run_gpu(w, K, precision, **kw)
+    co, Jo, rpo, rdo = run_oracle(w, K)
+    tc, tJ = TOL[precision]
+    assert np.isfinite(cg).all()
+    ec = per_traj_rel(w, cg, co)
+    eJ = rel(Jg, Jo)
+    print(f"[parity]   coeff rel {ec:.3e}  cost rel {eJ:.3e}", flush=True)
+    assert ec <= tc, ec
+    assert eJ <= tJ, eJ
+    if precision == "fp64" and K > 0:
+        assert np.allclose(rpg, rpo, rtol=1e-8, atol=1e-12)
+        assert np.allclose(rdg, rdo, rtol=1e-8, atol=1e-12)
+    return cg, Jg
+
+
+def test_config0_fp64_plain():
+    _check(make_config(0), 200, "fp64")
+
+
+def test_config0_init_guess_is_exact_chord_step():
+    w = make_config(0)
+    cg, Jg, _, _ = run_gpu(w, 0, "fp64")
+    co, Jo, _, _ = run_oracle(w, 0)
+    assert per_traj_rel(w, cg, co) < 1e-13
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_config1_full(precision):
+    _check(make_config(1), 500, precision)
+
+
+def test_config1_fp64_halo_tiles():
+    # 1024 segments in 64-lane tiles with 8-sweep halos: many tile seams, ragged last tile
+    _check(make_config(1), 100, "fp64", tile_lanes=64, halo=8)
+
+
+def test_config2_septic_fp32_reduced():
+    _check(make_config(2, scale=1 / 32), 300, "fp32")
+
+
+def test_config2_septic_fp64_reduced_halo():
+    _check(make_config(2, scale=1 / 64), 120, "fp64", tile_lanes=128, halo=16)
+
+
+def test_config3_batched_subset():
+    w = make_config(3, n_traj=48)
+    _check(w, 200, "fp32")
+
+
+def test_config3_batched_subset_fp64():
+    _check(make_config(3, n_traj=24), 200, "fp64")
+
+
+def test_config4_subset_fp32():
+    _check(make_config(4, n_traj=16), 100, "fp32")
+
+
+def test_ragged_batch_edges_fp64():
+    # 1-segment trajectories, lengths at and around the tile width, a long one split with halos
+    lens = [1, 2, 63, 64, 65, 1, 128, 129, 300, 7]
+    w = random_walk_batch("ragged", lens, list(range(100, 100 + len(lens))), order=3,
+                          rho=[0.5, 1.0, 2.0, 1.0, 0.5, 2.0, 1.0, 1.0, 2.0, 0.5], precision="fp64")
+    _check(w, 60, "fp64", tile_lanes=128, halo=12)
+
+
+def test_free_interior_and_unconstrained_fp64():
+    w = random_walk_batch("free", [5, 9], [7, 8], order=3, box=False, vmax=None, rho=[1.0, 2.0],
+                          precision="fp64", fix_interior=False)
+    _check(w, 150, "fp64")
+
+
+def test_consensus_s_plus_one_fp64():
+    w = make_config(0)
+    w.n_cont = 4
+    cg, Jg, _, _ = run_gpu(w, 200, "fp64")
+    from oracle import cadmm
+    pr = cadmm.problem_from_workload(w, s=4)
+    r = cadmm.run(pr, 200)
+    co = cadmm.coeffs_by_axis(pr, r.c).numpy()
+    assert per_traj_rel(w, cg, co) < 1e-10
+    assert rel(Jg, r.J.numpy()) < 1e-10
+
+
+def test_box_only_and_vel_only_fp64():
+    w = make_config(1, scale=40 / 1024)
+    wb = make_config(1, scale=40 / 1024)
+    wb.vmax = None
+    _check(wb, 80, "fp64")
+    wv = make_config(1, scale=40 / 1024)
+    wv.box_lo = wv.box_hi = None
+    _check(wv, 80, "fp64")
+    del w
+
+
+# ---------------------------------------------------------------------------
+# Full benchmark sizes, sampled.
+# ---------------------------------------------------------------------------
+
+def test_config3_full_sampled_trajectories():
+    w = make_config(3)
+    K = w.iters
+    print(f"[parity] config3 full S={w.n_seg}", flush=True)
+    cg, Jg, rpg, rdg = run_gpu(w, K, "fp32")
+    assert np.isfinite(cg).all() and np.isfinite(Jg).all()
+    L = w.traj_lengths()
+    picks = sorted({int(np.argmin(L)), int(np.argmax(L)), 0, 1, 2047, 4095})
+    sub = w.subset(picks)
+    co, Jo, _, _ = run_oracle(sub, K)
+    for k, t in enumerate(picks):
+        s0, s1 = int(w.seg_offsets[t]), int(w.seg_offsets[t + 1])
+        q0, q1 = int(sub.seg_offsets[k]), int(sub.seg_offsets[k + 1])
+        e = np.linalg.norm(cg[s0:s1] - co[q0:q1]) / np.linalg.norm(co[q0:q1])
+        eJ = abs(Jg[t] - Jo[k]) / abs(Jo[k])
+        print(f"[parity]   traj {t} (N={s1 - s0}) coeff {e:.2e} cost {eJ:.2e}", flush=True)
+        assert e <= 1e-4 and eJ <= 1e-3
+
+
+def test_config2_full_light_cone_samples():
+    w = make_config(2)
+    K = w.iters
+    print(f"[parity] config2 full S={w.n_seg}", flush=True)
+    cg, Jg, _, _ = run_gpu(w, K, "fp32")
+    assert np.isfinite(cg).all() and np.isfinite(Jg).all()
+    N = w.n_seg
+    for i in [0, 1, 777, N // 2, N - 2, N - 1]:
+        lo, hi = max(0, i - K - 1), min(N, i + K + 2)
+        win = w.window(0, lo, hi)
+        co, _, _, _ = run_oracle(win, K)
+        ci = co[i - lo]
+        e = np.linalg.norm(cg[i] - ci) / np.linalg.norm(ci)
+        print(f"[parity]   segment {i}: coeff rel {e:.2e}", flush=True)
+        assert e <= 1e-4
+
+
+# ---------------------------------------------------------------------------
+# Execution-form invariances (bitwise).
+# ---------------------------------------------------------------------------
+
+def test_tiling_graph_and_split_are_bitwise_invariant():
+    w = make_config(3, n_traj=40)
+    base, Jb, _, _ = run_gpu(w, 50, "fp32")
+    for kw in ({"tile_lanes": 64, "halo": 4}, {"tile_lanes": 256}, {"use_graph": False}):
+        c, J, _, _ = run_gpu(w, 50, "fp32", **kw)
+        assert np.array_equal(c, base), kw
+        assert np.array_equal(J, Jb), kw
+    from paper_2507_10290_amd import TopProblem
+    prob = TopProblem.from_workload(w, precision="fp32")
+    prob.iterate(20).iterate(1).iterate(29)
+    c = prob.coeffs().cpu().numpy()
+    prob.close()
+    assert np.array_equal(c, base)
+
+
+def test_repeat_runs_bitwise_equal():
+    w = make_config(1, scale=0.25)
+    a = run_gpu(w, 100, "fp32")[0]
+    b = run_gpu(w, 100, "fp32")[0]
+    assert np.array_equal(a, b)
+
+
+def test_autotune_keeps_results():
+    w = make_config(3, n_traj=64)
+    from paper_2507_10290_amd import TopProblem
+    ref = run_gpu(w, 30, "fp32")[0]
+    prob = TopProblem.from_workload(w, precision="fp32")
+    plan = prob.tune(5)
+    assert plan["tile_lanes"] in (64, 128, 256, 512)
+    prob.iterate(30)
+    c = prob.coeffs().cpu().numpy()
+    prob.close()
+    assert np.array_equal(c, ref)
+
+
+# ---------------------------------------------------------------------------
+# Device-side argument errors.
+# ---------------------------------------------------------------------------
+
+def test_invalid_device_inputs_are_rejected():
+    from paper_2507_10290_amd import TopError, TopProblem
+    w = make_config(1, scale=8 / 1024)
+    bad = w.waypoints.copy()
+    bad[3, 1] = np.nan
+    with pytest.raises(TopError, match="waypoints"):
+        TopProblem(w.seg_offsets, bad, w.durations, w.rho, box_lo=w.box_lo, box_hi=w.box_hi, vmax=w.vmax)
+    T = w.durations.copy()
+    T[2] = 0.0
+    with pytest.raises(TopError, match="durations"):
+        TopProblem(w.seg_offsets, w.waypoints, T, w.rho)
+    with pytest.raises(TopError, match="rho"):
+        TopProblem(w.seg_offsets, w.waypoints, w.durations, -w.rho)
+    lo = w.box_lo.copy()
+    lo[0, 0] = w.box_hi[0, 0] + 1
+    with pytest.raises(TopError, match="box"):
+        TopProblem(w.seg_offsets, w.waypoints, w.durations, w.rho, box_lo=lo, box_hi=w.box_hi)
+    prob = TopProblem(w.seg_offsets, w.waypoints, w.durations, w.rho)
+    with pytest.raises(TopError, match="TOP_E_STATE"):
+        prob.residuals()
+    prob.close()
