@@ -34,10 +34,24 @@ constexpr int32_t kSegMask = kHaloBit - 1;
 
 enum : uint8_t { kFirst = 1, kLast = 2 };
 
-__host__ __device__ constexpr double cfact(int o) { return o <= 1 ? 1.0 : o * cfact(o - 1); }
+// The helpers below are loops, not recursion, so that a call left to run time needs no stack.
+__host__ __device__ constexpr double cfact(int o) {
+  double r = 1.0;
+  for (int k = 2; k <= o; ++k) r *= k;
+  return r;
+}
 // j! / (j - o)!: factor of the o-th derivative on t^j
-__host__ __device__ constexpr double cfall(int o, int j) { return j < o ? 0.0 : cfact(j) / cfact(j - o); }
-__host__ __device__ constexpr double cpow(double x, int e) { return e <= 0 ? 1.0 : x * cpow(x, e - 1); }
+__host__ __device__ constexpr double cfall(int o, int j) {
+  if (j < o) return 0.0;
+  double r = 1.0;
+  for (int k = j - o + 1; k <= j; ++k) r *= k;
+  return r;
+}
+__host__ __device__ constexpr double cpow(double x, int e) {
+  double r = 1.0;
+  for (int k = 0; k < e; ++k) r *= x;
+  return r;
+}
 // sample instant tau_s = (s+1)/(M+1), s = 0..M-1
 __host__ __device__ constexpr double ctau(int s) { return double(s + 1) / double(kSamples + 1); }
 // position row of sample s, coefficient j: tau_s^j
