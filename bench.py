@@ -1,0 +1,249 @@
+#!/usr/bin/env python3
+"""Benchmark of the batched CADMM trajectory sweep on one MI355X.
+
+One step = one complete solve of the batched workload (4,096 independent
+minimum-jerk trajectories of 8..512 segments, about 1.05 M segments, box
+corridors and velocity balls, rho per trajectory, fp32 iterates, K = 200
+sweeps): top_create (intake, float64 precompute, Init) -> top_iterate(200) ->
+cost, residuals and coefficients -> top_destroy.  Inputs are float64 device
+tensors resident in HBM before the timed region starts.
+
+value = segment-updates/s = (segments x sweeps) / (wall time per step).
+
+Prints one JSON line.  Extra measurements beside it (not part of `value`):
+the sweep kernel alone (HIP events on the library's stream) with its ALU
+roofline, the plain per-trajectory launch on a sample, the 65,536-segment
+septic trajectory, and the CPU oracle timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+PEAK_FP32_NONPACKED = 256 * 4 * 16 * 2 * 2.4e9   # CUs x SIMDs x lanes x (FMA = 2 flops) x clock = 78.6 TF/s
+PEAK_FP32_PACKED = 157.3e12                      # published fp32 vector peak (needs packed fp32 ops)
+PEAK_FP64 = 78.6e12
+HBM_PEAK = 8.0e12
+
+
+def flops_per_update(p: int, s: int, M: int, box: bool, vel: bool) -> int:
+    """Floating-point operations of one segment-update in the minimal form (FMA = 2)."""
+    N = 2 * p
+    ax = 4 * s + 2 * s + 2 * (N * s - s * (s - 1) // 2)            # knot terms of the right-hand side
+    ax += 2 * N * N                                                 # (rho Htilde^-1) r
+    ax += 2 * s + 2 * (N * s - s * (s - 1) // 2) + s                # end states
+    ax += 8 * s                                                     # knot average and dual update
+    if box:
+        ax += 1 + M * (2 + 2 * N) + M * (2 * N + 6)                 # box rows: rhs, evaluation, y update
+    if vel:
+        ax += M * (4 + 2 * (N - 1)) + M * (2 * (N - 1) + 4)         # velocity rows: rhs, evaluation, g update
+    return 3 * ax + (8 * M if vel else 0)                           # three axes + shared projections
+
+
+def bytes_per_update(p: int, s: int, M: int, box: bool, vel: bool, rbytes: int = 4) -> int:
+    """Minimal state read and written once plus read-only constants, per segment-update."""
+    N = 2 * p
+    state = 6 * s + 3 * (s - 1) + (6 * M if box else 0) + (3 * M if vel else 0)
+    const = N * (N + 1) // 2 + 1 + 3 + (6 if box else 0)
+    return (2 * state + const) * rbytes
+
+
+def _dev_inputs(w, dev):
+    import torch
+    t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
+    return dict(waypoints=t(w.waypoints), durations=t(w.durations), rho=t(w.rho), box_lo=t(w.box_lo),
+                box_hi=t(w.box_hi), vmax=t(w.vmax))
+
+
+def _problem(w, d, **kw):
+    from paper_2507_10290_amd import TopProblem
+    return TopProblem(w.seg_offsets, d["waypoints"], d["durations"], d["rho"], order=w.order,
+                      n_cont=w.n_cont, box_lo=d["box_lo"], box_hi=d["box_hi"], vmax=d["vmax"],
+                      fix_interior=w.fix_interior, **kw)
+
+
+def solve_step(w, d, K, precision="fp32"):
+    prob = _problem(w, d, precision=precision)
+    prob.iterate(K)
+    out = (prob.cost(), prob.residuals(), prob.coeffs())
+    prob.close()
+    return out
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def sweep_kernel_ms(w, d, K, reps=3, precision="fp32"):
+    """Average device time of the sweep launches of top_iterate(K), and launches per call."""
+    prob = _problem(w, d, precision=precision)
+    plan = prob.plan()
+    launches = 1 if plan["halo"] == 0 else -(-K // plan["halo"])
+    prob.time_sweeps(K)                       # warm-up
+    ms = [prob.time_sweeps(K) for _ in range(reps)]
+    prob.close()
+    return float(np.mean(ms)), launches, plan
+
+
+def plain_rate(w, d_all, K, n_traj):
+    """Plain form: one handle per trajectory, created, iterated without a graph and read back in turn."""
+    import torch
+    from paper_2507_10290_amd import TopProblem
+    segs = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for b in range(n_traj):
+        s0, s1 = int(w.seg_offsets[b]), int(w.seg_offsets[b + 1])
+        sl = lambda a: None if a is None else a[s0:s1]
+        prob = TopProblem([0, s1 - s0], d_all["waypoints"][s0 + b:s1 + b + 1], d_all["durations"][s0:s1],
+                          d_all["rho"][b:b + 1], order=w.order, box_lo=sl(d_all["box_lo"]),
+                          box_hi=sl(d_all["box_hi"]),
+                          vmax=None if d_all["vmax"] is None else d_all["vmax"][b:b + 1],
+                          precision="fp32", use_graph=False)
+        prob.iterate(K)
+        prob.cost()
+        prob.close()
+        segs += s1 - s0
+    torch.cuda.synchronize()
+    return segs * K / (time.perf_counter() - t0)
+
+
+def cpu_baseline(w, K, target_s=12.0):
+    """The float64 CPU oracle, as it stands, on the first trajectories of the same workload."""
+    import torch
+    from oracle import cadmm
+    # size the sample from a short probe so the run takes roughly target_s seconds
+    probe = w.subset(range(4))
+    pr = cadmm.problem_from_workload(probe)
+    t0 = time.perf_counter()
+    cadmm.run(pr, 10)
+    rate = probe.n_seg * 10 / (time.perf_counter() - t0)
+    want = rate * target_s / K
+    nb, segs = 0, 0
+    L = w.traj_lengths()
+    while nb < w.n_traj and segs + L[nb] <= max(want, L[0]):
+        segs += int(L[nb])
+        nb += 1
+    nb = max(nb, 1)
+    sub = w.subset(range(nb))
+    pr = cadmm.problem_from_workload(sub)
+    t0 = time.perf_counter()
+    cadmm.run(pr, K)
+    dt = time.perf_counter() - t0
+    return {"value": sub.n_seg * K / dt, "unit": "segment-updates/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"first {nb} trajectories ({sub.n_seg} segments) x {K} sweeps, float64 torch-CPU, "
+                      f"{dt:.1f} s"}
+
+
+def calib_copy(nbytes=1 << 30):
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    return nbytes
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="only the timed steps and the roofline")
+    ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter scale)")
+    a = ap.parse_args()
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the batched sweep has no cross-GPU exchange "
+              "(trajectories shard by count; see the design notes). Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    from paper_2507_10290_amd.workloads import config_summary, make_config
+
+    dev = torch.device("cuda:0")
+    w = make_config(3)
+    K = w.iters
+    d = _dev_inputs(w, dev)
+    torch.cuda.synchronize()
+
+    sec = time_steps(lambda: solve_step(w, d, K), a.steps, a.warmup)
+    value = w.n_seg * K / sec
+
+    # dominant kernel: the sweep, timed with HIP events on the stream it is launched on
+    kms, launches, plan = sweep_kernel_ms(w, d, K)
+    fpu = flops_per_update(w.order, w.n_cont, w.n_samples, True, True)
+    bpu = bytes_per_update(w.order, w.n_cont, w.n_samples, True, True)
+    per_launch_ms = kms / launches
+    achieved = fpu * w.n_seg * K / (kms * 1e-3)
+    sweep_rate = w.n_seg * K / (kms * 1e-3)
+    roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_FP32_NONPACKED / 1e12, 1),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4), "traffic": None,
+                "kernel": "sweep_kernel<float,3,3,box,vel,512>", "flops_per_segment_update": fpu,
+                "launch_ms": round(per_launch_ms, 4), "launches_per_step": launches,
+                "frac_of_packed_fp32_peak": round(achieved / PEAK_FP32_PACKED, 4)}
+
+    line = {"metric": "CADMM segment-updates/sec and % HBM peak, batched vs plain, fwd+bwd, 1 MI355X",
+            "value": round(value, 1), "unit": "segment-updates/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": config_summary(w)["workload"], "n_traj": w.n_traj, "n_seg": w.n_seg,
+                       "seg_per_traj": [8, 512], "order": w.order, "iters": K, "samples": w.n_samples,
+                       "constraints": "box+velocity", "tile_lanes": plan["tile_lanes"],
+                       "n_tiles": plan["n_tiles"]},
+            "roofline": roofline}
+    hbm = {"bytes_per_segment_update": bpu,
+           "equiv_GBps": round(bpu * sweep_rate / 1e9, 1),
+           "frac_of_8TBps": round(bpu * sweep_rate / HBM_PEAK, 3),
+           "regime": "state stays on chip across sweeps (VALU-bound); the yardstick counts one read "
+                     "and one write of the minimal state per segment-update"}
+    extra = {"sweep_only_segment_updates_per_s": round(sweep_rate, 1), "hbm_yardstick": hbm}
+    if not a.no_extras:
+        nplain = 128
+        pr = plain_rate(w, d, K, nplain)
+        extra["plain_segment_updates_per_s"] = round(pr, 1)
+        extra["plain_sample"] = f"first {nplain} trajectories, one handle each, no graph"
+        extra["batched_over_plain"] = round(value / pr, 1)
+        w2 = make_config(2)
+        d2 = _dev_inputs(w2, dev)
+        sec2 = time_steps(lambda: solve_step(w2, d2, w2.iters), 2, 1)
+        kms2, l2, plan2 = sweep_kernel_ms(w2, d2, w2.iters)
+        extra["septic_65536"] = {
+            "segment_updates_per_s": round(w2.n_seg * w2.iters / sec2, 1),
+            "sweep_only_segment_updates_per_s": round(w2.n_seg * w2.iters / (kms2 * 1e-3), 1),
+            "ms_per_solve": round(sec2 * 1e3, 3), "tile_lanes": plan2["tile_lanes"], "halo": plan2["halo"],
+            "alu_frac": round(flops_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters / (kms2 * 1e-3)
+                              / PEAK_FP32_NONPACKED, 4),
+            "hbm_yardstick_frac": round(bytes_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters
+                                        / (kms2 * 1e-3) / HBM_PEAK, 3)}
+        del d2
+    line["extra"] = extra
+    if a.calib_copy:
+        extra["calib_copy_bytes"] = calib_copy()
+    if not a.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(w, K)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -109,6 +109,11 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
  * UpdateConsensus, UpdateResidual, ProjectNonNeg, UpdateDual).  Asynchronous. */
 top_status top_iterate(top_problem* h, int32_t k);
 
+/* Like top_iterate(h, k) with k >= 1, launched directly (no graph), then blocks and stores in *ms
+ * [host] the device time from the first to the last sweep launch (outputs excluded), measured
+ * with HIP events on the handle's stream.  For benchmarking. */
+top_status top_time_sweeps(top_problem* h, int32_t k, float* ms);
+
 /* [dev] float64 [B] outputs: ||r_p|| and ||r_d|| of the last sweep (eqs. splitting_primal_residual
  * and splitting_dual_residual, the dual residual read per segment as rho M~(T_i)^T (z~^{k+1}-z~^k)).
  * Either pointer may be NULL.  TOP_E_STATE before the first sweep. */

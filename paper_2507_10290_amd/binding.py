@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "TOP_OK", -1: "TOP_E_INVALID", -3: "TOP_E_HIP", -4: "TOP_E_ST
                 -5: "TOP_E_NONFINITE", -6: "TOP_E_UNSUPPORTED", -7: "TOP_E_NOMEM"}
 
 # Every entry point declared in include/top.h.
-EXPORTED = ["top_default_options", "top_create", "top_iterate", "top_residuals", "top_cost",
+EXPORTED = ["top_default_options", "top_create", "top_iterate", "top_time_sweeps", "top_residuals", "top_cost",
             "top_coeffs", "top_backward", "top_tune", "top_sync_status", "top_get_plan",
             "top_destroy", "top_last_error"]
 
@@ -73,6 +73,8 @@ def lib() -> ctypes.CDLL:
     L.top_create.restype = ctypes.c_int
     L.top_iterate.argtypes = [vp, i32]
     L.top_iterate.restype = ctypes.c_int
+    L.top_time_sweeps.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_float)]
+    L.top_time_sweeps.restype = ctypes.c_int
     L.top_residuals.argtypes = [vp, dp, dp]
     L.top_residuals.restype = ctypes.c_int
     L.top_cost.argtypes = [vp, dp]
@@ -139,6 +141,12 @@ def top_create(seg_offsets: Sequence[int], waypoints, durations, rho, *, bc=None
 
 def top_iterate(h: int, k: int) -> None:
     _check(lib().top_iterate(ctypes.c_void_p(h), int(k)))
+
+
+def top_time_sweeps(h: int, k: int) -> float:
+    ms = ctypes.c_float()
+    _check(lib().top_time_sweeps(ctypes.c_void_p(h), int(k), ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def top_residuals(h: int, r_primal, r_dual) -> None:
@@ -224,6 +232,10 @@ class TopProblem:
     def iterate(self, k: int) -> "TopProblem":
         top_iterate(self.h, k)
         return self
+
+    def time_sweeps(self, k: int) -> float:
+        """Run k sweeps and return the device milliseconds of the sweep launches alone."""
+        return top_time_sweeps(self.h, k)
 
     def residuals(self):
         rp, rd = self._empty(self.B), self._empty(self.B)

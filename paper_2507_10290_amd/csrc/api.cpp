@@ -281,6 +281,19 @@ struct top_problem {
                        : finalize_t<double>(coeffs, with_res, write_part, st);
   }
 
+  // Host bookkeeping after k sweeps were queued (mirrors the launch sequence of enqueue).
+  void advance(int k) {
+    int remaining = k, done = iters_done;
+    while (remaining > 0) {
+      const int n = chunk(remaining, done);
+      cur ^= 1;
+      remaining -= n;
+      done += n;
+    }
+    iters_done = done;
+    have_sweep = true;
+  }
+
   // Sweeps per launch for the remaining count.
   int chunk(int remaining, int done) const {
     int n = remaining;
@@ -290,9 +303,11 @@ struct top_problem {
   }
 
   // The launch sequence of k sweeps starting from buffer `c0` and sweep index `done0`.
-  top_status enqueue(int k, int c0, int done0, hipStream_t st) {
+  top_status enqueue(int k, int c0, int done0, hipStream_t st, hipEvent_t ev0 = nullptr,
+                     hipEvent_t ev1 = nullptr) {
     int remaining = k, c = c0, done = done0;
     const size_t sbytes = (size_t)nf * ld * rsz;
+    if (ev0 != nullptr) TOP_HIP(hipEventRecord(ev0, st));
     while (remaining > 0) {
       const int n = chunk(remaining, done);
       const bool fin = (n == remaining);
@@ -308,6 +323,7 @@ struct top_problem {
                                  hipMemcpyDeviceToDevice, st));
       }
     }
+    if (ev1 != nullptr) TOP_HIP(hipEventRecord(ev1, st));
     // residual and cost partials of the last sweep, reduced per trajectory
     const int save = cur;
     cur = c;
@@ -526,17 +542,29 @@ top_status top_iterate(top_problem* h, int32_t k) {
     }
     TOP_HIP(hipGraphLaunch(it->second, h->stream));
   }
-  // advance the host-side bookkeeping exactly as enqueue did
-  int remaining = k, done = h->iters_done;
-  while (remaining > 0) {
-    const int n = h->chunk(remaining, done);
-    h->cur ^= 1;
-    remaining -= n;
-    done += n;
-  }
-  h->iters_done = done;
-  h->have_sweep = true;
+  h->advance(k);
   return TOP_OK;
+}
+
+top_status top_time_sweeps(top_problem* h, int32_t k, float* ms) {
+  if (h == nullptr || ms == nullptr) return fail(TOP_E_INVALID, "handle and ms must be non-NULL");
+  if (k < 1) return fail(TOP_E_INVALID, "k must be >= 1 (got %d)", k);
+  if (h->tape != nullptr && h->iters_done + k > h->opt.max_taped_iters)
+    return fail(TOP_E_STATE, "the tape holds %d sweeps; %d done, %d more asked", h->opt.max_taped_iters,
+                h->iters_done, k);
+  hipEvent_t e0, e1;
+  TOP_HIP(hipEventCreate(&e0));
+  TOP_HIP(hipEventCreate(&e1));
+  top_status s = h->enqueue(k, h->cur, h->iters_done, h->stream, e0, e1);
+  if (s == TOP_OK) {
+    h->advance(k);
+    hipError_t e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    if (e != hipSuccess) s = fail(TOP_E_HIP, "sweep timing failed: %s", hipGetErrorString(e));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return s;
 }
 
 top_status top_residuals(const top_problem* h, double* r_primal, double* r_dual) {
