@@ -121,6 +121,33 @@ def plain_rate(w, d_all, K, n_traj):
     return segs * K / (time.perf_counter() - t0)
 
 
+def fwd_bwd(w, d, K, m, reps=3):
+    """Differentiation workload: forward with a tape (create + K sweeps + cost), then top_backward."""
+    import torch
+    dc = torch.ones(w.n_traj, dtype=torch.float64, device="cuda:0")
+    tf, tb = [], []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob = _problem(w, d, precision="fp32", checkpoint_every=m, max_taped_iters=K)
+        prob.iterate(K)
+        prob.cost()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prob.backward(dc)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        prob.close()
+        tf.append(t1 - t0)
+        tb.append(t2 - t1)
+    f, b = float(np.median(tf[1:])), float(np.median(tb[1:]))
+    return {"workload": "256 trajectories x 128 segments, fp32, K = 100, checkpoint every 10",
+            "forward_ms": round(f * 1e3, 3), "backward_ms": round(b * 1e3, 3),
+            "backward_over_forward": round(b / f, 2),
+            "forward_segment_updates_per_s": round(w.n_seg * K / f, 1),
+            "fwd_plus_bwd_segment_updates_per_s": round(w.n_seg * K / (f + b), 1)}
+
+
 def cpu_baseline(w, K, target_s=12.0):
     """The float64 CPU oracle, as it stands, on the first trajectories of the same workload."""
     import torch
@@ -237,6 +264,8 @@ def main():
             "hbm_yardstick_frac": round(bytes_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters
                                         / (kms2 * 1e-3) / HBM_PEAK, 3)}
         del d2
+        w4 = make_config(4)
+        extra["fwd_bwd"] = fwd_bwd(w4, _dev_inputs(w4, dev), w4.iters, 10)
     line["extra"] = extra
     if a.calib_copy:
         extra["calib_copy_bytes"] = calib_copy()

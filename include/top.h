@@ -76,7 +76,8 @@ typedef struct top_options {
   int32_t tile_lanes;        /* segments per workgroup tile, a multiple of 64 in [64, 1024];
                                 0 picks the default (or the tuned value after top_tune)               */
   int32_t halo;              /* sweeps per launch for trajectories longer than a tile (their halo
-                                width); 0 picks the default                                           */
+                                width); 0 picks the default.  With a tape it must be >= 2: the
+                                reverse pass runs halo - 1 steps per launch                           */
   int32_t use_graph;         /* 1: replay each top_iterate(k) launch sequence as a cached hipGraph    */
 } top_options;
 

@@ -4,6 +4,6 @@
 * ``workloads`` -- seeded synthetic inputs of the benchmark workloads
 * ``build``     -- in-tree hipcc build of the library for gfx950
 """
-from .binding import TopError, TopProblem, lib  # noqa: F401
+from .binding import TopError, TopProblem, lib, top_cost_fn  # noqa: F401
 
-__all__ = ["TopProblem", "TopError", "lib"]
+__all__ = ["TopProblem", "TopError", "lib", "top_cost_fn"]

@@ -278,3 +278,50 @@ class TopProblem:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Autograd: J(waypoints, durations) through Init and K sweeps.
+# ---------------------------------------------------------------------------
+
+def _autograd_function():
+    import torch
+
+    class TopCost(torch.autograd.Function):
+        """Cost per trajectory after `iters` sweeps; backward runs the library's reverse pass.
+
+        Gradients flow to waypoints [S+B,3] and durations [S]; corridor, vmax and rho are
+        held constant.  The tape keeps the state every `checkpoint_every` sweeps.
+        """
+
+        @staticmethod
+        def forward(ctx, waypoints, durations, seg_offsets, rho, box_lo, box_hi, vmax, iters,
+                    checkpoint_every, precision, order):
+            prob = TopProblem(seg_offsets, waypoints.detach(), durations.detach(), rho, order=order,
+                              box_lo=box_lo, box_hi=box_hi, vmax=vmax, precision=precision,
+                              checkpoint_every=checkpoint_every, max_taped_iters=iters,
+                              device=str(waypoints.device))
+            prob.iterate(iters)
+            ctx.prob = prob
+            return prob.cost()
+
+        @staticmethod
+        def backward(ctx, gJ):
+            dP, dT = ctx.prob.backward(gJ.detach().to(torch.float64).contiguous())
+            ctx.prob.close()
+            return dP, dT, None, None, None, None, None, None, None, None, None
+
+    return TopCost
+
+
+_TopCost = None
+
+
+def top_cost_fn(waypoints, durations, seg_offsets, rho, *, box_lo=None, box_hi=None, vmax=None,
+                iters: int = 100, checkpoint_every: int = 10, precision: str = "fp32", order: int = 3):
+    """Differentiable cost J[B] of the trajectories after `iters` sweeps (torch tensors on the GPU)."""
+    global _TopCost
+    if _TopCost is None:
+        _TopCost = _autograd_function()
+    return _TopCost.apply(waypoints, durations, seg_offsets, rho, box_lo, box_hi, vmax, iters,
+                          checkpoint_every, precision, order)

@@ -11,12 +11,14 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
 #include <vector>
 
+#include "adjoint_impl.h"
 #include "common.h"
 
 namespace {
@@ -40,6 +42,22 @@ top_status fail(top_status s, const char* fmt, ...) {
   } while (0)
 
 int max_tile(const top::Variant& v) { return v.prec == 0 ? (v.p == 3 ? 512 : 256) : 256; }
+// Handles that keep a tape also run the adjoint kernel on the same tiles: it is built for tiles of up
+// to 256 lanes, and its per-lane LDS column (box and velocity pair adjoints) must fit the device's
+// per-workgroup LDS.
+int max_tile(const top::Variant& v, bool taped) {
+  if (!taped) return max_tile(v);
+  int lds = 65536;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int q = 0;
+    if (hipDeviceGetAttribute(&q, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && q > 0) lds = q;
+  }
+  const size_t rsz = v.prec == 0 ? 4 : 8;
+  int W = std::min(256, max_tile(v));
+  while (W > 64 && top::adjoint_lds_bytes(v, rsz, W) + top::kAdjointStaticLds > (size_t)lds) W -= 64;
+  return W;
+}
 
 struct Plan {
   int W = 0;
@@ -147,6 +165,120 @@ void tune_cache_store() {
   std::fclose(f);
 }
 
+// ---- device memory pool: blocks released by top_destroy are kept per (device, size class) and
+// handed to the next handle that asks for the same size class, so repeated problems of one shape
+// do not call hipMalloc/hipFree.  Released blocks were synchronised with their stream first.
+size_t size_class(size_t b) {
+  const size_t g = b < (size_t(2) << 20) ? size_t(4096) : (size_t(2) << 20);
+  return (b + g - 1) / g * g;
+}
+
+struct Pool {
+  std::mutex mu;
+  std::multimap<std::pair<int, size_t>, void*> blocks;
+  size_t cached = 0;
+  size_t cap() const {
+    const char* e = std::getenv("TOP_POOL_MAX_BYTES");
+    return e != nullptr ? std::strtoull(e, nullptr, 10) : (size_t(64) << 30);
+  }
+};
+Pool g_pool;
+
+hipError_t pool_get(size_t bytes, void** out, int* dev_out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const size_t sc = size_class(bytes);
+  *dev_out = dev;
+  {
+    std::lock_guard<std::mutex> lk(g_pool.mu);
+    auto it = g_pool.blocks.find({dev, sc});
+    if (it != g_pool.blocks.end()) {
+      *out = it->second;
+      g_pool.blocks.erase(it);
+      g_pool.cached -= sc;
+      return hipSuccess;
+    }
+  }
+  return hipMalloc(out, sc);
+}
+
+void pool_put(void* p, size_t bytes, int dev) {
+  const size_t sc = size_class(bytes);
+  std::lock_guard<std::mutex> lk(g_pool.mu);
+  if (g_pool.cached + sc > g_pool.cap()) {
+    (void)hipFree(p);
+    return;
+  }
+  g_pool.blocks.insert({{dev, sc}, p});
+  g_pool.cached += sc;
+}
+
+// ---- plan cache: the packed lane map of a CSR shape, on the device, shared by every handle of
+// that shape (immutable once built).
+struct PlanEntry {
+  Plan plan;
+  std::vector<int64_t> off;
+  int device = 0;
+  int32_t* dev = nullptr;
+  ~PlanEntry() {
+    if (dev != nullptr) (void)hipFree(dev);
+  }
+};
+
+std::mutex g_plan_mu;
+// Never destroyed: entries free device memory, which must not happen after the HIP runtime has
+// shut down at process exit.
+std::map<uint64_t, std::shared_ptr<PlanEntry>>& g_plans = *new std::map<uint64_t, std::shared_ptr<PlanEntry>>();
+
+uint64_t plan_key(const std::vector<int64_t>& off, int W, int halo, int device) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the offsets and the shape parameters
+  auto mix = [&](uint64_t v) {
+    for (int i = 0; i < 8; ++i) { h ^= (v >> (8 * i)) & 0xff; h *= 1099511628211ull; }
+  };
+  for (int64_t o : off) mix((uint64_t)o);
+  mix((uint64_t)W);
+  mix((uint64_t)halo);
+  mix((uint64_t)device);
+  return h;
+}
+
+// The cached plan of this shape, building and uploading it on first use.
+top_status get_plan(const std::vector<int64_t>& off, int W, int halo, std::shared_ptr<PlanEntry>* out) {
+  int dev = 0;
+  TOP_HIP(hipGetDevice(&dev));
+  const uint64_t key = plan_key(off, W, halo, dev);
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    auto it = g_plans.find(key);
+    if (it != g_plans.end() && it->second->off == off && it->second->plan.W == W) {
+      *out = it->second;
+      return TOP_OK;
+    }
+  }
+  auto e = std::make_shared<PlanEntry>();
+  e->plan = make_plan(off, W, halo);
+  e->off = off;
+  e->device = dev;
+  const size_t bytes = e->plan.lanes.size() * sizeof(int32_t);
+  void* q = nullptr;
+  hipError_t he = hipMalloc(&q, bytes);
+  if (he != hipSuccess) return fail(TOP_E_NOMEM, "hipMalloc(%zu) for the lane map failed", bytes);
+  e->dev = static_cast<int32_t*>(q);
+  he = hipMemcpy(e->dev, e->plan.lanes.data(), bytes, hipMemcpyHostToDevice);
+  if (he != hipSuccess) return fail(TOP_E_HIP, "lane map upload failed: %s", hipGetErrorString(he));
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  // keep at most 16 shapes; drop the ones no handle uses any more
+  if (g_plans.size() >= 16) {
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+      if (it->second.use_count() == 1) it = g_plans.erase(it); else ++it;
+    }
+  }
+  g_plans[key] = e;
+  *out = e;
+  return TOP_OK;
+}
+
 }  // namespace
 
 struct top_problem {
@@ -159,7 +291,8 @@ struct top_problem {
   std::vector<int64_t> off;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
-  std::vector<void*> allocs;
+  struct Block { void* p; size_t bytes; int dev; };
+  std::vector<Block> allocs;
   // device buffers
   void *Hr = nullptr, *iT = nullptr, *lo = nullptr, *hi = nullptr, *vmax = nullptr, *bcL = nullptr;
   void* state[2] = {nullptr, nullptr};
@@ -169,9 +302,10 @@ struct top_problem {
   double *Tdev = nullptr, *rho_seg = nullptr, *part = nullptr, *out = nullptr;
   int64_t* off_dev = nullptr;
   int* flag_dev = nullptr;
-  int32_t* lanes_dev = nullptr;
-  size_t lanes_cap = 0;
-  Plan plan;
+  std::shared_ptr<PlanEntry> pe;
+  Plan empty_plan;
+  const Plan& plan_ref() const { return pe ? pe->plan : empty_plan; }
+  const int32_t* lanes() const { return pe ? pe->dev : nullptr; }
   int cur = 0;
   int iters_done = 0;
   bool have_sweep = false;
@@ -179,6 +313,11 @@ struct top_problem {
   // tape: slot j holds the state before sweep j * checkpoint_every
   void* tape = nullptr;
   int tape_slots = 0;
+  // reverse pass: T-derivative of rho Htilde^-1, float64 copies of the inputs, work buffers
+  void* Hd = nullptr;
+  double *wp64 = nullptr, *lo64 = nullptr, *hi64 = nullptr, *vmax64 = nullptr, *bc64 = nullptr;
+  void *blk = nullptr, *adjb[2] = {nullptr, nullptr}, *acc_iT = nullptr, *acc_hd = nullptr, *acc_z0 = nullptr;
+  double *dPL = nullptr, *dPR = nullptr, *dK = nullptr, *dK0 = nullptr;
   std::map<std::tuple<int, int>, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_defs;
 
@@ -186,28 +325,11 @@ struct top_problem {
   top_status alloc(T** p, size_t bytes) {
     void* q = nullptr;
     if (bytes == 0) bytes = 256;
-    hipError_t e = hipMalloc(&q, bytes);
-    if (e != hipSuccess) return fail(TOP_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-    allocs.push_back(q);
+    int dev = 0;
+    hipError_t e = pool_get(bytes, &q, &dev);
+    if (e != hipSuccess) return fail(TOP_E_NOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    allocs.push_back({q, bytes, dev});
     *p = reinterpret_cast<T*>(q);
-    return TOP_OK;
-  }
-
-  top_status upload_plan(const Plan& pl) {
-    const size_t bytes = pl.lanes.size() * sizeof(int32_t);
-    if (bytes > lanes_cap) {
-      void* q = nullptr;
-      hipError_t e = hipMalloc(&q, bytes);
-      if (e != hipSuccess) return fail(TOP_E_NOMEM, "hipMalloc(%zu) failed", bytes);
-      if (lanes_dev != nullptr) {
-        TOP_HIP(hipStreamSynchronize(stream));
-        (void)hipFree(lanes_dev);
-      }
-      lanes_dev = static_cast<int32_t*>(q);
-      lanes_cap = bytes;
-    }
-    TOP_HIP(hipMemcpyAsync(lanes_dev, pl.lanes.data(), bytes, hipMemcpyHostToDevice, stream));
-    TOP_HIP(hipStreamSynchronize(stream));
     return TOP_OK;
   }
 
@@ -219,7 +341,7 @@ struct top_problem {
   }
 
   template <typename R>
-  top::SweepArgs<R> sweep_args(const Plan& pl) const {
+  top::SweepArgs<R> sweep_args(const Plan& pl, const int32_t* lane_map) const {
     top::SweepArgs<R> a{};
     a.k.Hr = (const R*)Hr;
     a.k.iT = (const R*)iT;
@@ -230,7 +352,7 @@ struct top_problem {
     a.k.traj = traj;
     a.k.bcL = (const R*)bcL;
     a.k.ld = ld;
-    a.lane_seg = lanes_dev;
+    a.lane_seg = lane_map;
     a.W = pl.W;
     a.fixpos = opt.fix_interior;
     a.c_out = (R*)cbuf;
@@ -239,8 +361,9 @@ struct top_problem {
   }
 
   template <typename R>
-  top_status launch_one(const Plan& pl, const void* in, void* outp, int n, bool fin, hipStream_t st) {
-    top::SweepArgs<R> a = sweep_args<R>(pl);
+  top_status launch_one(const Plan& pl, const int32_t* lane_map, const void* in, void* outp, int n, bool fin,
+                        hipStream_t st) {
+    top::SweepArgs<R> a = sweep_args<R>(pl, lane_map);
     a.st_in = (const R*)in;
     a.st_out = (R*)outp;
     a.iters = n;
@@ -250,8 +373,10 @@ struct top_problem {
     return TOP_OK;
   }
 
-  top_status sweep_launch(const Plan& pl, const void* in, void* outp, int n, bool fin, hipStream_t st) {
-    return v.prec == 0 ? launch_one<float>(pl, in, outp, n, fin, st) : launch_one<double>(pl, in, outp, n, fin, st);
+  top_status sweep_launch(const Plan& pl, const int32_t* lane_map, const void* in, void* outp, int n, bool fin,
+                          hipStream_t st) {
+    return v.prec == 0 ? launch_one<float>(pl, lane_map, in, outp, n, fin, st)
+                       : launch_one<double>(pl, lane_map, in, outp, n, fin, st);
   }
 
   template <typename R>
@@ -281,6 +406,99 @@ struct top_problem {
                        : finalize_t<double>(coeffs, with_res, write_part, st);
   }
 
+  template <typename R>
+  top_status backward_t(const double* dcost, double* dP, double* dT) {
+    const int K = iters_done, m = opt.checkpoint_every;
+    const size_t sl = (size_t)nf * ld;
+    top::Layout L{v.p, v.s, v.box, v.vel};
+    top_status s;
+    if (blk == nullptr) {
+      if ((s = alloc(&blk, (size_t)m * sl * sizeof(R))) != TOP_OK) return s;
+      for (int q = 0; q < 2; ++q)
+        if ((s = alloc(&adjb[q], sl * sizeof(R))) != TOP_OK) return s;
+      if ((s = alloc(&acc_iT, ld * sizeof(R))) != TOP_OK) return s;
+      if ((s = alloc(&acc_hd, ld * sizeof(R))) != TOP_OK) return s;
+      if ((s = alloc(&acc_z0, 3 * (size_t)v.s * ld * sizeof(R))) != TOP_OK) return s;
+      for (double** p : {&dPL, &dPR, &dK, &dK0})
+        if ((s = alloc(p, (size_t)S * 3 * sizeof(double))) != TOP_OK) return s;
+    }
+    auto chk = [](hipError_t e) -> top_status {
+      return e == hipSuccess ? TOP_OK : fail(TOP_E_HIP, "backward launch failed: %s", hipGetErrorString(e));
+    };
+    if ((s = chk(top::launch_fill<R>((R*)adjb[0], (int64_t)sl, R(0), stream))) != TOP_OK) return s;
+    if ((s = chk(top::launch_fill<R>((R*)acc_iT, ld, R(0), stream))) != TOP_OK) return s;
+    if ((s = chk(top::launch_fill<R>((R*)acc_hd, ld, R(0), stream))) != TOP_OK) return s;
+    if ((s = chk(top::launch_fill<R>((R*)acc_z0, 3 * v.s * ld, R(0), stream))) != TOP_OK) return s;
+    int ai = 0;
+    const int nblk = (K + m - 1) / m;
+    for (int j = nblk - 1; j >= 0; --j) {
+      const int k_lo = j * m;
+      const int n = std::min(K, k_lo + m) - k_lo;
+      // replay the block from its checkpoint, keeping the state before every sweep
+      TOP_HIP(hipMemcpyAsync(blk, (char*)tape + (size_t)j * sl * sizeof(R), sl * sizeof(R),
+                             hipMemcpyDeviceToDevice, stream));
+      for (int t = 1; t < n; ++t) {
+        s = sweep_launch(plan_ref(), lanes(), (R*)blk + (size_t)(t - 1) * sl, (R*)blk + (size_t)t * sl, 1, false,
+                         stream);
+        if (s != TOP_OK) return s;
+      }
+      int t_hi = n;
+      while (t_hi > 0) {
+        // Reverse steps per launch on split trajectories: halo - 1.  A wrong value entering at a
+        // tile's right edge reaches one lane further than in the forward sweep (the adjoint of a
+        // right knot also flows through the neighbour's solve into the next knot's u), so after
+        // `halo` steps the last core lane's knot adjoint would be stale.
+        const int cnt = plan_ref().halo > 0 ? std::min(t_hi, plan_ref().halo - 1) : t_hi;
+        const int t_lo = t_hi - cnt;
+        top::AdjArgs<R> a{};
+        a.k = sweep_args<R>(plan_ref(), lanes()).k;
+        a.Hd = (const R*)Hd;
+        a.lane_seg = lanes();
+        a.W = plan_ref().W;
+        a.fixpos = opt.fix_interior;
+        a.blk = (const R*)blk + (size_t)t_lo * sl;
+        a.slot = (int64_t)sl;
+        a.steps = cnt;
+        a.adj_in = (const R*)adjb[ai];
+        a.adj_out = (R*)adjb[ai ^ 1];
+        a.dcost = dcost;
+        a.with_cost = (k_lo + t_hi == K) ? 1 : 0;
+        a.acc_iT = (R*)acc_iT;
+        a.acc_hd = (R*)acc_hd;
+        a.acc_z0 = (R*)acc_z0;
+        if ((s = chk(top::launch_adjoint<R>(v, a, plan_ref().n_tiles, stream))) != TOP_OK) return s;
+        ai ^= 1;
+        t_hi = t_lo;
+      }
+    }
+    top::InitAdjArgs<R> ia{};
+    ia.waypoints = wp64;
+    ia.durations = Tdev;
+    ia.box_lo = lo64;
+    ia.box_hi = hi64;
+    ia.vmax = vmax64;
+    ia.bc = bc64;
+    ia.traj = traj;
+    ia.flags = flags;
+    ia.S = S;
+    ia.ld = ld;
+    ia.lam = (const R*)adjb[ai];
+    ia.acc_iT = (const R*)acc_iT;
+    ia.acc_hd = (const R*)acc_hd;
+    ia.acc_z0 = (const R*)acc_z0;
+    ia.dPL = dPL;
+    ia.dPR = dPR;
+    ia.dK = dK;
+    ia.dK0 = dK0;
+    ia.dT = dT;
+    if ((s = chk(top::launch_init_adjoint<R>(v, ia, stream))) != TOP_OK) return s;
+    if (dP != nullptr)
+      if ((s = chk(top::launch_gather_waypoints(dPL, dPR, dK, dK0, off_dev, B, S + B, dP, stream))) != TOP_OK)
+        return s;
+    (void)L;
+    return TOP_OK;
+  }
+
   // Host bookkeeping after k sweeps were queued (mirrors the launch sequence of enqueue).
   void advance(int k) {
     int remaining = k, done = iters_done;
@@ -297,7 +515,7 @@ struct top_problem {
   // Sweeps per launch for the remaining count.
   int chunk(int remaining, int done) const {
     int n = remaining;
-    if (plan.halo > 0) n = std::min(n, plan.halo);
+    if (plan_ref().halo > 0) n = std::min(n, plan_ref().halo);
     if (tape != nullptr) n = std::min(n, opt.checkpoint_every - (done % opt.checkpoint_every));
     return n;
   }
@@ -311,7 +529,7 @@ struct top_problem {
     while (remaining > 0) {
       const int n = chunk(remaining, done);
       const bool fin = (n == remaining);
-      top_status s = sweep_launch(plan, state[c], state[c ^ 1], n, fin, st);
+      top_status s = sweep_launch(plan_ref(), lanes(), state[c], state[c ^ 1], n, fin, st);
       if (s != TOP_OK) return s;
       c ^= 1;
       remaining -= n;
@@ -360,8 +578,7 @@ void top_destroy(top_problem* h) {
   (void)hipStreamSynchronize(h->stream);
   h->drop_graphs();
   if (h->cap_stream != nullptr) (void)hipStreamDestroy(h->cap_stream);
-  for (void* p : h->allocs) (void)hipFree(p);
-  if (h->lanes_dev != nullptr) (void)hipFree(h->lanes_dev);
+  for (auto& b : h->allocs) pool_put(b.p, b.bytes, b.dev);
   delete h;
 }
 
@@ -395,12 +612,22 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
   if (opt.checkpoint_every < 0 || (opt.checkpoint_every > 0 && opt.max_taped_iters < 1))
     return fail(TOP_E_INVALID, "checkpoint_every >= 0, and max_taped_iters >= 1 when it is > 0");
   top::Variant v{opt.precision == TOP_FP64 ? 1 : 0, opt.order, s, box_lo != nullptr, vmax != nullptr};
-  if (opt.tile_lanes != 0 && (opt.tile_lanes < 64 || opt.tile_lanes > max_tile(v) || opt.tile_lanes % 64 != 0))
-    return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, %d] (got %d)", max_tile(v), opt.tile_lanes);
+  const bool taped = opt.checkpoint_every > 0;
+  if (opt.tile_lanes != 0 &&
+      (opt.tile_lanes < 64 || opt.tile_lanes > max_tile(v, taped) || opt.tile_lanes % 64 != 0))
+    return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, %d] (got %d)", max_tile(v, taped),
+                opt.tile_lanes);
   if (opt.halo < 0) return fail(TOP_E_INVALID, "halo must be >= 0");
 
   top_problem* h = new (std::nothrow) top_problem();
   if (h == nullptr) return fail(TOP_E_NOMEM, "host allocation failed");
+  if (opt.checkpoint_every > 0 && opt.precision == TOP_FP64) {
+    // The float64 adjoint kernels keep a large spill area in per-lane scratch; make sure the
+    // runtime's per-thread stack limit is not below it.
+    size_t lim = 0;
+    if (hipDeviceGetLimit(&lim, hipLimitStackSize) == hipSuccess && lim < 16384)
+      (void)hipDeviceSetLimit(hipLimitStackSize, 16384);
+  }
   h->opt = opt;
   h->opt.n_cont = s;
   h->v = v;
@@ -437,6 +664,27 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
   if (opt.checkpoint_every > 0) {
     h->tape_slots = opt.max_taped_iters / opt.checkpoint_every + 1;
     if ((st = h->alloc(&h->tape, (size_t)h->tape_slots * h->nf * ld * R)) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->Hd, L.nh() * ld * R)) != TOP_OK) return bail(st);
+    const size_t nwp = (size_t)(S + n_traj) * 3 * sizeof(double);
+    if ((st = h->alloc(&h->wp64, nwp)) != TOP_OK) return bail(st);
+    hipError_t e = hipMemcpyAsync(h->wp64, waypoints, nwp, hipMemcpyDeviceToDevice, stream);
+    if (e == hipSuccess && box_lo != nullptr) {
+      if ((st = h->alloc(&h->lo64, (size_t)S * 3 * sizeof(double))) != TOP_OK) return bail(st);
+      if ((st = h->alloc(&h->hi64, (size_t)S * 3 * sizeof(double))) != TOP_OK) return bail(st);
+      e = hipMemcpyAsync(h->lo64, box_lo, (size_t)S * 3 * sizeof(double), hipMemcpyDeviceToDevice, stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(h->hi64, box_hi, (size_t)S * 3 * sizeof(double), hipMemcpyDeviceToDevice, stream);
+    }
+    if (e == hipSuccess && vmax != nullptr) {
+      if ((st = h->alloc(&h->vmax64, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
+      e = hipMemcpyAsync(h->vmax64, vmax, (size_t)n_traj * sizeof(double), hipMemcpyDeviceToDevice, stream);
+    }
+    if (e == hipSuccess && bc != nullptr) {
+      const size_t nbc = (size_t)n_traj * 2 * v.p * 3 * sizeof(double);
+      if ((st = h->alloc(&h->bc64, nbc)) != TOP_OK) return bail(st);
+      e = hipMemcpyAsync(h->bc64, bc, nbc, hipMemcpyDeviceToDevice, stream);
+    }
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "input copy failed: %s", hipGetErrorString(e)));
   }
   {
     hipError_t e = hipMemcpyAsync(h->off_dev, seg_offsets, (n_traj + 1) * sizeof(int64_t),
@@ -470,12 +718,12 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
     if (v.prec == 0) {
       top::SetupOut<float> o{(float*)h->Hr, (float*)h->iT, (float*)h->lo, (float*)h->hi, (float*)h->vmax,
                              h->flags, h->traj, (float*)h->bcL, (float*)h->state[0], (float*)h->cbuf,
-                             h->ld, h->Tdev, h->rho_seg};
+                             h->ld, h->Tdev, h->rho_seg, (float*)h->Hd};
       e = top::launch_setup<float>(v, sa, o, stream);
     } else {
       top::SetupOut<double> o{(double*)h->Hr, (double*)h->iT, (double*)h->lo, (double*)h->hi, (double*)h->vmax,
                               h->flags, h->traj, (double*)h->bcL, (double*)h->state[0], (double*)h->cbuf,
-                              h->ld, h->Tdev, h->rho_seg};
+                              h->ld, h->Tdev, h->rho_seg, (double*)h->Hd};
       e = top::launch_setup<double>(v, sa, o, stream);
     }
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "setup launch failed: %s", hipGetErrorString(e)));
@@ -497,16 +745,19 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache_load();
     auto it = g_tune.find(shape_key(v, h->off));
-    if (it != g_tune.end() && it->second.first <= max_tile(v)) {
+    if (it != g_tune.end() && it->second.first <= max_tile(v, taped)) {
       W = it->second.first;
       if (halo == 0) halo = it->second.second;
     }
   }
-  if (W == 0) W = max_tile(v);
+  if (W == 0) W = max_tile(v, taped);
   if (halo == 0) halo = std::max(1, std::min(32, W / 8));
   if (2 * halo >= W) return bail(fail(TOP_E_INVALID, "halo %d too large for %d-lane tiles", halo, W));
-  h->plan = make_plan(h->off, W, halo);
-  if ((st = h->upload_plan(h->plan)) != TOP_OK) return bail(st);
+  if (taped && halo < 2) {
+    if (opt.halo != 0) return bail(fail(TOP_E_INVALID, "a handle that records a tape needs halo >= 2 (got %d)", halo));
+    halo = 2;
+  }
+  if ((st = get_plan(h->off, W, halo, &h->pe)) != TOP_OK) return bail(st);
   *out = h;
   return TOP_OK;
 }
@@ -591,9 +842,11 @@ top_status top_coeffs(const top_problem* h, double* coeffs) {
 top_status top_backward(top_problem* h, const double* dcost, double* dwaypoints, double* ddurations) {
   if (h == nullptr || dcost == nullptr) return fail(TOP_E_INVALID, "handle and dcost must be non-NULL");
   if (h->tape == nullptr) return fail(TOP_E_STATE, "no tape: create with checkpoint_every > 0");
-  (void)dwaypoints;
-  (void)ddurations;
-  return fail(TOP_E_UNSUPPORTED, "top_backward is not built in this library version");
+  if (h->iters_done < 1) return fail(TOP_E_STATE, "no sweep has run yet");
+  if (h->iters_done > h->opt.max_taped_iters)
+    return fail(TOP_E_STATE, "%d sweeps run but the tape holds %d", h->iters_done, h->opt.max_taped_iters);
+  return h->v.prec == 0 ? h->backward_t<float>(dcost, dwaypoints, ddurations)
+                        : h->backward_t<double>(dcost, dwaypoints, ddurations);
 }
 
 top_status top_sync_status(top_problem* h) {
@@ -607,12 +860,12 @@ top_status top_sync_status(top_problem* h) {
 
 top_status top_get_plan(const top_problem* h, top_plan_info* info) {
   if (h == nullptr || info == nullptr) return fail(TOP_E_INVALID, "handle and info must be non-NULL");
-  info->tile_lanes = h->plan.W;
-  info->n_tiles = h->plan.n_tiles;
-  info->halo = h->plan.halo;
+  info->tile_lanes = h->plan_ref().W;
+  info->n_tiles = h->plan_ref().n_tiles;
+  info->halo = h->plan_ref().halo;
   info->n_traj = h->B;
   info->n_seg = h->S;
-  info->used_lanes = h->plan.used;
+  info->used_lanes = h->plan_ref().used;
   info->precision = h->opt.precision;
   info->order = h->opt.order;
   info->n_cont = h->opt.n_cont;
@@ -631,7 +884,7 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   int64_t mx = 0;
   for (int b = 0; b < h->B; ++b) mx = std::max(mx, h->off[b + 1] - h->off[b]);
   std::vector<std::pair<int, int>> cands;
-  for (int W = 64; W <= max_tile(h->v); W *= 2) {
+  for (int W = 64; W <= max_tile(h->v, h->tape != nullptr); W *= 2) {
     if (mx <= W) cands.push_back({W, 0});
     else
       for (int halo : {8, 16, 32})
@@ -641,11 +894,12 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   TOP_HIP(hipEventCreate(&e0));
   TOP_HIP(hipEventCreate(&e1));
   float best = 1e30f;
-  std::pair<int, int> bestc = {h->plan.W, h->plan.halo};
+  std::pair<int, int> bestc = {h->plan_ref().W, h->plan_ref().halo};
   for (auto c : cands) {
-    Plan pl = make_plan(h->off, c.first, c.second > 0 ? c.second : 1);
-    top_status s = h->upload_plan(pl);
+    std::shared_ptr<PlanEntry> cand;
+    top_status s = get_plan(h->off, c.first, c.second > 0 ? c.second : 1, &cand);
     if (s != TOP_OK) return s;
+    const Plan& pl = cand->plan;
     float tbest = 1e30f;
     for (int rep = 0; rep < 3; ++rep) {
       TOP_HIP(hipEventRecord(e0, h->stream));
@@ -653,7 +907,7 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
       while (remaining > 0) {
         const int n = pl.halo > 0 ? std::min(remaining, pl.halo) : remaining;
         // probe sweeps read the live state and write scratch; the iterate is not advanced
-        s = h->sweep_launch(pl, h->state[h->cur], h->scratch, n, false, h->stream);
+        s = h->sweep_launch(pl, cand->dev, h->state[h->cur], h->scratch, n, false, h->stream);
         if (s != TOP_OK) return s;
         remaining -= n;
       }
@@ -670,13 +924,13 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  h->plan = make_plan(h->off, bestc.first, bestc.second > 0 ? bestc.second : std::max(1, std::min(32, bestc.first / 8)));
-  top_status s = h->upload_plan(h->plan);
+  top_status s = get_plan(h->off, bestc.first,
+                          bestc.second > 0 ? bestc.second : std::max(1, std::min(32, bestc.first / 8)), &h->pe);
   if (s != TOP_OK) return s;
   h->drop_graphs();
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[shape_key(h->v, h->off)] = {h->plan.W, h->plan.halo};
+    g_tune[shape_key(h->v, h->off)] = {h->plan_ref().W, h->plan_ref().halo};
     tune_cache_store();
   }
   return TOP_OK;

@@ -146,6 +146,7 @@ struct SetupOut {
   R* state; R* c; int64_t ld;
   double* Tdev;              // [S] float64 copy of T (finalize)
   double* rho_seg;           // [S] float64 rho of the segment's trajectory (finalize)
+  R* Hd;                     // [nh][ld] d(rho Htilde^-1)/dT, or null when no tape is kept
 };
 
 template <typename R>
@@ -180,5 +181,50 @@ hipError_t launch_reduce(const double* part, int64_t S, const int64_t* seg_off, 
                          hipStream_t st);
 
 hipError_t launch_copy_rows(const double* src, double* dst, int B, hipStream_t st);
+
+// ---- reverse pass
+template <typename R>
+struct AdjArgs;
+template <typename R>
+hipError_t launch_adjoint(const Variant& v, const AdjArgs<R>& a, int n_tiles, hipStream_t st);
+
+template <typename R>
+hipError_t launch_fill(R* p, int64_t n, R v, hipStream_t st);
+
+// Dynamic LDS of the adjoint kernel: the box and velocity pair adjoints of every lane.
+inline size_t adjoint_lds_bytes(const Variant& v, size_t rsz, int W) {
+  const int nyg = (v.box ? 6 * kSamples : 0) + (v.vel ? 3 * kSamples : 0);
+  return (size_t)(nyg > 0 ? nyg : 1) * rsz * (size_t)W;
+}
+// Static LDS of the adjoint kernel (wave-boundary exchange buffers), an upper bound.
+constexpr size_t kAdjointStaticLds = 2 * kMaxWaves * 12 * 5 * sizeof(double);
+
+template <typename R>
+struct InitAdjArgs {
+  const double* waypoints;
+  const double* durations;
+  const double* box_lo;
+  const double* box_hi;
+  const double* vmax;
+  const double* bc;          // null: rest end states at the end waypoints
+  const int32_t* traj;
+  const uint8_t* flags;
+  int64_t S, ld;
+  const R* lam;              // adjoint of the Init state [nf][ld]
+  const R* acc_iT;
+  const R* acc_hd;
+  const R* acc_z0;           // [3s][ld]
+  double* dPL;               // [S][3] per segment: its start waypoint
+  double* dPR;               // [S][3] its end waypoint
+  double* dK;                // [S][3] its end knot's position
+  double* dK0;               // [S][3] the trajectory start knot's position (first segments)
+  double* dT;                // [S] or null
+};
+
+template <typename R>
+hipError_t launch_init_adjoint(const Variant& v, const InitAdjArgs<R>& a, hipStream_t st);
+
+hipError_t launch_gather_waypoints(const double* dPL, const double* dPR, const double* dK, const double* dK0,
+                                   const int64_t* off, int B, int64_t rows, double* dP, hipStream_t st);
 
 }  // namespace top

@@ -82,9 +82,9 @@ __global__ void setup_kernel(SetupArgs a, SetupOut<R> out) {
   const double T = a.durations[i];
   const double iT = 1.0 / T;
   const double rho = a.rho[b];
-  double iTp[N];
+  double iTp[2 * N];  // powers of 1/T up to 2N-1 (the T-derivative rows need 2o+1 <= 2s-1)
   iTp[0] = 1.0;
-  for (int o = 1; o < N; ++o) iTp[o] = iTp[o - 1] * iT;
+  for (int o = 1; o < 2 * N; ++o) iTp[o] = iTp[o - 1] * iT;
 
   // ---- Htilde = 2 T^(1-2p) Q(1) + rho [boundary rows + box rows + velocity rows]
   double H[N][N];
@@ -143,12 +143,45 @@ __global__ void setup_kernel(SetupArgs a, SetupOut<R> out) {
       Li[r][c] = v / H[r][r];
     }
   }
+  double Hi[N][N];
   for (int r = 0; r < N; ++r) {
     for (int c = r; c < N; ++c) {
       double v = 0.0;
       for (int k = c; k < N; ++k) v += Li[k][r] * Li[k][c];
+      Hi[r][c] = Hi[c][r] = v;
       out.Hr[(int64_t)tri(N, r, c) * ld + i] = (R)(rho * v);
     }
+  }
+  if (out.Hd != nullptr) {
+    // d(rho Htilde^-1)/dT = -rho Htilde^-1 (dHtilde/dT) Htilde^-1, with
+    // dHtilde/dT = 2(1-2p) T^-2p Q(1) + rho [ -2o (o!)^2 T^(-2o-1) on left rows,
+    //              -2o T^(-2o-1) f_o f_o^T on right rows, -2 T^-3 sum_s tau'_s tau'_s^T ]
+    double dH[N][N];
+    const double cq = 2.0 * (1.0 - 2.0 * P) * iTp[2 * P - 1] * iT;
+    for (int j = 0; j < N; ++j)
+      for (int k = 0; k < N; ++k) dH[j][k] = cq * cgram(P, j, k);
+    for (int o = 1; o < nL; ++o) dH[o][o] += rho * (-2.0 * o) * cfact(o) * cfact(o) * iTp[2 * o] * iT;
+    for (int o = 1; o < nR; ++o)
+      for (int j = 0; j < N; ++j)
+        for (int k = 0; k < N; ++k) dH[j][k] += rho * (-2.0 * o) * iTp[2 * o] * iT * cfall(o, j) * cfall(o, k);
+    if (VEL) {
+      for (int s = 0; s < M; ++s)
+        for (int j = 0; j < N; ++j)
+          for (int k = 0; k < N; ++k) dH[j][k] += rho * (-2.0) * iT * iT * iT * cvel(s, j) * cvel(s, k);
+    }
+    double tmp[N][N];
+    for (int r = 0; r < N; ++r)
+      for (int c = 0; c < N; ++c) {
+        double v = 0.0;
+        for (int k = 0; k < N; ++k) v += dH[r][k] * Hi[k][c];
+        tmp[r][c] = v;
+      }
+    for (int r = 0; r < N; ++r)
+      for (int c = r; c < N; ++c) {
+        double v = 0.0;
+        for (int k = 0; k < N; ++k) v += Hi[r][k] * tmp[k][c];
+        out.Hd[(int64_t)tri(N, r, c) * ld + i] = (R)(-rho * v);
+      }
   }
 
   // ---- per-segment constants

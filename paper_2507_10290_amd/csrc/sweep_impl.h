@@ -35,6 +35,12 @@ __device__ inline float inv_sqrt<float>(float x) { return rsqrtf(x); }
 template <>
 __device__ inline double inv_sqrt<double>(double x) { return 1.0 / sqrt(x); }
 
+// max(0, x).  For fp32 this is one integer max on the bit pattern (non-negative floats order like
+// their bits, negative ones have the sign bit set), which avoids the NaN-quieting copy an IEEE
+// fmax needs; the result is the same for every finite x.
+__device__ __forceinline__ float relu(float x) { return __int_as_float(max(__float_as_int(x), 0)); }
+__device__ __forceinline__ double relu(double x) { return fmax(0.0, x); }
+
 template <typename R, int P, int S, bool BOX, bool VEL>
 struct Lane {
   static constexpr int N = 2 * P;
@@ -120,8 +126,8 @@ __device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh
           constexpr R k = R(cpos(s, j));
           pv += k * c[j];
         });
-        L.yh[a][s] = pv - L.hi[a] + fmax(R(0), L.yh[a][s]);
-        L.yl[a][s] = L.lo[a] - pv + fmax(R(0), L.yl[a][s]);
+        L.yh[a][s] = pv - L.hi[a] + relu(L.yh[a][s]);
+        L.yl[a][s] = L.lo[a] - pv + relu(L.yl[a][s]);
       });
     }
     if constexpr (VEL) {

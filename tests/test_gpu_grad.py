@@ -1,0 +1,166 @@
+"""GPU reverse pass (top_backward) against the oracle's torch autograd and central differences.
+
+Gradients of sum_b dcost_b J_b after K sweeps with respect to the waypoints and
+durations; corridor, vmax and rho are held constant.  float64 iterates are
+compared to the oracle's autograd at 1e-8 (norm-wise, relative); float32 ones to
+the float64 GPU gradient at 1e-3.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cadmm
+from paper_2507_10290_amd.workloads import make_config, random_walk_batch
+from tests._harness import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def gpu_grad(w, K, m, precision, dcost, **kw):
+    from paper_2507_10290_amd import TopProblem
+    prob = TopProblem.from_workload(w, precision=precision, checkpoint_every=m, max_taped_iters=K, **kw)
+    prob.iterate(K)
+    J = prob.cost()
+    dP, dT = prob.backward(torch.tensor(dcost, dtype=torch.float64))
+    prob.sync_status()
+    out = J.cpu().numpy(), dP.cpu().numpy(), dT.cpu().numpy()
+    prob.close()
+    return out
+
+
+def oracle_grad(w, K, dcost):
+    P = torch.tensor(w.waypoints, dtype=torch.float64, requires_grad=True)
+    T = torch.tensor(w.durations, dtype=torch.float64, requires_grad=True)
+    pr = cadmm.problem_from_workload(w, P=P, T=T)
+    J = cadmm.run(pr, K).J
+    gP, gT = torch.autograd.grad((J * torch.tensor(dcost, dtype=torch.float64)).sum(), (P, T))
+    return J.detach().numpy(), gP.numpy(), gT.numpy()
+
+
+def nrel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _small_batch():
+    w4 = make_config(4, n_traj=2)
+    parts = [w4.window(0, 0, 10), w4.window(1, 3, 16)]
+    lens = [p.n_seg for p in parts]
+    w = random_walk_batch("gradbatch", lens, [41, 42], order=3, rho=[1.0, 2.0], precision="fp64")
+    w.waypoints = np.concatenate([p.waypoints for p in parts])
+    w.durations = np.concatenate([p.durations for p in parts])
+    w.box_lo = np.concatenate([p.box_lo for p in parts])
+    w.box_hi = np.concatenate([p.box_hi for p in parts])
+    return w
+
+
+@pytest.mark.parametrize("K,m", [(25, 7), (12, 12), (1, 4)])
+def test_fp64_backward_matches_oracle_autograd(K, m):
+    w = _small_batch()
+    dcost = [1.0, 0.5]
+    print(f"[grad] fp64 K={K} m={m}", flush=True)
+    Jg, dPg, dTg = gpu_grad(w, K, m, "fp64", dcost)
+    Jo, dPo, dTo = oracle_grad(w, K, dcost)
+    print(f"[grad]   J rel {nrel(Jg, Jo):.2e}  dP rel {nrel(dPg, dPo):.2e}  dT rel {nrel(dTg, dTo):.2e}", flush=True)
+    assert nrel(Jg, Jo) < 1e-11
+    assert nrel(dPg, dPo) < 1e-8
+    assert nrel(dTg, dTo) < 1e-8
+
+
+def test_fp64_backward_unconstrained_and_free_interior():
+    w = random_walk_batch("gfree", [6, 4], [51, 52], order=3, box=False, vmax=None, rho=[1.0, 3.0],
+                          precision="fp64", fix_interior=False)
+    dcost = [1.0, -2.0]
+    Jg, dPg, dTg = gpu_grad(w, 30, 8, "fp64", dcost)
+    Jo, dPo, dTo = oracle_grad(w, 30, dcost)
+    assert nrel(dPg, dPo) < 1e-8 and nrel(dTg, dTo) < 1e-8
+
+
+@pytest.mark.parametrize("order,halo", [(4, 5), (4, 2), (3, 5), (3, 8)])
+def test_fp64_backward_halo_tiles(order, halo):
+    # one 200-segment trajectory on 64-lane tiles: four tiles, several reverse launches per block,
+    # so the reverse state crosses tile edges between launches
+    w = make_config(2, scale=200 / 65536) if order == 4 else make_config(1, scale=200 / 1024)
+    w.precision = "fp64"
+    dcost = [1.0]
+    Jg, dPg, dTg = gpu_grad(w, 20, 6, "fp64", dcost, tile_lanes=64, halo=halo)
+    Jo, dPo, dTo = oracle_grad(w, 20, dcost)
+    print(f"[grad]   p={order} halo={halo} dP rel {nrel(dPg, dPo):.2e}  dT rel {nrel(dTg, dTo):.2e}", flush=True)
+    assert nrel(dPg, dPo) < 1e-8 and nrel(dTg, dTo) < 1e-8
+
+
+def test_fp32_backward_matches_fp64_config4_subset():
+    w = make_config(4, n_traj=16)
+    dcost = np.linspace(0.5, 1.5, 16)
+    _, dP64, dT64 = gpu_grad(w, 100, 10, "fp64", dcost)
+    _, dP32, dT32 = gpu_grad(w, 100, 10, "fp32", dcost)
+    print(f"[grad]   fp32 vs fp64: dP rel {nrel(dP32, dP64):.2e}  dT rel {nrel(dT32, dT64):.2e}", flush=True)
+    assert nrel(dP32, dP64) < 1e-3 and nrel(dT32, dT64) < 1e-3
+    # and the float64 gradient against the oracle on two of those trajectories
+    sub = w.subset([0, 7])
+    _, dPg, dTg = gpu_grad(sub, 100, 10, "fp64", [dcost[0], dcost[7]])
+    _, dPo, dTo = oracle_grad(sub, 100, [dcost[0], dcost[7]])
+    assert nrel(dPg, dPo) < 1e-8 and nrel(dTg, dTo) < 1e-8
+
+
+def test_central_differences_fp64():
+    from paper_2507_10290_amd import TopProblem
+    w = make_config(4, n_traj=1).window(0, 0, 12)
+    K = 40
+    _, dP, dT = gpu_grad(w, K, 10, "fp64", [1.0])
+
+    def J(wp, du):
+        prob = TopProblem(w.seg_offsets, wp, du, w.rho, box_lo=w.box_lo, box_hi=w.box_hi, vmax=w.vmax,
+                          precision="fp64")
+        prob.iterate(K)
+        v = prob.cost().cpu().numpy()[0]
+        prob.close()
+        return v
+
+    h = 1e-6
+    checked = 0
+    for i in [0, 3, 7, 11]:
+        e = np.zeros_like(w.durations); e[i] = h
+        fd = (J(w.waypoints, w.durations + e) - J(w.waypoints, w.durations - e)) / (2 * h)
+        assert abs(fd - dT[i]) <= 1e-5 * max(1.0, abs(dT[i])), (i, fd, dT[i])
+        checked += 1
+    for r, a in [(0, 0), (2, 1), (6, 2), (12, 0)]:
+        e = np.zeros_like(w.waypoints); e[r, a] = h
+        fd = (J(w.waypoints + e, w.durations) - J(w.waypoints - e, w.durations)) / (2 * h)
+        assert abs(fd - dP[r, a]) <= 1e-5 * max(1.0, abs(dP[r, a])), (r, a, fd, dP[r, a])
+        checked += 1
+    assert checked == 8
+
+
+def test_autograd_function_matches_backward():
+    from paper_2507_10290_amd import top_cost_fn
+    w = make_config(4, n_traj=3)
+    dev = torch.device("cuda:0")
+    P = torch.tensor(w.waypoints, dtype=torch.float64, device=dev, requires_grad=True)
+    T = torch.tensor(w.durations, dtype=torch.float64, device=dev, requires_grad=True)
+    t = lambda a: torch.tensor(a, dtype=torch.float64, device=dev)
+    J = top_cost_fn(P, T, w.seg_offsets, t(w.rho), box_lo=t(w.box_lo), box_hi=t(w.box_hi), vmax=t(w.vmax),
+                    iters=30, checkpoint_every=10, precision="fp64")
+    (J * torch.tensor([1.0, 2.0, 3.0], dtype=torch.float64, device=dev)).sum().backward()
+    _, dP, dT = gpu_grad(w, 30, 10, "fp64", [1.0, 2.0, 3.0])
+    assert np.allclose(P.grad.cpu().numpy(), dP, rtol=1e-12, atol=1e-12)
+    assert np.allclose(T.grad.cpu().numpy(), dT, rtol=1e-12, atol=1e-12)
+
+
+def test_backward_error_paths():
+    from paper_2507_10290_amd import TopError, TopProblem
+    w = make_config(4, n_traj=1)
+    prob = TopProblem.from_workload(w)
+    prob.iterate(3)
+    with pytest.raises(TopError, match="no tape"):
+        prob.backward(torch.ones(1, dtype=torch.float64))
+    prob.close()
+    prob = TopProblem.from_workload(w, checkpoint_every=5, max_taped_iters=10)
+    with pytest.raises(TopError, match="no sweep"):
+        prob.backward(torch.ones(1, dtype=torch.float64))
+    with pytest.raises(TopError, match="tape holds"):
+        prob.iterate(11)
+    prob.close()
+    # a tape on split trajectories needs at least two halo lanes
+    with pytest.raises(TopError, match="halo >= 2"):
+        TopProblem.from_workload(make_config(1, scale=200 / 1024), checkpoint_every=5, max_taped_iters=10,
+                                 tile_lanes=64, halo=1)
