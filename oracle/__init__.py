@@ -15,6 +15,8 @@ the oracle's own gradients), written in the paper's variables and order:
   paper's variables c, z, u, s, v, phi, w as they are printed.
 * ``minimal``     — the same iteration with the slack/dual pairs folded into
   one value per constraint row (used only to pin that algebra).
+* ``adaptive``    — the stopping test and the adaptive penalty rule of
+  Sec. III-D.3 around that iteration, one trajectory at a time.
 * ``references``  — direct solutions the iteration must converge to: the
   global KKT system, the square optimality-condition system, and a
   general-purpose constrained solve.

@@ -28,7 +28,8 @@ its justification in the design notes of the repository):
 * Init: each segment starts on its chord as the rest-to-rest step polynomial,
   z^0 holds the waypoint positions with zero higher derivatives, all scaled
   duals start at zero, s^0 = max(0, b - A^o c^0), phi^0 = Proj(A^v c^0);
-* rho is fixed per trajectory (the adaptive-rho rule is not part of this run).
+* rho is fixed per trajectory here; the stopping test and the adaptive-rho
+  rule are applied around this iteration by ``adaptive``.
 """
 from __future__ import annotations
 
