@@ -79,9 +79,24 @@ typedef struct top_options {
                                 width); 0 picks the default.  With a tape it must be >= 2: the
                                 reverse pass runs halo - 1 steps per launch                           */
   int32_t use_graph;         /* 1: replay each top_iterate(k) launch sequence as a cached hipGraph    */
+  /* Stopping test and adaptive penalty (Sec. III-D.3, eqs. splitting_tolerance and UpdateRho).
+     Residuals are formed every check_every sweeps, counted from Init; at each such check a
+     trajectory of N segments whose ||r_p||^2 and ||r_d||^2 are both below (N tol)^2 stops (its
+     coefficients, cost and residuals stay those of that sweep; later sweeps leave it unchanged),
+     and otherwise, with adapt_rho, its rho is multiplied by tau_incr when ||r_p|| > mu ||r_d||
+     or divided by tau_decr when ||r_d|| > mu ||r_p||, the scaled duals being multiplied by
+     rho_old / rho_new.  Not available together with a tape.                                       */
+  int32_t check_every;       /* sweeps between checks; 0 disables checks (fixed rho, no stopping)    */
+  int32_t adapt_rho;         /* 1: apply the penalty rule at every check                             */
+  double tol;                /* E of the stopping test; <= 0 never stops (the paper uses 0.05)        */
+  double mu;                 /* residual ratio that triggers a change (> 1; the paper uses 10)        */
+  double tau_incr;           /* growth factor (> 1; the paper uses 1.1)                               */
+  double tau_decr;           /* shrink factor (> 1; the paper uses 1.1)                               */
 } top_options;
 
-/* Fill *opt with the defaults: p = 3, s = p, pinned interior, M = 8, FP32, no tape, graph on. */
+/* Fill *opt with the defaults: p = 3, s = p, pinned interior, M = 8, FP32, no tape, graph on,
+   no checks (check_every = 0), and the paper's rule constants tol = 0.05, mu = 10,
+   tau_incr = tau_decr = 1.1 for when checks are switched on. */
 void top_default_options(top_options* opt);
 
 /* Create a problem and run Init (Algorithm 1) on `stream`.
@@ -106,8 +121,9 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
                       const double* box_hi, const double* vmax, const double* rho,
                       const top_options* opt, hipStream_t stream, top_problem** out);
 
-/* Queue k >= 0 more sweeps (Algorithm 1 loop body with fixed rho: ClosedFormSolve,
- * UpdateConsensus, UpdateResidual, ProjectNonNeg, UpdateDual).  Asynchronous. */
+/* Queue k >= 0 more sweeps (Algorithm 1 loop body: ClosedFormSolve, UpdateConsensus,
+ * UpdateResidual, ProjectNonNeg, UpdateDual, and UpdateRho at the checks when check_every > 0).
+ * Trajectories that passed the stopping test are left unchanged.  Asynchronous. */
 top_status top_iterate(top_problem* h, int32_t k);
 
 /* Like top_iterate(h, k) with k >= 1, launched directly (no graph), then blocks and stores in *ms
@@ -140,6 +156,14 @@ top_status top_backward(top_problem* h, const double* dcost, double* dwaypoints,
  * iterate untouched), keep the fastest and remember it for problems of the same shape class.
  * Blocks.  A tile shape given explicitly in the options is not overridden. */
 top_status top_tune(top_problem* h, int32_t k_probe);
+
+/* Per-trajectory outcome of the checks (Sec. III-D.3), written on the handle's stream:
+ *   iters  [dev] int32 [B]: sweeps applied to each trajectory (where it stopped, else all so far)
+ *   rho    [dev] float64 [B]: its current penalty (the input rho when adapt_rho is off)
+ *   done   [dev] uint8 [B]: 1 if it passed the stopping test
+ * Any pointer may be NULL.  Without checks every trajectory reports all sweeps, its input rho
+ * and 0. */
+top_status top_convergence(const top_problem* h, int32_t* iters, double* rho, uint8_t* done);
 
 /* Block on the stream; TOP_E_NONFINITE if any sweep so far produced a non-finite value. */
 top_status top_sync_status(top_problem* h);

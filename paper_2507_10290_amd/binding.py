@@ -30,7 +30,7 @@ STATUS_NAMES = {0: "TOP_OK", -1: "TOP_E_INVALID", -3: "TOP_E_HIP", -4: "TOP_E_ST
 
 # Every entry point declared in include/top.h.
 EXPORTED = ["top_default_options", "top_create", "top_iterate", "top_time_sweeps", "top_residuals", "top_cost",
-            "top_coeffs", "top_backward", "top_tune", "top_sync_status", "top_get_plan",
+            "top_coeffs", "top_backward", "top_tune", "top_convergence", "top_sync_status", "top_get_plan",
             "top_destroy", "top_last_error"]
 
 
@@ -38,7 +38,9 @@ class TopOptions(ctypes.Structure):
     _fields_ = [("order", ctypes.c_int32), ("n_cont", ctypes.c_int32), ("fix_interior", ctypes.c_int32),
                 ("n_samples", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("checkpoint_every", ctypes.c_int32), ("max_taped_iters", ctypes.c_int32),
-                ("tile_lanes", ctypes.c_int32), ("halo", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("tile_lanes", ctypes.c_int32), ("halo", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("check_every", ctypes.c_int32), ("adapt_rho", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("mu", ctypes.c_double), ("tau_incr", ctypes.c_double), ("tau_decr", ctypes.c_double)]
 
 
 class TopPlanInfo(ctypes.Structure):
@@ -85,6 +87,8 @@ def lib() -> ctypes.CDLL:
     L.top_backward.restype = ctypes.c_int
     L.top_tune.argtypes = [vp, i32]
     L.top_tune.restype = ctypes.c_int
+    L.top_convergence.argtypes = [vp, vp, vp, vp]
+    L.top_convergence.restype = ctypes.c_int
     L.top_sync_status.argtypes = [vp]
     L.top_sync_status.restype = ctypes.c_int
     L.top_get_plan.argtypes = [vp, ctypes.POINTER(TopPlanInfo)]
@@ -169,6 +173,10 @@ def top_tune(h: int, k_probe: int) -> None:
     _check(lib().top_tune(ctypes.c_void_p(h), int(k_probe)))
 
 
+def top_convergence(h: int, iters, rho, done) -> None:
+    _check(lib().top_convergence(ctypes.c_void_p(h), _ptr(iters), _ptr(rho), _ptr(done)))
+
+
 def top_sync_status(h: int) -> None:
     _check(lib().top_sync_status(ctypes.c_void_p(h)))
 
@@ -193,8 +201,9 @@ class TopProblem:
     def __init__(self, seg_offsets, waypoints, durations, rho, *, order: int = 3, n_cont: int = 0,
                  bc=None, box_lo=None, box_hi=None, vmax=None, precision: str = "fp32",
                  fix_interior: bool = True, checkpoint_every: int = 0, max_taped_iters: int = 0,
-                 tile_lanes: int = 0, halo: int = 0, use_graph: bool = True, device: str = "cuda:0",
-                 stream=None):
+                 tile_lanes: int = 0, halo: int = 0, use_graph: bool = True, check_every: int = 0,
+                 adapt_rho: bool = False, tol: float = 0.05, mu: float = 10.0, tau_incr: float = 1.1,
+                 tau_decr: float = 1.1, device: str = "cuda:0", stream=None):
         import torch
         self.device = torch.device(device)
         self.seg_offsets = np.asarray(seg_offsets, dtype=np.int64)
@@ -212,6 +221,9 @@ class TopProblem:
         o.tile_lanes = int(tile_lanes)
         o.halo = int(halo)
         o.use_graph = 1 if use_graph else 0
+        o.check_every = int(check_every)
+        o.adapt_rho = 1 if adapt_rho else 0
+        o.tol, o.mu, o.tau_incr, o.tau_decr = float(tol), float(mu), float(tau_incr), float(tau_decr)
         self.options = o
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         args = [_dev(x, self.device) for x in (waypoints, durations, rho, bc, box_lo, box_hi, vmax)]
@@ -261,6 +273,15 @@ class TopProblem:
     def tune(self, k_probe: int = 20) -> dict:
         top_tune(self.h, k_probe)
         return self.plan()
+
+    def convergence(self):
+        """(sweeps applied, current rho, stopped) per trajectory, as device tensors."""
+        import torch
+        it = torch.empty(self.B, dtype=torch.int32, device=self.device)
+        done = torch.empty(self.B, dtype=torch.uint8, device=self.device)
+        rho = self._empty(self.B)
+        top_convergence(self.h, it, rho, done)
+        return it, rho, done.bool()
 
     def sync_status(self) -> None:
         top_sync_status(self.h)

@@ -19,7 +19,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtop.so")
 
 SOURCES = ["sweep_f32.hip", "sweep_f64.hip", "adjoint_f32.hip", "adjoint_f64.hip", "setup.hip",
-           "finalize.hip", "grad.hip", "api.cpp"]
+           "finalize.hip", "grad.hip", "adapt.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 VALU forms are kept out of the generated code.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,

@@ -1,0 +1,145 @@
+// Stopping test and adaptive penalty between sweeps (Sec. III-D.3, eqs.
+// splitting_tolerance and UpdateRho).
+//
+// A check follows a sweep launch whose last sweep wrote c~ and the old knots;
+// the finalize/reduce kernels have turned them into per-trajectory residual
+// norms.  check_kernel then decides per trajectory (float64): stop, or update
+// rho.  rescale_kernel applies a change of rho to the folded state and to the
+// per-segment solve matrix:
+//   * scaled consensus duals: u <- r u with r = rho_old / rho_new;
+//   * box pairs: y stands for the slack max(0, -y) and the scaled dual max(0, y),
+//     so only a positive y is scaled;
+//   * velocity: g stands for the split value Proj(g) and the scaled dual
+//     g - Proj(g), so g <- Proj(g) + r (g - Proj(g));
+//   * rho * Htilde^-1 is rebuilt in float64 at the new rho.
+#include "common.h"
+#include "htilde.h"
+#include "sweep_impl.h"
+
+namespace top {
+
+__global__ void check_kernel(CheckArgs a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.B) return;
+  double ratio = 1.0;
+  if (a.done[b] == 0) {
+    a.swept[b] += a.check_every;
+    const double rp = a.res[a.B + b], rd = a.res[2 * a.B + b];
+    const double t = (double)(a.off[b + 1] - a.off[b]) * a.tol;
+    if (a.tol > 0.0 && rp * rp < t * t && rd * rd < t * t) {
+      a.done[b] = 1;
+      a.stop_at[b] = a.swept[b];
+    } else if (a.adapt) {
+      const double old = a.rho[b];
+      double nw = old;
+      if (rp > a.mu * rd) nw = old * a.tau_incr;
+      else if (rd > a.mu * rp) nw = old / a.tau_decr;
+      if (nw != old) {
+        ratio = old / nw;
+        a.rho[b] = nw;
+      }
+    }
+  }
+  a.ratio[b] = ratio;
+}
+
+hipError_t launch_check(const CheckArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(check_kernel, dim3((a.B + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename R, int P, int S, bool BOX, bool VEL>
+__global__ void rescale_kernel(RescaleArgs<R> a) {
+  constexpr int N = 2 * P;
+  constexpr int M = kSamples;
+  constexpr int F_UL = 3 * S, F_YH = 9 * S;
+  constexpr int F_YL = F_YH + (BOX ? 3 * M : 0);
+  constexpr int F_G = 9 * S + (BOX ? 6 * M : 0);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.S) return;
+  const int b = a.traj[i];
+  const double r = a.ratio[b];
+  if (r == 1.0) return;
+  const int64_t ld = a.ld;
+  R* st = a.state;
+  const R rr = (R)r;
+  for (int f = F_UL; f < F_UL + 6 * S; ++f) st[f * ld + i] *= rr;
+  if (BOX) {
+    for (int f = F_YH; f < F_YL + 3 * M; ++f) {
+      const R y = st[f * ld + i];
+      if (y > R(0)) st[f * ld + i] = rr * y;
+    }
+  }
+  if (VEL) {
+    const R vm = a.vmax[i];
+    for (int s = 0; s < M; ++s) {
+      R g[3];
+      for (int c = 0; c < 3; ++c) g[c] = st[(F_G + c * M + s) * ld + i];
+      const R n2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+      const R f = fmin(R(1), vm * inv_sqrt<R>(n2));
+      for (int c = 0; c < 3; ++c) {
+        const R pr = f * g[c];
+        st[(F_G + c * M + s) * ld + i] = pr + rr * (g[c] - pr);
+      }
+    }
+  }
+  // rho * Htilde^-1 at the new rho
+  const double rho = a.rho[b];
+  a.rho_seg[i] = rho;
+  const uint8_t fl = a.flags[i];
+  const double iT = 1.0 / a.T[i];
+  double iTp[2 * N];
+  iTp[0] = 1.0;
+  for (int o = 1; o < 2 * N; ++o) iTp[o] = iTp[o - 1] * iT;
+  double H[N][N], Hi[N][N];
+  build_htilde<P, S, BOX, VEL>(iTp, iT, rho, (fl & kFirst) != 0, (fl & kLast) != 0, H);
+  spd_inverse<N>(H, Hi);
+  for (int rw = 0; rw < N; ++rw)
+    for (int c = rw; c < N; ++c) a.Hr[(int64_t)tri(N, rw, c) * ld + i] = (R)(rho * Hi[rw][c]);
+}
+
+template <typename R>
+hipError_t launch_rescale(const Variant& v, const RescaleArgs<R>& a, hipStream_t st) {
+  const int bs = 128;
+  const dim3 grid((unsigned)((a.S + bs - 1) / bs)), block(bs);
+#define TOP_RESCALE_CASE(P_, S_, B_, V_)                                                  \
+  if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_) {             \
+    hipLaunchKernelGGL((rescale_kernel<R, P_, S_, B_, V_>), grid, block, 0, st, a);      \
+    return hipGetLastError();                                                           \
+  }
+#define TOP_RESCALE_PS(P_, S_)                                                            \
+  TOP_RESCALE_CASE(P_, S_, true, true)                                                    \
+  TOP_RESCALE_CASE(P_, S_, true, false)                                                   \
+  TOP_RESCALE_CASE(P_, S_, false, true)                                                   \
+  TOP_RESCALE_CASE(P_, S_, false, false)
+  TOP_RESCALE_PS(3, 3)
+  TOP_RESCALE_PS(3, 4)
+  TOP_RESCALE_PS(4, 4)
+  TOP_RESCALE_PS(4, 5)
+#undef TOP_RESCALE_PS
+#undef TOP_RESCALE_CASE
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_rescale<float>(const Variant&, const RescaleArgs<float>&, hipStream_t);
+template hipError_t launch_rescale<double>(const Variant&, const RescaleArgs<double>&, hipStream_t);
+
+__global__ void conv_report_kernel(const uint8_t* done, const int32_t* stop_at, const double* rho, int B,
+                                   int32_t iters_done, int32_t* iters_out, double* rho_out, uint8_t* done_out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  const bool d = done != nullptr && done[b] != 0;
+  if (iters_out != nullptr) iters_out[b] = d ? stop_at[b] : iters_done;
+  if (rho_out != nullptr) rho_out[b] = rho[b];
+  if (done_out != nullptr) done_out[b] = d ? 1 : 0;
+}
+
+hipError_t launch_conv_report(const uint8_t* done, const int32_t* stop_at, const double* rho, int B,
+                              int32_t iters_done, int32_t* iters_out, double* rho_out, uint8_t* done_out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(conv_report_kernel, dim3((B + 255) / 256), dim3(256), 0, st, done, stop_at, rho, B,
+                     iters_done, iters_out, rho_out, done_out);
+  return hipGetLastError();
+}
+
+}  // namespace top

@@ -318,7 +318,12 @@ struct top_problem {
   double *wp64 = nullptr, *lo64 = nullptr, *hi64 = nullptr, *vmax64 = nullptr, *bc64 = nullptr;
   void *blk = nullptr, *adjb[2] = {nullptr, nullptr}, *acc_iT = nullptr, *acc_hd = nullptr, *acc_z0 = nullptr;
   double *dPL = nullptr, *dPR = nullptr, *dK = nullptr, *dK0 = nullptr;
-  std::map<std::tuple<int, int>, hipGraphExec_t> graphs;
+  // residual checks: per-trajectory stop flag, sweep counters, current rho and the last change
+  uint8_t* done_dev = nullptr;
+  int32_t *swept = nullptr, *stop_at = nullptr;
+  double *rho_traj = nullptr, *ratio = nullptr;
+  // launch sequences replayed as graphs, keyed by (sweeps, start buffer, sweep index mod check_every)
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
   std::vector<hipGraph_t> graph_defs;
 
   template <typename T>
@@ -357,6 +362,7 @@ struct top_problem {
     a.fixpos = opt.fix_interior;
     a.c_out = (R*)cbuf;
     a.zold_out = (R*)zold;
+    a.done = opt.check_every > 0 ? done_dev : nullptr;
     return a;
   }
 
@@ -517,7 +523,57 @@ struct top_problem {
     int n = remaining;
     if (plan_ref().halo > 0) n = std::min(n, plan_ref().halo);
     if (tape != nullptr) n = std::min(n, opt.checkpoint_every - (done % opt.checkpoint_every));
+    if (opt.check_every > 0) n = std::min(n, opt.check_every - (done % opt.check_every));
     return n;
+  }
+
+  // Residuals of the sweep that just wrote buffer `c`, the stopping test and the penalty update.
+  top_status run_check(int c, hipStream_t st) {
+    const int save = cur;
+    cur = c;
+    top_status s = finalize(nullptr, true, true, st);
+    cur = save;
+    if (s != TOP_OK) return s;
+    hipError_t e = top::launch_reduce(part, S, off_dev, B, out, st);
+    if (e != hipSuccess) return fail(TOP_E_HIP, "reduce launch failed: %s", hipGetErrorString(e));
+    top::CheckArgs ca{};
+    ca.res = out;
+    ca.off = off_dev;
+    ca.B = B;
+    ca.check_every = opt.check_every;
+    ca.adapt = opt.adapt_rho;
+    ca.tol = opt.tol;
+    ca.mu = opt.mu;
+    ca.tau_incr = opt.tau_incr;
+    ca.tau_decr = opt.tau_decr;
+    ca.done = done_dev;
+    ca.swept = swept;
+    ca.stop_at = stop_at;
+    ca.rho = rho_traj;
+    ca.ratio = ratio;
+    if ((e = top::launch_check(ca, st)) != hipSuccess)
+      return fail(TOP_E_HIP, "check launch failed: %s", hipGetErrorString(e));
+    if (!opt.adapt_rho) return TOP_OK;
+    e = v.prec == 0 ? rescale_t<float>(c, st) : rescale_t<double>(c, st);
+    if (e != hipSuccess) return fail(TOP_E_HIP, "rescale launch failed: %s", hipGetErrorString(e));
+    return TOP_OK;
+  }
+
+  template <typename R>
+  hipError_t rescale_t(int c, hipStream_t st) {
+    top::RescaleArgs<R> ra{};
+    ra.state = (R*)state[c];
+    ra.Hr = (R*)Hr;
+    ra.rho_seg = rho_seg;
+    ra.ratio = ratio;
+    ra.rho = rho_traj;
+    ra.T = Tdev;
+    ra.flags = flags;
+    ra.traj = traj;
+    ra.vmax = (const R*)vmax;
+    ra.S = S;
+    ra.ld = ld;
+    return top::launch_rescale<R>(v, ra, st);
   }
 
   // The launch sequence of k sweeps starting from buffer `c0` and sweep index `done0`.
@@ -526,14 +582,18 @@ struct top_problem {
     int remaining = k, c = c0, done = done0;
     const size_t sbytes = (size_t)nf * ld * rsz;
     if (ev0 != nullptr) TOP_HIP(hipEventRecord(ev0, st));
+    bool checked_last = false;
     while (remaining > 0) {
       const int n = chunk(remaining, done);
-      const bool fin = (n == remaining);
+      const bool check = opt.check_every > 0 && (done + n) % opt.check_every == 0;
+      const bool fin = (n == remaining) || check;
       top_status s = sweep_launch(plan_ref(), lanes(), state[c], state[c ^ 1], n, fin, st);
       if (s != TOP_OK) return s;
       c ^= 1;
       remaining -= n;
       done += n;
+      checked_last = check;
+      if (check && (s = run_check(c, st)) != TOP_OK) return s;
       if (tape != nullptr && done % opt.checkpoint_every == 0) {
         const int slot = done / opt.checkpoint_every;
         if (slot < tape_slots)
@@ -542,7 +602,9 @@ struct top_problem {
       }
     }
     if (ev1 != nullptr) TOP_HIP(hipEventRecord(ev1, st));
-    // residual and cost partials of the last sweep, reduced per trajectory
+    // residual and cost partials of the last sweep, reduced per trajectory (a check just did that,
+    // before any change of rho)
+    if (checked_last) return TOP_OK;
     const int save = cur;
     cur = c;
     top_status s = finalize(nullptr, true, true, st);
@@ -569,6 +631,12 @@ void top_default_options(top_options* opt) {
   opt->tile_lanes = 0;
   opt->halo = 0;
   opt->use_graph = 1;
+  opt->check_every = 0;
+  opt->adapt_rho = 0;
+  opt->tol = 0.05;
+  opt->mu = 10.0;
+  opt->tau_incr = 1.1;
+  opt->tau_decr = 1.1;
 }
 
 const char* top_last_error(void) { return g_err.c_str(); }
@@ -618,6 +686,15 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
     return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, %d] (got %d)", max_tile(v, taped),
                 opt.tile_lanes);
   if (opt.halo < 0) return fail(TOP_E_INVALID, "halo must be >= 0");
+  if (opt.check_every < 0) return fail(TOP_E_INVALID, "check_every must be >= 0 (got %d)", opt.check_every);
+  if (opt.check_every > 0) {
+    if (taped) return fail(TOP_E_UNSUPPORTED, "residual checks cannot be combined with a tape");
+    if (opt.adapt_rho != 0 && opt.adapt_rho != 1) return fail(TOP_E_INVALID, "adapt_rho must be 0 or 1");
+    if (!std::isfinite(opt.tol)) return fail(TOP_E_INVALID, "tol must be finite");
+    if (opt.adapt_rho && !(opt.mu > 1.0 && opt.tau_incr > 1.0 && opt.tau_decr > 1.0 && std::isfinite(opt.mu) &&
+                           std::isfinite(opt.tau_incr) && std::isfinite(opt.tau_decr)))
+      return fail(TOP_E_INVALID, "mu, tau_incr and tau_decr must be finite and > 1");
+  }
 
   top_problem* h = new (std::nothrow) top_problem();
   if (h == nullptr) return fail(TOP_E_NOMEM, "host allocation failed");
@@ -661,6 +738,21 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
   if ((st = h->alloc(&h->out, 3 * (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->off_dev, (size_t)(n_traj + 1) * sizeof(int64_t))) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->flag_dev, 2 * sizeof(int))) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->rho_traj, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
+  if (opt.check_every > 0) {
+    if ((st = h->alloc(&h->done_dev, (size_t)n_traj)) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->swept, (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->stop_at, (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->ratio, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
+    hipError_t e = hipMemsetAsync(h->done_dev, 0, (size_t)n_traj, stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->swept, 0, (size_t)n_traj * sizeof(int32_t), stream);
+    if (e == hipSuccess) e = hipMemsetAsync(h->stop_at, 0xff, (size_t)n_traj * sizeof(int32_t), stream);
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "check state reset failed: %s", hipGetErrorString(e)));
+  }
+  {
+    hipError_t e = hipMemcpyAsync(h->rho_traj, rho, (size_t)n_traj * sizeof(double), hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "rho copy failed: %s", hipGetErrorString(e)));
+  }
   if (opt.checkpoint_every > 0) {
     h->tape_slots = opt.max_taped_iters / opt.checkpoint_every + 1;
     if ((st = h->alloc(&h->tape, (size_t)h->tape_slots * h->nf * ld * R)) != TOP_OK) return bail(st);
@@ -775,7 +867,7 @@ top_status top_iterate(top_problem* h, int32_t k) {
     top_status s = h->enqueue(k, h->cur, h->iters_done, h->stream);
     if (s != TOP_OK) return s;
   } else {
-    auto key = std::make_tuple(k, h->cur);
+    auto key = std::make_tuple(k, h->cur, h->opt.check_every > 0 ? h->iters_done % h->opt.check_every : 0);
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
       if (h->cap_stream == nullptr) TOP_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
@@ -847,6 +939,14 @@ top_status top_backward(top_problem* h, const double* dcost, double* dwaypoints,
     return fail(TOP_E_STATE, "%d sweeps run but the tape holds %d", h->iters_done, h->opt.max_taped_iters);
   return h->v.prec == 0 ? h->backward_t<float>(dcost, dwaypoints, ddurations)
                         : h->backward_t<double>(dcost, dwaypoints, ddurations);
+}
+
+top_status top_convergence(const top_problem* h, int32_t* iters, double* rho, uint8_t* done) {
+  if (h == nullptr) return fail(TOP_E_INVALID, "handle is NULL");
+  hipError_t e = top::launch_conv_report(h->opt.check_every > 0 ? h->done_dev : nullptr, h->stop_at, h->rho_traj,
+                                         h->B, h->iters_done, iters, rho, done, h->stream);
+  if (e != hipSuccess) return fail(TOP_E_HIP, "convergence report failed: %s", hipGetErrorString(e));
+  return TOP_OK;
 }
 
 top_status top_sync_status(top_problem* h) {

@@ -115,6 +115,8 @@ struct SweepArgs {
   int final_out;            // write c~ and the end knot before its last update, at the last sweep
   R* c_out;                 // [3n][ld]
   R* zold_out;              // [3s][ld]
+  const uint8_t* done;      // [B] nonzero: the trajectory has stopped and its state is copied through;
+                            // or null
 };
 
 struct Variant {
@@ -181,6 +183,43 @@ hipError_t launch_reduce(const double* part, int64_t S, const int64_t* seg_off, 
                          hipStream_t st);
 
 hipError_t launch_copy_rows(const double* src, double* dst, int B, hipStream_t st);
+
+// ---- residual checks and the adaptive penalty (Sec. III-D.3)
+struct CheckArgs {
+  const double* res;      // [3][B] cost, ||r_p||, ||r_d|| of the sweep just finished
+  const int64_t* off;     // [B+1] segment offsets
+  int B;
+  int check_every;
+  int adapt;
+  double tol, mu, tau_incr, tau_decr;
+  uint8_t* done;          // [B] set once the stopping test passes
+  int32_t* swept;         // [B] sweeps counted at the checks while the trajectory runs
+  int32_t* stop_at;       // [B] sweeps applied when it stopped
+  double* rho;            // [B] current penalty
+  double* ratio;          // [B] rho_old / rho_new at this check, 1 when unchanged
+};
+hipError_t launch_check(const CheckArgs& a, hipStream_t st);
+
+template <typename R>
+struct RescaleArgs {
+  R* state;               // [nf][ld] current state, rescaled in place
+  R* Hr;                  // [nh][ld] rho * Htilde^-1, refactored in place
+  double* rho_seg;        // [S]
+  const double* ratio;    // [B]
+  const double* rho;      // [B]
+  const double* T;        // [S]
+  const uint8_t* flags;
+  const int32_t* traj;
+  const R* vmax;
+  int64_t S, ld;
+};
+template <typename R>
+hipError_t launch_rescale(const Variant& v, const RescaleArgs<R>& a, hipStream_t st);
+
+// top_convergence outputs; done/stop_at may be null (no checks), then every trajectory has all sweeps.
+hipError_t launch_conv_report(const uint8_t* done, const int32_t* stop_at, const double* rho, int B,
+                              int32_t iters_done, int32_t* iters_out, double* rho_out, uint8_t* done_out,
+                              hipStream_t st);
 
 // ---- reverse pass
 template <typename R>

@@ -10,6 +10,7 @@
 // y = min(0, A^o c^0 - b); the velocity split starts at Proj(A^v c^0) with a
 // zero dual, stored as g = Proj(A^v c^0).
 #include "common.h"
+#include "htilde.h"
 
 namespace top {
 
@@ -86,72 +87,14 @@ __global__ void setup_kernel(SetupArgs a, SetupOut<R> out) {
   iTp[0] = 1.0;
   for (int o = 1; o < 2 * N; ++o) iTp[o] = iTp[o - 1] * iT;
 
-  // ---- Htilde = 2 T^(1-2p) Q(1) + rho [boundary rows + box rows + velocity rows]
-  double H[N][N];
-  const double sq = 2.0 * iTp[2 * P - 1];
-#pragma unroll
-  for (int j = 0; j < N; ++j)
-#pragma unroll
-    for (int k = 0; k < N; ++k) H[j][k] = sq * cgram(P, j, k);
+  // ---- Htilde = 2 T^(1-2p) Q(1) + rho [boundary rows + box rows + velocity rows], inverted
+  double H[N][N], Hi[N][N];
+  build_htilde<P, S, BOX, VEL>(iTp, iT, rho, first, last, H);
+  spd_inverse<N>(H, Hi);
+  for (int r = 0; r < N; ++r)
+    for (int c = r; c < N; ++c) out.Hr[(int64_t)tri(N, r, c) * ld + i] = (R)(rho * Hi[r][c]);
   const int nL = first ? P : S;
   const int nR = last ? P : S;
-  for (int o = 0; o < nL; ++o) {
-    const double v = cfact(o) * iTp[o];
-    H[o][o] += rho * v * v;
-  }
-  for (int o = 0; o < nR; ++o) {
-#pragma unroll
-    for (int j = 0; j < N; ++j)
-#pragma unroll
-      for (int k = 0; k < N; ++k) H[j][k] += rho * (cfall(o, j) * iTp[o]) * (cfall(o, k) * iTp[o]);
-  }
-  if (BOX) {
-#pragma unroll
-    for (int s = 0; s < M; ++s)
-#pragma unroll
-      for (int j = 0; j < N; ++j)
-#pragma unroll
-        for (int k = 0; k < N; ++k) H[j][k] += rho * 2.0 * cpos(s, j) * cpos(s, k);
-  }
-  if (VEL) {
-#pragma unroll
-    for (int s = 0; s < M; ++s)
-#pragma unroll
-      for (int j = 0; j < N; ++j)
-#pragma unroll
-        for (int k = 0; k < N; ++k) H[j][k] += rho * iT * iT * cvel(s, j) * cvel(s, k);
-  }
-  // Cholesky H = L L^T (lower triangle of H overwritten by L)
-  for (int j = 0; j < N; ++j) {
-    double d = H[j][j];
-    for (int k = 0; k < j; ++k) d -= H[j][k] * H[j][k];
-    d = sqrt(d);
-    H[j][j] = d;
-    for (int r = j + 1; r < N; ++r) {
-      double v = H[r][j];
-      for (int k = 0; k < j; ++k) v -= H[r][k] * H[j][k];
-      H[r][j] = v / d;
-    }
-  }
-  // Linv = L^-1 (lower), then Hinv = Linv^T Linv
-  double Li[N][N];
-  for (int c = 0; c < N; ++c) {
-    for (int r = 0; r < N; ++r) {
-      if (r < c) { Li[r][c] = 0.0; continue; }
-      double v = (r == c) ? 1.0 : 0.0;
-      for (int k = c; k < r; ++k) v -= H[r][k] * Li[k][c];
-      Li[r][c] = v / H[r][r];
-    }
-  }
-  double Hi[N][N];
-  for (int r = 0; r < N; ++r) {
-    for (int c = r; c < N; ++c) {
-      double v = 0.0;
-      for (int k = c; k < N; ++k) v += Li[k][r] * Li[k][c];
-      Hi[r][c] = Hi[c][r] = v;
-      out.Hr[(int64_t)tri(N, r, c) * ld + i] = (R)(rho * v);
-    }
-  }
   if (out.Hd != nullptr) {
     // d(rho Htilde^-1)/dT = -rho Htilde^-1 (dHtilde/dT) Htilde^-1, with
     // dHtilde/dT = 2(1-2p) T^-2p Q(1) + rho [ -2o (o!)^2 T^(-2o-1) on left rows,

@@ -271,8 +271,17 @@ __global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
   }
 
   const int wl = lane & 63, wid = lane >> 6, nw = W >> 6;
-  // A wave with no segment only has to keep the workgroup's barrier count (one per sweep).
-  if (__ballot(active) == 0) {
+  // A stopped trajectory keeps its state: its lanes sweep along (their neighbours belong to the same
+  // trajectory, so nothing leaks) but store their input state and leave c~ and the old knot alone.
+  const bool frozen = active && A.done != nullptr && A.done[tr] != 0;
+  auto copy_through = [&]() {
+    constexpr int NF = F_G + (VEL ? 3 * M : 0);
+#pragma unroll 4
+    for (int f = 0; f < NF; ++f) A.st_out[f * ld + seg] = in[f * ld + seg];
+  };
+  // A wave with no live segment only has to keep the workgroup's barrier count (one per sweep).
+  if (__ballot(active && !frozen) == 0) {
+    if (core && frozen) copy_through();
     for (int it = 0; it < A.iters; ++it) __syncthreads();
     return;
   }
@@ -283,7 +292,7 @@ __global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
     sweep_once<false>(L, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
   if (A.final_out && A.iters > 0) {
     sweep_once<true>(L, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
-    if (core) {
+    if (core && !frozen) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -294,7 +303,8 @@ __global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
     }
   }
 
-  if (core) {
+  if (core && frozen) copy_through();
+  if (core && !frozen) {
     R* out = A.st_out;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
