@@ -177,15 +177,89 @@ def cpu_baseline(w, K, target_s=12.0):
 
 
 def calib_copy(nbytes=1 << 30):
-    """A plain device copy of known size, for scaling the HBM byte counters."""
+    """A copy kernel of known size (reads and writes nbytes each), for scaling the HBM byte counters."""
     import torch
     src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
     src.fill_(1.0)
     torch.cuda.synchronize()
-    dst.copy_(src)
+    torch.mul(src, 1.0, out=dst)          # an elementwise kernel, not a DMA copy, so the counters see it
     torch.cuda.synchronize()
     return nbytes
+
+
+# ---------------------------------------------------------------------------
+# HBM traffic of the sweep kernel from two rocprofv3 counter runs.
+# ---------------------------------------------------------------------------
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+COUNTERS_MD = os.path.join(ROOT, "profiles", "sweep_batched_B4096_counters.md")
+SWEEP_SOURCES = ["paper_2507_10290_amd/csrc/sweep_impl.h", "paper_2507_10290_amd/csrc/sweep_f32.hip",
+                 "paper_2507_10290_amd/csrc/common.h"]
+SWEEP_KERNEL = "sweep_kernel<float, 3, 3, true, true, 512>"
+CALIB_KERNEL = "mul"
+
+
+def sweep_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_rows(path, counter):
+    """(kernel name, value) per dispatch of one counter from a rocprofv3 counter_collection.csv."""
+    import csv
+    rows = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Counter_Name") == counter:
+                rows.append((r.get("Kernel_Name", ""), float(r["Counter_Value"])))
+    return rows
+
+
+def counters_summary(fetch_csv, write_csv, calib_bytes=1 << 30):
+    """Markdown summary of the sweep kernel's FETCH_SIZE / WRITE_SIZE (KiB per dispatch), scaled by
+    what the same counters read for the calibration copy kernel."""
+    out = {}
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _counter_rows(path, name)
+        sweep = [v for k, v in rows if "sweep_kernel" in k and "float, 3, 3, true, true" in k]
+        calib = [v for k, v in rows if CALIB_KERNEL in k.lower() and "elementwise" in k.lower()]
+        if not sweep or not calib:
+            raise SystemExit(f"{path}: no {name} rows for the sweep kernel or the calibration copy")
+        kib_cal = max(calib)                  # the 1 GiB copy is the largest elementwise mul dispatch
+        scale = calib_bytes / (kib_cal * 1024.0)
+        out[name] = {"kib_per_dispatch": float(np.median(sweep)), "dispatches": len(sweep),
+                     "calib_kib": kib_cal, "scale": scale,
+                     "bytes_per_launch": float(np.median(sweep)) * 1024.0 * scale}
+    total = out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"]
+    lines = ["# HBM traffic of the batched sweep kernel (rocprofv3 counters)", "",
+             f"Kernel: `{SWEEP_KERNEL}`, batched workload (4,096 trajectories, 1,049,917 segments, "
+             "K = 200 sweeps in one launch).", "",
+             "| counter | median KiB / dispatch | dispatches | calibration copy KiB (1 GiB read + 1 GiB written) "
+             "| scale | bytes / launch |", "|---|---|---|---|---|---|"]
+    for name in ("FETCH_SIZE", "WRITE_SIZE"):
+        o = out[name]
+        lines.append(f"| {name} | {o['kib_per_dispatch']:.0f} | {o['dispatches']} | {o['calib_kib']:.0f} | "
+                     f"{o['scale']:.4f} | {o['bytes_per_launch']:.4e} |")
+    lines += ["", f"traffic_bytes_per_launch = {total:.6e}",
+              f"sweep_source_digest = {sweep_source_digest()}", ""]
+    return "\n".join(lines)
+
+
+def stored_traffic():
+    """Bytes per launch from the committed counter summary, or None once the kernel sources changed."""
+    try:
+        txt = open(COUNTERS_MD).read()
+    except OSError:
+        return None
+    kv = dict(l.split(" = ", 1) for l in txt.splitlines() if " = " in l)
+    if kv.get("sweep_source_digest", "").strip() != sweep_source_digest():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def main():
@@ -196,7 +270,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps and the roofline")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter scale)")
+    ap.add_argument("--counters-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="print the markdown summary of two rocprofv3 counter runs and exit (no GPU)")
     a = ap.parse_args()
+    if a.counters_summary:
+        print(counters_summary(*a.counters_summary))
+        return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the batched sweep has no cross-GPU exchange "
               "(trajectories shard by count; see the design notes). Run with --gpus 1.", file=sys.stderr)
@@ -225,7 +304,7 @@ def main():
     achieved = fpu * w.n_seg * K / (kms * 1e-3)
     sweep_rate = w.n_seg * K / (kms * 1e-3)
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_FP32_NONPACKED / 1e12, 1),
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4), "traffic": stored_traffic(),
                 "kernel": "sweep_kernel<float,3,3,box,vel,512>", "flops_per_segment_update": fpu,
                 "launch_ms": round(per_launch_ms, 4), "launches_per_step": launches,
                 "frac_of_packed_fp32_peak": round(achieved / PEAK_FP32_PACKED, 4)}
