@@ -443,10 +443,19 @@ struct top_problem {
       // replay the block from its checkpoint, keeping the state before every sweep
       TOP_HIP(hipMemcpyAsync(blk, (char*)tape + (size_t)j * sl * sizeof(R), sl * sizeof(R),
                              hipMemcpyDeviceToDevice, stream));
-      for (int t = 1; t < n; ++t) {
-        s = sweep_launch(plan_ref(), lanes(), (R*)blk + (size_t)(t - 1) * sl, (R*)blk + (size_t)t * sl, 1, false,
-                         stream);
-        if (s != TOP_OK) return s;
+      // one recording launch per replay chunk (halo sweeps at most on split trajectories): the launch
+      // from slot t0 stores the states after its sweeps in slots t0+1 .. t0+cnt
+      for (int t0 = 0; t0 < n - 1;) {
+        const int cnt = plan_ref().halo > 0 ? std::min(n - 1 - t0, plan_ref().halo) : n - 1 - t0;
+        top::SweepArgs<R> a = sweep_args<R>(plan_ref(), lanes());
+        a.st_in = (const R*)blk + (size_t)t0 * sl;
+        a.st_out = (R*)blk + (size_t)(t0 + cnt) * sl;
+        a.iters = cnt;
+        a.final_out = 0;
+        a.rec = (R*)blk + (size_t)t0 * sl;
+        a.rec_slot = (int64_t)sl;
+        if ((s = chk(top::launch_sweep<R>(v, a, plan_ref().n_tiles, stream))) != TOP_OK) return s;
+        t0 += cnt;
       }
       int t_hi = n;
       while (t_hi > 0) {

@@ -117,6 +117,8 @@ struct SweepArgs {
   R* zold_out;              // [3s][ld]
   const uint8_t* done;      // [B] nonzero: the trajectory has stopped and its state is copied through;
                             // or null
+  R* rec;                   // recording launches (reverse-pass replay): the state after sweep i of the
+  int64_t rec_slot;         // launch, i < iters - 1, goes to rec + (i + 1) * rec_slot; else null
 };
 
 struct Variant {

@@ -194,7 +194,9 @@ __device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh
   }
 }
 
-template <typename R, int P, int S, bool BOX, bool VEL, int LB>
+// REC: the instance used to replay checkpoint blocks for the reverse pass; it also stores the state
+// after every sweep but the last (the ordinary instance never stores inside its sweep loop).
+template <typename R, int P, int S, bool BOX, bool VEL, int LB, bool REC = false>
 __global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
   using LT = Lane<R, P, S, BOX, VEL>;
   constexpr int N = LT::N;
@@ -285,27 +287,7 @@ __global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
     for (int it = 0; it < A.iters; ++it) __syncthreads();
     return;
   }
-  R cfin[3][N], zfin[3][S];
-  const int n_plain = A.final_out ? A.iters - 1 : A.iters;
-  int it = 0;
-  for (; it < n_plain; ++it)
-    sweep_once<false>(L, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
-  if (A.final_out && A.iters > 0) {
-    sweep_once<true>(L, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
-    if (core && !frozen) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-#pragma unroll
-        for (int j = 0; j < N; ++j) A.c_out[(a * N + j) * ld + seg] = cfin[a][j];
-#pragma unroll
-        for (int o = 0; o < S; ++o) A.zold_out[(a * S + o) * ld + seg] = zfin[a][o];
-      }
-    }
-  }
-
-  if (core && frozen) copy_through();
-  if (core && !frozen) {
-    R* out = A.st_out;
+  auto store_to = [&](R* out) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -327,18 +309,44 @@ __global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
         for (int s = 0; s < M; ++s) out[(F_G + a * M + s) * ld + seg] = L.g[a][s];
       }
     }
+  };
+  R cfin[3][N], zfin[3][S];
+  const int n_plain = A.final_out ? A.iters - 1 : A.iters;
+  int it = 0;
+  for (; it < n_plain; ++it) {
+    sweep_once<false>(L, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
+    if constexpr (REC) {
+      if (core && it + 1 < A.iters) store_to(A.rec + (int64_t)(it + 1) * A.rec_slot);
+    }
   }
+  if (A.final_out && A.iters > 0) {
+    sweep_once<true>(L, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
+    if (core && !frozen) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) A.c_out[(a * N + j) * ld + seg] = cfin[a][j];
+#pragma unroll
+        for (int o = 0; o < S; ++o) A.zold_out[(a * S + o) * ld + seg] = zfin[a][o];
+      }
+    }
+  }
+
+  if (core && frozen) copy_through();
+  if (core && !frozen) store_to(A.st_out);
 }
 
 // LB3 / LB4: largest tile (launch bound) for the quintic / septic kernels.
 template <typename R, int LB3, int LB4>
 hipError_t dispatch_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st) {
-  const int lb = (v.p == 3) ? LB3 : LB4;
+  const bool rec = a.rec != nullptr;
+  const int lb = rec ? 256 : (v.p == 3) ? LB3 : LB4;
   if (a.W <= 0 || a.W > lb || (a.W & 63) != 0 || n_tiles <= 0) return hipErrorInvalidValue;
   dim3 grid(n_tiles), block(a.W);
 #define TOP_SWEEP_CASE(P_, S_, B_, V_, LB_)                                                   \
   if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_) {                 \
-    hipLaunchKernelGGL((sweep_kernel<R, P_, S_, B_, V_, LB_>), grid, block, 0, st, a);       \
+    if (rec) hipLaunchKernelGGL((sweep_kernel<R, P_, S_, B_, V_, 256, true>), grid, block, 0, st, a); \
+    else hipLaunchKernelGGL((sweep_kernel<R, P_, S_, B_, V_, LB_>), grid, block, 0, st, a);  \
     return hipGetLastError();                                                               \
   }
 #define TOP_SWEEP_PS(P_, S_, LB_)                                                             \
