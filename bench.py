@@ -98,6 +98,30 @@ def sweep_kernel_ms(w, d, K, reps=3, precision="fp32"):
     return float(np.mean(ms)), launches, plan
 
 
+def adaptive_leg(w, d, K, fixed_sec, check_every=10, tol=0.05):
+    """Batched solve with residual checks every `check_every` sweeps, the stopping test and adaptive rho."""
+    import torch
+    res = {}
+
+    def step():
+        prob = _problem(w, d, precision="fp32", check_every=check_every, adapt_rho=True, tol=tol)
+        prob.iterate(K)
+        out = (prob.cost(), prob.residuals(), prob.coeffs())
+        res["conv"] = prob.convergence()
+        prob.close()
+        return out
+
+    sec = time_steps(step, 3, 1)
+    it, rho, done = (x.cpu().numpy() for x in res["conv"])
+    L = w.traj_lengths()
+    applied = float(np.sum(it.astype(np.float64) * L))
+    return {"check_every": check_every, "tol": tol, "ms_per_solve": round(sec * 1e3, 3),
+            "over_fixed_rho": round(sec / fixed_sec, 3), "stopped_fraction": round(float(done.mean()), 4),
+            "segment_sweeps_applied_fraction": round(applied / (w.n_seg * K), 4),
+            "rho_changed_fraction": round(float(np.mean(rho != w.rho)), 4),
+            "applied_segment_updates_per_s": round(applied / sec, 1)}
+
+
 def plain_rate(w, d_all, K, n_traj):
     """Plain form: one handle per trajectory, created, iterated without a graph and read back in turn."""
     import torch
@@ -345,6 +369,7 @@ def main():
         del d2
         w4 = make_config(4)
         extra["fwd_bwd"] = fwd_bwd(w4, _dev_inputs(w4, dev), w4.iters, 10)
+        extra["adaptive_rho"] = adaptive_leg(w, d, K, sec)
     line["extra"] = extra
     if a.calib_copy:
         extra["calib_copy_bytes"] = calib_copy()

@@ -59,7 +59,8 @@ def subproblem(pr: cadmm.Problem, b: int) -> cadmm.Problem:
         seg_offsets=np.array([0, n], dtype=np.int64), traj=torch.zeros(n, dtype=torch.long),
         first=pr.first[seg], last=pr.last[seg], knot_l=torch.arange(n), knot_r=torch.arange(n) + 1,
         P=pr.P[s0 + b:s1 + b + 1], T=pr.T[seg], lo=opt(pr.lo, seg), hi=opt(pr.hi, seg),
-        vmax=opt(pr.vmax, slice(b, b + 1)), rho=pr.rho[b:b + 1].clone(), bc=opt(pr.bc, slice(b, b + 1)))
+        vmax=opt(pr.vmax, slice(b, b + 1)), rho=pr.rho[b:b + 1].clone(), bc=opt(pr.bc, slice(b, b + 1)),
+        faces=opt(pr.faces, seg))
 
 
 def factor(pr: cadmm.Problem, mats: dict) -> torch.Tensor:

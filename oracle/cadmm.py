@@ -4,8 +4,10 @@ Sources (Sec. III of the paper):
 * consensus reformulation and the scaled-dual CADMM iteration: Sec. III-B,
   eqs. ``Consensus_problem``, ``Consensus_augmented_Lagrangian_problem``,
   ``Consensus_update``;
-* box corridor as linear inequalities with slack s and dual v:
-  Sec. III-C.1 (slack update) and the per-segment polytope of Sec. III-D.1;
+* corridor as linear inequalities with slack s and dual v: Sec. III-C.1
+  (slack update) and the per-segment polytope P_i^H of Sec. III-D.1, either
+  an axis-aligned box (lo, hi) or general half-spaces a_k . x <= b_k, each
+  imposed at the M sample instants (M K rows);
 * velocity ball as a quadratic inequality with split variable phi and dual w:
   Sec. III-C.2 (closed-form projection);
 * the per-segment closed-form update rules: Sec. III-D.1, eqs.
@@ -66,6 +68,7 @@ class Problem:
     vmax: Optional[torch.Tensor]   # [B]
     rho: torch.Tensor              # [B]
     bc: Optional[torch.Tensor]     # [B, 2, p, 3]
+    faces: Optional[torch.Tensor] = None   # [S, K, 4] polytope corridor a . x <= b (instead of lo/hi)
 
     @property
     def S(self) -> int:
@@ -104,7 +107,8 @@ def problem_from_workload(w, P=None, T=None, s: Optional[int] = None,
         fix_interior=bool(w.fix_interior if fix_interior is None else fix_interior),
         seg_offsets=offs, traj=torch.tensor(traj), first=torch.tensor(first),
         last=torch.tensor(last), knot_l=torch.tensor(knot_l), knot_r=torch.tensor(knot_l + 1),
-        P=P, T=T, lo=t(w.box_lo), hi=t(w.box_hi), vmax=t(w.vmax), rho=t(w.rho), bc=t(w.bc))
+        P=P, T=T, lo=t(w.box_lo), hi=t(w.box_hi), vmax=t(w.vmax), rho=t(w.rho), bc=t(w.bc),
+        faces=t(getattr(w, "faces", None)))
 
 
 # ---------------------------------------------------------------------------
@@ -146,6 +150,17 @@ def segment_matrices(pr: Problem) -> dict:
                 rhs.append(-pr.lo[:, a])
         out["Ao"] = torch.stack(rows, 1)          # [S, 2*M*3, 3n]
         out["b"] = torch.stack(rhs, 1)            # [S, 2*M*3]
+    if pr.faces is not None:
+        # P_i^H sampled at the M instants: one row a_k^T sigma_i(T_ij) <= b_k per (sample j, face k)
+        b0 = beta(0, ts, pr.d)                                        # [S, M, n]
+        rows, rhs = [], []
+        for j in range(M):
+            for k in range(pr.faces.shape[1]):
+                a = pr.faces[:, k, :3]                                # [S, 3]
+                rows.append(torch.cat([a[:, q:q + 1] * b0[:, j, :] for q in range(M_AXES)], 1))
+                rhs.append(pr.faces[:, k, 3])
+        out["Ao"] = torch.stack(rows, 1)          # [S, M*K, 3n]
+        out["b"] = torch.stack(rhs, 1)            # [S, M*K]
     if pr.vmax is not None:
         b1 = beta(1, ts, pr.d)                    # [S, M, n]
         out["Av"] = kron_axes(b1[:, :, None, :])  # [S, M, 3, 3n]

@@ -110,7 +110,8 @@ def optimality_reference(pr: Problem):
 
 
 def constrained_reference(pr: Problem, tol: float = 1e-15, maxiter: int = 2000):
-    """Box- and velocity-constrained optimum of one trajectory by scipy's SLSQP (tiny N only)."""
+    """Corridor- (box or polytope) and velocity-constrained optimum of one trajectory by scipy's SLSQP
+    (tiny N only)."""
     assert pr.B == 1
     n, d, S = pr.n, pr.d, pr.S
     Q = _np(cost_gram(pr.T, pr.p, pr.d))
@@ -151,6 +152,18 @@ def constrained_reference(pr: Problem, tol: float = 1e-15, maxiter: int = 2000):
                     l.append(lo[i, a])
                     u.append(hi[i, a])
         cons.append(scipy.optimize.LinearConstraint(np.array(A), np.array(l), np.array(u)))
+    if pr.faces is not None:
+        F = _np(pr.faces)
+        A, u = [], []
+        for i in range(S):
+            for j in range(pr.n_samples):
+                bj = _row(0, ts[i, j], d)
+                for k in range(F.shape[1]):
+                    r = np.zeros((S, 3, n))
+                    r[i] = F[i, k, :3, None] * bj[None, :]
+                    A.append(r.reshape(-1))
+                    u.append(F[i, k, 3])
+        cons.append(scipy.optimize.LinearConstraint(np.array(A), -np.inf, np.array(u)))
     if pr.vmax is not None:
         vm = float(_np(pr.vmax)[0])
         D = []

@@ -15,6 +15,11 @@ stand in for them with the same structure:
 * an axis-aligned box corridor per segment (the K = 6 half-space polytope of
   Sec. III-D), built around the segment's chord: per axis
   lo = min(P_{i-1}, P_i) - h, hi = max(P_{i-1}, P_i) + h, h ~ U[0.3, 1.0];
+* or, instead of the box, a general convex polytope per segment (the
+  H-representation P_i^H = {x : a_k . x <= b_k, k = 1..K} of Sec. III-D.1):
+  the six faces of a randomly rotated box around the chord plus K - 6 random
+  cuts, each offset h ~ U[0.3, 1.0] beyond the farther chord end, so both
+  waypoints lie strictly inside and consecutive polytopes overlap;
 * a velocity-norm bound v_max (the quadratic constraint of Sec. III-C.2);
 * a penalty rho per trajectory.
 
@@ -24,7 +29,9 @@ seg_offsets[b] + b .. seg_offsets[b+1] + b (N_b + 1 points).
 
 Draw order inside one trajectory (fixed, so every consumer sees the same
 numbers): step lengths (N), directions (N x 3 normals), independent durations
-(N, only when requested), box half-widths (N x 3, only when boxes are on).
+(N, only when requested), box half-widths (N x 3, only when boxes are on);
+for polytopes, per segment in order: a 3 x 3 normal matrix (rotation by QR),
+(K - 6) x 3 normals of the extra cuts, K offsets.
 """
 from __future__ import annotations
 
@@ -54,6 +61,7 @@ class Workload:
     precision: str = "fp64"         # iterate precision the workload is quoted in
     bc: Optional[np.ndarray] = None  # [B, 2, p, 3] end states, None = rest-to-rest
     notes: str = ""
+    faces: Optional[np.ndarray] = None  # [S, K, 4] polytope corridor a . x <= b (rows a_x, a_y, a_z, b)
 
     @property
     def n_traj(self) -> int:
@@ -69,7 +77,7 @@ class Workload:
     def subset(self, trajs: Sequence[int], name: Optional[str] = None) -> "Workload":
         """The same inputs restricted to the listed trajectories (in that order)."""
         offs = [0]
-        wp, du, lo, hi = [], [], [], []
+        wp, du, lo, hi, fc = [], [], [], [], []
         for b in trajs:
             s0, s1 = int(self.seg_offsets[b]), int(self.seg_offsets[b + 1])
             offs.append(offs[-1] + (s1 - s0))
@@ -78,6 +86,8 @@ class Workload:
             if self.box_lo is not None:
                 lo.append(self.box_lo[s0:s1])
                 hi.append(self.box_hi[s0:s1])
+            if self.faces is not None:
+                fc.append(self.faces[s0:s1])
         idx = np.asarray(list(trajs), dtype=np.int64)
         return Workload(
             name=name or f"{self.name}[subset]",
@@ -89,7 +99,8 @@ class Workload:
             box_hi=np.concatenate(hi, 0) if hi else None,
             vmax=None if self.vmax is None else self.vmax[idx].copy(),
             rho=self.rho[idx].copy(), iters=self.iters, precision=self.precision,
-            bc=None if self.bc is None else self.bc[idx].copy(), notes=self.notes)
+            bc=None if self.bc is None else self.bc[idx].copy(), notes=self.notes,
+            faces=np.concatenate(fc, 0) if fc else None)
 
     def window(self, traj: int, seg_lo: int, seg_hi: int, name: Optional[str] = None) -> "Workload":
         """Segments seg_lo..seg_hi-1 (local indices) of one trajectory as a trajectory of its own.
@@ -113,7 +124,8 @@ class Workload:
             box_hi=None if self.box_hi is None else self.box_hi[a:b].copy(),
             vmax=None if self.vmax is None else self.vmax[[traj]].copy(),
             rho=self.rho[[traj]].copy(), iters=self.iters, precision=self.precision,
-            bc=None, notes="light-cone window")
+            bc=None, notes="light-cone window",
+            faces=None if self.faces is None else self.faces[a:b].copy())
 
 
 def _unit_dirs(rng: np.random.Generator, n: int) -> np.ndarray:
@@ -141,18 +153,39 @@ def _one_walk(rng: np.random.Generator, n: int, step: Sequence[float],
     return P, T, lo, hi
 
 
+def _polytopes(rng: np.random.Generator, P: np.ndarray, K: int) -> np.ndarray:
+    """[N, K, 4] half-spaces around each chord P[i] -> P[i+1]: a rotated box plus K - 6 cuts."""
+    n = P.shape[0] - 1
+    out = np.zeros((n, K, 4))
+    for i in range(n):
+        Rm, _ = np.linalg.qr(rng.standard_normal((3, 3)))
+        normals = [Rm[:, a] for a in range(3)] + [-Rm[:, a] for a in range(3)]
+        normals += list(_unit_dirs(rng, K - 6))
+        h = rng.uniform(0.3, 1.0, K)
+        for k, a in enumerate(normals):
+            out[i, k, :3] = a
+            out[i, k, 3] = max(a @ P[i], a @ P[i + 1]) + h[k]
+    return out
+
+
 def random_walk_batch(name: str, lengths: Sequence[int], seeds: Sequence, *, order: int = 3,
                       n_cont: int = 0, n_samples: int = 8, step=(1.0, 3.0), dur=None,
                       speed: float = 2.0, box: bool = True, vmax: Optional[float] = 3.0,
                       rho=1.0, iters: int = 200, precision: str = "fp32",
-                      fix_interior: bool = True) -> Workload:
-    """A batch of independent random-walk trajectories, one seed per trajectory."""
+                      fix_interior: bool = True, faces: int = 0) -> Workload:
+    """A batch of independent random-walk trajectories, one seed per trajectory.
+
+    faces = K >= 6 replaces the box corridor by a K-face polytope per segment."""
     lengths = [int(n) for n in lengths]
     if any(n < 1 for n in lengths):
         raise ValueError("every trajectory needs at least one segment")
+    if faces and faces < 6:
+        raise ValueError("a polytope corridor needs at least 6 faces")
+    if faces:
+        box = False
     offs = np.zeros(len(lengths) + 1, dtype=np.int64)
     offs[1:] = np.cumsum(lengths)
-    wp, du, lo, hi = [], [], [], []
+    wp, du, lo, hi, fc = [], [], [], [], []
     for n, sd in zip(lengths, seeds):
         rng = np.random.Generator(np.random.PCG64(sd))
         P, T, l, h = _one_walk(rng, n, step, dur, speed, box)
@@ -161,6 +194,8 @@ def random_walk_batch(name: str, lengths: Sequence[int], seeds: Sequence, *, ord
         if box:
             lo.append(l)
             hi.append(h)
+        if faces:
+            fc.append(_polytopes(rng, P, faces))
     B = len(lengths)
     rho_arr = np.broadcast_to(np.asarray(rho, dtype=np.float64), (B,)).copy()
     return Workload(
@@ -170,7 +205,8 @@ def random_walk_batch(name: str, lengths: Sequence[int], seeds: Sequence, *, ord
         box_lo=np.concatenate(lo, 0) if box else None,
         box_hi=np.concatenate(hi, 0) if box else None,
         vmax=None if vmax is None else np.full(B, float(vmax)),
-        rho=rho_arr, iters=iters, precision=precision)
+        rho=rho_arr, iters=iters, precision=precision,
+        faces=np.concatenate(fc, 0) if faces else None)
 
 
 # ---------------------------------------------------------------------------
@@ -184,6 +220,7 @@ CONFIG_NAMES = {
     2: "single-N65536-septic-box-vel",
     3: "batched-B4096-quintic-box-vel",
     4: "grad-B256xN128-quintic-box-vel",
+    5: "batched-B4096-quintic-poly8-vel",
 }
 
 
@@ -220,6 +257,17 @@ def make_config(i: int, *, scale: Optional[float] = None, n_traj: Optional[int] 
         seeds = np.random.SeedSequence(4).spawn(256)[:B]
         return random_walk_batch(CONFIG_NAMES[4], [128] * B, seeds, order=3, rho=1.0,
                                  iters=100, precision="fp32")
+    if i == 5:
+        # the batched workload with 8-face polytope corridors instead of boxes (general corridor form)
+        parent = np.random.Generator(np.random.PCG64(3))
+        B = 4096
+        lengths = parent.integers(8, 512, size=B, endpoint=True)
+        rhos = parent.choice(np.array([0.5, 1.0, 2.0]), size=B)
+        seeds = np.random.SeedSequence(5).spawn(B)
+        if n_traj is not None:
+            lengths, rhos, seeds = lengths[:n_traj], rhos[:n_traj], seeds[:n_traj]
+        return random_walk_batch(CONFIG_NAMES[5], lengths, seeds, order=3, rho=rhos, iters=200,
+                                 precision="fp32", faces=8)
     raise ValueError(f"no workload {i}")
 
 
