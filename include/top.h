@@ -121,6 +121,19 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
                       const double* box_hi, const double* vmax, const double* rho,
                       const top_options* opt, hipStream_t stream, top_problem** out);
 
+/* top_create with a general convex polytope corridor per segment instead of a box: the
+ * H-representation P_i^H = {x : a_k . x <= b_k} of Sec. III-D.1, imposed at the M samples
+ * (M * n_faces rows per segment, eq. linear_inequality).
+ *   n_faces  K in [1, 8] faces per segment (segments with fewer faces pad with a = 0, b = 1)
+ *   faces    [dev] float64 [S][K][4]: a_x, a_y, a_z, b of each face, finite
+ * The other arguments are those of top_create.  The axes are coupled through sum_k a_k a_k^T; the
+ * library solves per segment in the frame of its eigenvectors.  Not available with a tape
+ * (checkpoint_every > 0): TOP_E_UNSUPPORTED. */
+top_status top_create_polytope(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
+                               const double* durations, const double* bc, int32_t n_faces, const double* faces,
+                               const double* vmax, const double* rho, const top_options* opt,
+                               hipStream_t stream, top_problem** out);
+
 /* Queue k >= 0 more sweeps (Algorithm 1 loop body: ClosedFormSolve, UpdateConsensus,
  * UpdateResidual, ProjectNonNeg, UpdateDual, and UpdateRho at the checks when check_every > 0).
  * Trajectories that passed the stopping test are left unchanged.  Asynchronous. */

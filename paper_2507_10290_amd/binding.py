@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "TOP_OK", -1: "TOP_E_INVALID", -3: "TOP_E_HIP", -4: "TOP_E_ST
                 -5: "TOP_E_NONFINITE", -6: "TOP_E_UNSUPPORTED", -7: "TOP_E_NOMEM"}
 
 # Every entry point declared in include/top.h.
-EXPORTED = ["top_default_options", "top_create", "top_iterate", "top_time_sweeps", "top_residuals", "top_cost",
+EXPORTED = ["top_default_options", "top_create", "top_create_polytope", "top_iterate", "top_time_sweeps", "top_residuals", "top_cost",
             "top_coeffs", "top_backward", "top_tune", "top_convergence", "top_sync_status", "top_get_plan",
             "top_destroy", "top_last_error"]
 
@@ -73,6 +73,9 @@ def lib() -> ctypes.CDLL:
     L.top_create.argtypes = [i32, i64p, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(TopOptions), vp,
                              ctypes.POINTER(vp)]
     L.top_create.restype = ctypes.c_int
+    L.top_create_polytope.argtypes = [i32, i64p, dp, dp, dp, i32, dp, dp, dp, ctypes.POINTER(TopOptions), vp,
+                                      ctypes.POINTER(vp)]
+    L.top_create_polytope.restype = ctypes.c_int
     L.top_iterate.argtypes = [vp, i32]
     L.top_iterate.restype = ctypes.c_int
     L.top_time_sweeps.argtypes = [vp, i32, ctypes.POINTER(ctypes.c_float)]
@@ -143,6 +146,19 @@ def top_create(seg_offsets: Sequence[int], waypoints, durations, rho, *, bc=None
     return h.value
 
 
+def top_create_polytope(seg_offsets: Sequence[int], waypoints, durations, rho, faces, *, bc=None, vmax=None,
+                        options: Optional[TopOptions] = None, stream: int = 0) -> int:
+    """Like top_create with a polytope corridor: faces is a float64 device tensor [S, K, 4] (a, b)."""
+    offs = np.ascontiguousarray(np.asarray(seg_offsets, dtype=np.int64))
+    h = ctypes.c_void_p()
+    st = lib().top_create_polytope(int(offs.shape[0] - 1), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                   _ptr(waypoints), _ptr(durations), _ptr(bc), int(faces.shape[1]), _ptr(faces),
+                                   _ptr(vmax), _ptr(rho), None if options is None else ctypes.byref(options),
+                                   ctypes.c_void_p(stream), ctypes.byref(h))
+    _check(st)
+    return h.value
+
+
 def top_iterate(h: int, k: int) -> None:
     _check(lib().top_iterate(ctypes.c_void_p(h), int(k)))
 
@@ -199,7 +215,7 @@ class TopProblem:
     """A batch of trajectories on one GPU, owned by one library handle."""
 
     def __init__(self, seg_offsets, waypoints, durations, rho, *, order: int = 3, n_cont: int = 0,
-                 bc=None, box_lo=None, box_hi=None, vmax=None, precision: str = "fp32",
+                 bc=None, box_lo=None, box_hi=None, faces=None, vmax=None, precision: str = "fp32",
                  fix_interior: bool = True, checkpoint_every: int = 0, max_taped_iters: int = 0,
                  tile_lanes: int = 0, halo: int = 0, use_graph: bool = True, check_every: int = 0,
                  adapt_rho: bool = False, tol: float = 0.05, mu: float = 10.0, tau_incr: float = 1.1,
@@ -226,15 +242,21 @@ class TopProblem:
         o.tol, o.mu, o.tau_incr, o.tau_decr = float(tol), float(mu), float(tau_incr), float(tau_decr)
         self.options = o
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        args = [_dev(x, self.device) for x in (waypoints, durations, rho, bc, box_lo, box_hi, vmax)]
-        self.h = top_create(self.seg_offsets, args[0], args[1], args[2], bc=args[3], box_lo=args[4],
-                            box_hi=args[5], vmax=args[6], options=o, stream=self.stream.cuda_stream)
+        args = [_dev(x, self.device) for x in (waypoints, durations, rho, bc, box_lo, box_hi, vmax, faces)]
+        if faces is not None:
+            if box_lo is not None or box_hi is not None:
+                raise ValueError("give a box corridor or polytope faces, not both")
+            self.h = top_create_polytope(self.seg_offsets, args[0], args[1], args[2], args[7], bc=args[3],
+                                         vmax=args[6], options=o, stream=self.stream.cuda_stream)
+        else:
+            self.h = top_create(self.seg_offsets, args[0], args[1], args[2], bc=args[3], box_lo=args[4],
+                                box_hi=args[5], vmax=args[6], options=o, stream=self.stream.cuda_stream)
 
     @classmethod
     def from_workload(cls, w, **kw):
         kw.setdefault("precision", w.precision)
         return cls(w.seg_offsets, w.waypoints, w.durations, w.rho, order=w.order, n_cont=w.n_cont,
-                   bc=w.bc, box_lo=w.box_lo, box_hi=w.box_hi, vmax=w.vmax,
+                   bc=w.bc, box_lo=w.box_lo, box_hi=w.box_hi, faces=getattr(w, "faces", None), vmax=w.vmax,
                    fix_interior=w.fix_interior, **kw)
 
     def _empty(self, *shape):

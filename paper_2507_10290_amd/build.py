@@ -18,9 +18,11 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtop.so")
 
-SOURCES = ["sweep_f32.hip", "sweep_f64.hip", "adjoint_f32.hip", "adjoint_f64.hip", "setup.hip",
+SOURCES = ["sweep_f32.hip", "sweep_f64.hip", "poly_f32.hip", "poly_f64.hip", "adjoint_f32.hip", "adjoint_f64.hip",
+           "setup.hip",
            "finalize.hip", "grad.hip", "adapt.hip", "api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+SCRATCH_LIMIT = 8192   # kScratchLimit of csrc/common.h
 # Packed FP32 VALU forms are kept out of the generated code.
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
@@ -68,6 +70,11 @@ def build(jobs: int = 0, verbose: bool = False) -> str:
             f.write(" ".join(f"{a}={b}" for a, b in k.items()) + "\n")
     if dyn:
         raise RuntimeError("kernels with a dynamic stack: " + ", ".join(dyn))
+    # The library raises the runtime's per-lane stack limit to kScratchLimit (common.h) and relies
+    # on every kernel's fixed scratch fitting under it.
+    big = [k["name"] for k in kernels if int(k.get("ScratchSize [bytes/lane]", "0")) > SCRATCH_LIMIT]
+    if big:
+        raise RuntimeError(f"kernels with more than {SCRATCH_LIMIT} bytes of scratch per lane: " + ", ".join(big))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

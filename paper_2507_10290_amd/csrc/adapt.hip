@@ -7,11 +7,11 @@
 // rho.  rescale_kernel applies a change of rho to the folded state and to the
 // per-segment solve matrix:
 //   * scaled consensus duals: u <- r u with r = rho_old / rho_new;
-//   * box pairs: y stands for the slack max(0, -y) and the scaled dual max(0, y),
+//   * corridor pairs (box rows or polytope faces): y stands for the slack max(0, -y) and the scaled dual max(0, y),
 //     so only a positive y is scaled;
 //   * velocity: g stands for the split value Proj(g) and the scaled dual
 //     g - Proj(g), so g <- Proj(g) + r (g - Proj(g));
-//   * rho * Htilde^-1 is rebuilt in float64 at the new rho.
+//   * rho * Htilde^-1 (for a polytope, one per rotated axis) is rebuilt in float64 at the new rho.
 #include "common.h"
 #include "htilde.h"
 #include "sweep_impl.h"
@@ -48,13 +48,14 @@ hipError_t launch_check(const CheckArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename R, int P, int S, bool BOX, bool VEL>
+// KF = kFaces: polytope corridor (one y per face and sample, one matrix per rotated axis).
+template <typename R, int P, int S, bool BOX, bool VEL, int KF = 0>
 __global__ void rescale_kernel(RescaleArgs<R> a) {
   constexpr int N = 2 * P;
   constexpr int M = kSamples;
   constexpr int F_UL = 3 * S, F_YH = 9 * S;
-  constexpr int F_YL = F_YH + (BOX ? 3 * M : 0);
-  constexpr int F_G = 9 * S + (BOX ? 6 * M : 0);
+  constexpr int NY = BOX ? 6 * M : KF * M;   // corridor pairs
+  constexpr int F_G = 9 * S + NY;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.S) return;
   const int b = a.traj[i];
@@ -64,8 +65,8 @@ __global__ void rescale_kernel(RescaleArgs<R> a) {
   R* st = a.state;
   const R rr = (R)r;
   for (int f = F_UL; f < F_UL + 6 * S; ++f) st[f * ld + i] *= rr;
-  if (BOX) {
-    for (int f = F_YH; f < F_YL + 3 * M; ++f) {
+  if (NY > 0) {
+    for (int f = F_YH; f < F_YH + NY; ++f) {
       const R y = st[f * ld + i];
       if (y > R(0)) st[f * ld + i] = rr * y;
     }
@@ -92,16 +93,34 @@ __global__ void rescale_kernel(RescaleArgs<R> a) {
   iTp[0] = 1.0;
   for (int o = 1; o < 2 * N; ++o) iTp[o] = iTp[o - 1] * iT;
   double H[N][N], Hi[N][N];
-  build_htilde<P, S, BOX, VEL>(iTp, iT, rho, (fl & kFirst) != 0, (fl & kLast) != 0, H);
-  spd_inverse<N>(H, Hi);
-  for (int rw = 0; rw < N; ++rw)
-    for (int c = rw; c < N; ++c) a.Hr[(int64_t)tri(N, rw, c) * ld + i] = (R)(rho * Hi[rw][c]);
+  constexpr int NH = N * (N + 1) / 2;
+  for (int ax = 0; ax < (KF > 0 ? 3 : 1); ++ax) {
+    const double wpos = KF > 0 ? a.lam[ax * ld + i] : (BOX ? 2.0 : 0.0);
+    build_htilde<P, S, VEL>(iTp, iT, rho, (fl & kFirst) != 0, (fl & kLast) != 0, wpos, H);
+    spd_inverse<N>(H, Hi);
+    for (int rw = 0; rw < N; ++rw)
+      for (int c = rw; c < N; ++c) a.Hr[(int64_t)(ax * NH + tri(N, rw, c)) * ld + i] = (R)(rho * Hi[rw][c]);
+  }
 }
 
 template <typename R>
 hipError_t launch_rescale(const Variant& v, const RescaleArgs<R>& a, hipStream_t st) {
   const int bs = 128;
   const dim3 grid((unsigned)((a.S + bs - 1) / bs)), block(bs);
+  if (v.faces != 0) {
+    if (v.faces != kFaces || v.box || a.lam == nullptr) return hipErrorInvalidValue;
+#define TOP_RESCALE_POLY(P_, S_, V_)                                                        \
+    if (v.p == P_ && v.s == S_ && (v.vel != 0) == V_) {                                     \
+      hipLaunchKernelGGL((rescale_kernel<R, P_, S_, false, V_, kFaces>), grid, block, 0, st, a); \
+      return hipGetLastError();                                                             \
+    }
+    TOP_RESCALE_POLY(3, 3, true) TOP_RESCALE_POLY(3, 3, false)
+    TOP_RESCALE_POLY(3, 4, true) TOP_RESCALE_POLY(3, 4, false)
+    TOP_RESCALE_POLY(4, 4, true) TOP_RESCALE_POLY(4, 4, false)
+    TOP_RESCALE_POLY(4, 5, true) TOP_RESCALE_POLY(4, 5, false)
+#undef TOP_RESCALE_POLY
+    return hipErrorInvalidValue;
+  }
 #define TOP_RESCALE_CASE(P_, S_, B_, V_)                                                  \
   if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_) {             \
     hipLaunchKernelGGL((rescale_kernel<R, P_, S_, B_, V_>), grid, block, 0, st, a);      \

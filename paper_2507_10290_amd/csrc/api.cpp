@@ -41,7 +41,7 @@ top_status fail(top_status s, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(TOP_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
-int max_tile(const top::Variant& v) { return v.prec == 0 ? (v.p == 3 ? 512 : 256) : 256; }
+int max_tile(const top::Variant& v) { return (v.prec == 0 && v.p == 3 && v.faces == 0) ? 512 : 256; }
 // Handles that keep a tape also run the adjoint kernel on the same tiles: it is built for tiles of up
 // to 256 lanes, and its per-lane LDS column (box and velocity pair adjoints) must fit the device's
 // per-workgroup LDS.
@@ -295,6 +295,8 @@ struct top_problem {
   std::vector<Block> allocs;
   // device buffers
   void *Hr = nullptr, *iT = nullptr, *lo = nullptr, *hi = nullptr, *vmax = nullptr, *bcL = nullptr;
+  void *Urot = nullptr, *fa = nullptr;  // polytope corridor: rotation and faces
+  double* lam = nullptr;                // polytope corridor: eigenvalues of sum_k a_k a_k^T
   void* state[2] = {nullptr, nullptr};
   void *cbuf = nullptr, *zold = nullptr, *scratch = nullptr;
   uint8_t* flags = nullptr;
@@ -356,6 +358,8 @@ struct top_problem {
     a.k.flags = flags;
     a.k.traj = traj;
     a.k.bcL = (const R*)bcL;
+    a.k.U = (const R*)Urot;
+    a.k.fa = (const R*)fa;
     a.k.ld = ld;
     a.lane_seg = lane_map;
     a.W = pl.W;
@@ -374,7 +378,7 @@ struct top_problem {
     a.st_out = (R*)outp;
     a.iters = n;
     a.final_out = fin ? 1 : 0;
-    hipError_t e = top::launch_sweep<R>(v, a, pl.n_tiles, st);
+    hipError_t e = v.faces ? top::launch_poly_sweep<R>(v, a, pl.n_tiles, st) : top::launch_sweep<R>(v, a, pl.n_tiles, st);
     if (e != hipSuccess) return fail(TOP_E_HIP, "sweep launch failed: %s", hipGetErrorString(e));
     return TOP_OK;
   }
@@ -416,7 +420,7 @@ struct top_problem {
   top_status backward_t(const double* dcost, double* dP, double* dT) {
     const int K = iters_done, m = opt.checkpoint_every;
     const size_t sl = (size_t)nf * ld;
-    top::Layout L{v.p, v.s, v.box, v.vel};
+    top::Layout L{v.p, v.s, v.box, v.vel, v.faces};
     top_status s;
     if (blk == nullptr) {
       if ((s = alloc(&blk, (size_t)m * sl * sizeof(R))) != TOP_OK) return s;
@@ -571,6 +575,7 @@ struct top_problem {
   template <typename R>
   hipError_t rescale_t(int c, hipStream_t st) {
     top::RescaleArgs<R> ra{};
+    ra.lam = lam;
     ra.state = (R*)state[c];
     ra.Hr = (R*)Hr;
     ra.rho_seg = rho_seg;
@@ -659,10 +664,11 @@ void top_destroy(top_problem* h) {
   delete h;
 }
 
-top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
-                      const double* durations, const double* bc, const double* box_lo,
-                      const double* box_hi, const double* vmax, const double* rho,
-                      const top_options* opt_in, hipStream_t stream, top_problem** out) {
+static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
+                              const double* durations, const double* bc, const double* box_lo,
+                              const double* box_hi, int32_t n_faces, const double* faces, const double* vmax,
+                              const double* rho, const top_options* opt_in, hipStream_t stream,
+                              top_problem** out) {
   if (out == nullptr) return fail(TOP_E_INVALID, "out is NULL");
   *out = nullptr;
   top_options opt;
@@ -688,8 +694,10 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
   if (opt.fix_interior != 0 && opt.fix_interior != 1) return fail(TOP_E_INVALID, "fix_interior must be 0 or 1");
   if (opt.checkpoint_every < 0 || (opt.checkpoint_every > 0 && opt.max_taped_iters < 1))
     return fail(TOP_E_INVALID, "checkpoint_every >= 0, and max_taped_iters >= 1 when it is > 0");
-  top::Variant v{opt.precision == TOP_FP64 ? 1 : 0, opt.order, s, box_lo != nullptr, vmax != nullptr};
+  top::Variant v{opt.precision == TOP_FP64 ? 1 : 0, opt.order, s, box_lo != nullptr, vmax != nullptr,
+                 faces != nullptr ? top::kFaces : 0};
   const bool taped = opt.checkpoint_every > 0;
+  if (faces != nullptr && taped) return fail(TOP_E_UNSUPPORTED, "a polytope corridor cannot be combined with a tape");
   if (opt.tile_lanes != 0 &&
       (opt.tile_lanes < 64 || opt.tile_lanes > max_tile(v, taped) || opt.tile_lanes % 64 != 0))
     return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, %d] (got %d)", max_tile(v, taped),
@@ -707,12 +715,13 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
 
   top_problem* h = new (std::nothrow) top_problem();
   if (h == nullptr) return fail(TOP_E_NOMEM, "host allocation failed");
-  if (opt.checkpoint_every > 0 && opt.precision == TOP_FP64) {
-    // The float64 adjoint kernels keep a large spill area in per-lane scratch; make sure the
-    // runtime's per-thread stack limit is not below it.
+  {
+    // Several kernels keep spill areas or local arrays in per-lane scratch (up to a few KiB; the
+    // build refuses any kernel above top::kScratchLimit).  A kernel whose scratch exceeded the
+    // runtime's per-lane stack limit was seen to compute wrong values, so raise the limit first.
     size_t lim = 0;
-    if (hipDeviceGetLimit(&lim, hipLimitStackSize) == hipSuccess && lim < 16384)
-      (void)hipDeviceSetLimit(hipLimitStackSize, 16384);
+    if (hipDeviceGetLimit(&lim, hipLimitStackSize) == hipSuccess && lim < top::kScratchLimit)
+      (void)hipDeviceSetLimit(hipLimitStackSize, top::kScratchLimit);
   }
   h->opt = opt;
   h->opt.n_cont = s;
@@ -723,13 +732,18 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
   h->rsz = v.prec == 0 ? sizeof(float) : sizeof(double);
   h->off.assign(seg_offsets, seg_offsets + n_traj + 1);
   h->stream = stream;
-  top::Layout L{v.p, v.s, v.box, v.vel};
+  top::Layout L{v.p, v.s, v.box, v.vel, v.faces};
   h->nf = L.nf();
 
   auto bail = [&](top_status st) { top_destroy(h); return st; };
   const size_t R = h->rsz, ld = (size_t)h->ld;
   top_status st;
-  if ((st = h->alloc(&h->Hr, L.nh() * ld * R)) != TOP_OK) return bail(st);
+  if ((st = h->alloc(&h->Hr, L.nhr() * ld * R)) != TOP_OK) return bail(st);
+  if (v.faces) {
+    if ((st = h->alloc(&h->Urot, 9 * ld * R)) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->fa, 4 * (size_t)top::kFaces * ld * R)) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->lam, 3 * ld * sizeof(double))) != TOP_OK) return bail(st);
+  }
   if ((st = h->alloc(&h->iT, ld * R)) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->lo, 3 * ld * R)) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->hi, 3 * ld * R)) != TOP_OK) return bail(st);
@@ -795,7 +809,8 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
     e = hipMemcpyAsync(h->flag_dev, zero2, sizeof zero2, hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "flag reset failed: %s", hipGetErrorString(e)));
   }
-  top::SetupArgs sa{waypoints, durations, bc, box_lo, box_hi, vmax, rho, h->off_dev, n_traj, S, opt.fix_interior};
+  top::SetupArgs sa{waypoints, durations, bc, box_lo, box_hi, faces, n_faces, vmax, rho, h->off_dev, n_traj, S,
+                    opt.fix_interior};
   {
     hipError_t e = top::launch_validate(sa, v.p, h->flag_dev, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "validation launch failed: %s", hipGetErrorString(e)));
@@ -811,6 +826,7 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
       if (bad[0] & 8) what += " rho (need finite > 0);";
       if (bad[0] & 16) what += " vmax (need finite > 0);";
       if (bad[0] & 32) what += " bc (need finite);";
+      if (bad[0] & 64) what += " faces (need finite);";
       return bail(fail(TOP_E_INVALID, "invalid input:%s", what.c_str()));
     }
   }
@@ -819,12 +835,13 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
     if (v.prec == 0) {
       top::SetupOut<float> o{(float*)h->Hr, (float*)h->iT, (float*)h->lo, (float*)h->hi, (float*)h->vmax,
                              h->flags, h->traj, (float*)h->bcL, (float*)h->state[0], (float*)h->cbuf,
-                             h->ld, h->Tdev, h->rho_seg, (float*)h->Hd};
+                             h->ld, h->Tdev, h->rho_seg, (float*)h->Hd, (float*)h->Urot, (float*)h->fa, h->lam};
       e = top::launch_setup<float>(v, sa, o, stream);
     } else {
       top::SetupOut<double> o{(double*)h->Hr, (double*)h->iT, (double*)h->lo, (double*)h->hi, (double*)h->vmax,
                               h->flags, h->traj, (double*)h->bcL, (double*)h->state[0], (double*)h->cbuf,
-                              h->ld, h->Tdev, h->rho_seg, (double*)h->Hd};
+                              h->ld, h->Tdev, h->rho_seg, (double*)h->Hd, (double*)h->Urot, (double*)h->fa,
+                              h->lam};
       e = top::launch_setup<double>(v, sa, o, stream);
     }
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "setup launch failed: %s", hipGetErrorString(e)));
@@ -861,6 +878,26 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
   if ((st = get_plan(h->off, W, halo, &h->pe)) != TOP_OK) return bail(st);
   *out = h;
   return TOP_OK;
+}
+
+top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
+                      const double* durations, const double* bc, const double* box_lo,
+                      const double* box_hi, const double* vmax, const double* rho,
+                      const top_options* opt, hipStream_t stream, top_problem** out) {
+  return create_impl(n_traj, seg_offsets, waypoints, durations, bc, box_lo, box_hi, 0, nullptr, vmax, rho, opt,
+                     stream, out);
+}
+
+top_status top_create_polytope(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
+                               const double* durations, const double* bc, int32_t n_faces, const double* faces,
+                               const double* vmax, const double* rho, const top_options* opt,
+                               hipStream_t stream, top_problem** out) {
+  if (out != nullptr) *out = nullptr;
+  if (faces == nullptr) return fail(TOP_E_INVALID, "faces is NULL");
+  if (n_faces < 1 || n_faces > top::kFaces)
+    return fail(TOP_E_UNSUPPORTED, "n_faces must be in [1, %d] (got %d)", top::kFaces, n_faces);
+  return create_impl(n_traj, seg_offsets, waypoints, durations, bc, nullptr, nullptr, n_faces, faces, vmax, rho, opt,
+                     stream, out);
 }
 
 top_status top_iterate(top_problem* h, int32_t k) {

@@ -28,8 +28,10 @@ __host__ __device__ __forceinline__ void static_for(F&& f) {
 }
 
 constexpr int kSamples = 8;      // M, constraint samples per segment
+constexpr int kFaces = 8;        // faces of a general polytope corridor (fewer are padded with inert faces)
 constexpr int kMaxWaves = 16;    // 1024-lane workgroups at most
 constexpr int32_t kHaloBit = 1 << 30;
+constexpr size_t kScratchLimit = 8192;  // per-lane stack limit the library sets; no kernel may exceed it
 constexpr int32_t kSegMask = kHaloBit - 1;
 
 enum : uint8_t { kFirst = 1, kLast = 2 };
@@ -75,9 +77,11 @@ __host__ __device__ constexpr int tri(int n, int i, int j) {
 
 // Field offsets of the per-segment iterate state (structure of arrays, one row of ld values per
 // field).  z holds the segment's end knot; its start knot is the previous segment's end knot, or
-// the trajectory's start state.  y packs each box slack/dual pair, g each velocity split/dual pair.
+// the trajectory's start state.  y packs each corridor slack/dual pair (box: upper and lower row
+// per axis and sample; polytope: one row per face and sample), g each velocity split/dual pair.
 struct Layout {
   int p, s, box, vel;
+  int faces = 0;             // kFaces for a polytope corridor, else 0
   __host__ __device__ int n() const { return 2 * p; }
   __host__ __device__ int nh() const { return n() * (n() + 1) / 2; }
   __host__ __device__ int zR() const { return 0; }
@@ -85,17 +89,21 @@ struct Layout {
   __host__ __device__ int uR() const { return 6 * s; }
   __host__ __device__ int yh() const { return 9 * s; }
   __host__ __device__ int yl() const { return 9 * s + (box ? 3 * kSamples : 0); }
-  __host__ __device__ int g() const { return 9 * s + (box ? 6 * kSamples : 0); }
+  __host__ __device__ int g() const { return 9 * s + (box ? 6 * kSamples : faces * kSamples); }
   __host__ __device__ int nf() const { return g() + (vel ? 3 * kSamples : 0); }
+  // rho * Htilde^-1 rows: one matrix, or one per rotated axis for a polytope
+  __host__ __device__ int nhr() const { return faces ? 3 * nh() : nh(); }
 };
 
 // Read-only per-segment constants, all [.][ld] structure of arrays in the iterate precision.
 template <typename R>
 struct SegConsts {
-  const R* Hr;          // [nh] packed rho * Htilde^-1 (symmetric)
+  const R* Hr;          // [nh] packed rho * Htilde^-1 (symmetric); polytope: [3][nh], one per rotated axis
   const R* iT;          // 1/T
   const R* lo;          // [3] corridor
   const R* hi;          // [3]
+  const R* U;           // polytope: [9] rotation to the axes of sum_k a_k a_k^T, U[3 q + a'] = U_{q a'}
+  const R* fa;          // polytope: [kFaces][4] faces a_x, a_y, a_z, b
   const R* vmax;        // velocity bound of the segment's trajectory
   const uint8_t* flags; // kFirst | kLast
   const int32_t* traj;  // trajectory of the segment
@@ -124,10 +132,14 @@ struct SweepArgs {
 struct Variant {
   int prec;  // 0 fp32, 1 fp64
   int p, s, box, vel;
+  int faces = 0;  // kFaces: general polytope corridor (box is then 0)
 };
 
 template <typename R>
 hipError_t launch_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
+// the same launch for a general polytope corridor (v.faces = kFaces)
+template <typename R>
+hipError_t launch_poly_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
 
 // One-time setup (precompute + Init), float64 arithmetic, output in R.
 struct SetupArgs {
@@ -136,6 +148,8 @@ struct SetupArgs {
   const double* bc;          // [B][2][p][3] or null
   const double* box_lo;      // [S][3] or null
   const double* box_hi;
+  const double* faces;       // [S][n_faces][4] polytope a_x, a_y, a_z, b, or null
+  int n_faces;
   const double* vmax;        // [B] or null
   const double* rho;         // [B]
   const int64_t* seg_off;    // [B+1] device copy
@@ -151,6 +165,9 @@ struct SetupOut {
   double* Tdev;              // [S] float64 copy of T (finalize)
   double* rho_seg;           // [S] float64 rho of the segment's trajectory (finalize)
   R* Hd;                     // [nh][ld] d(rho Htilde^-1)/dT, or null when no tape is kept
+  R* U;                      // polytope: [9][ld] rotation
+  R* fa;                     // polytope: [kFaces * 4][ld] faces (padded)
+  double* lam;               // polytope: [3][ld] eigenvalues of sum_k a_k a_k^T
 };
 
 template <typename R>
@@ -204,6 +221,7 @@ hipError_t launch_check(const CheckArgs& a, hipStream_t st);
 
 template <typename R>
 struct RescaleArgs {
+  const double* lam;      // polytope: [3][ld] eigenvalues of sum_k a_k a_k^T
   R* state;               // [nf][ld] current state, rescaled in place
   R* Hr;                  // [nh][ld] rho * Htilde^-1, refactored in place
   double* rho_seg;        // [S]

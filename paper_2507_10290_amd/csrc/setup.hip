@@ -27,6 +27,10 @@ __global__ void validate_kernel(SetupArgs a, int p, int* bad) {
       }
     }
   }
+  if (i < a.S && a.faces != nullptr) {
+    for (int q = 0; q < 4 * a.n_faces; ++q)
+      if (!isfinite(a.faces[i * 4 * a.n_faces + q])) flag |= 64;
+  }
   if (i < a.S + a.B) {
     for (int c = 0; c < 3; ++c)
       if (!isfinite(a.waypoints[i * 3 + c])) flag |= 4;
@@ -60,13 +64,14 @@ __device__ inline double end_state(const SetupArgs& a, int P, int b, int side, i
   return o == 0 ? a.waypoints[wp_row * 3 + c] : 0.0;
 }
 
-template <typename R, int P, int S, bool BOX, bool VEL>
+// KF = kFaces: general polytope corridor (BOX is then false).
+template <typename R, int P, int S, bool BOX, bool VEL, int KF = 0>
 __global__ void setup_kernel(SetupArgs a, SetupOut<R> out) {
   constexpr int N = 2 * P;
   constexpr int M = kSamples;
   constexpr int F_ZR = 0, F_UL = 3 * S, F_UR = 6 * S, F_YH = 9 * S;
   constexpr int F_YL = F_YH + (BOX ? 3 * M : 0);
-  constexpr int F_G = 9 * S + (BOX ? 6 * M : 0);
+  constexpr int F_G = 9 * S + (BOX ? 6 * M : KF * M);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.S) return;
   const int64_t ld = out.ld;
@@ -87,15 +92,40 @@ __global__ void setup_kernel(SetupArgs a, SetupOut<R> out) {
   iTp[0] = 1.0;
   for (int o = 1; o < 2 * N; ++o) iTp[o] = iTp[o - 1] * iT;
 
-  // ---- Htilde = 2 T^(1-2p) Q(1) + rho [boundary rows + box rows + velocity rows], inverted
+  // ---- Htilde = 2 T^(1-2p) Q(1) + rho [boundary rows + corridor rows + velocity rows], inverted
   double H[N][N], Hi[N][N];
-  build_htilde<P, S, BOX, VEL>(iTp, iT, rho, first, last, H);
-  spd_inverse<N>(H, Hi);
-  for (int r = 0; r < N; ++r)
-    for (int c = r; c < N; ++c) out.Hr[(int64_t)tri(N, r, c) * ld + i] = (R)(rho * Hi[r][c]);
+  if constexpr (KF > 0) {
+    // faces (padded with a = 0, b = 1, which never bind and add nothing), G = sum_k a_k a_k^T,
+    // G = U diag(lam) U^T, and one matrix per rotated axis
+    double G[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, Um[3][3], lam[3];
+    for (int k = 0; k < KF; ++k) {
+      double f[4] = {0.0, 0.0, 0.0, 1.0};
+      if (k < a.n_faces)
+        for (int q = 0; q < 4; ++q) f[q] = a.faces[(i * a.n_faces + k) * 4 + q];
+      for (int q = 0; q < 4; ++q) out.fa[(int64_t)(k * 4 + q) * ld + i] = (R)f[q];
+      for (int q = 0; q < 3; ++q)
+        for (int r = 0; r < 3; ++r) G[q][r] += f[q] * f[r];
+    }
+    sym3_eig(G, Um, lam);
+    constexpr int NH = N * (N + 1) / 2;
+    for (int ax = 0; ax < 3; ++ax) {
+      build_htilde<P, S, VEL>(iTp, iT, rho, first, last, lam[ax], H);
+      spd_inverse<N>(H, Hi);
+      for (int r = 0; r < N; ++r)
+        for (int c = r; c < N; ++c) out.Hr[(int64_t)(ax * NH + tri(N, r, c)) * ld + i] = (R)(rho * Hi[r][c]);
+      out.lam[ax * ld + i] = lam[ax];
+    }
+    for (int q = 0; q < 3; ++q)
+      for (int ax = 0; ax < 3; ++ax) out.U[(int64_t)(3 * q + ax) * ld + i] = (R)Um[q][ax];
+  } else {
+    build_htilde<P, S, VEL>(iTp, iT, rho, first, last, BOX ? 2.0 : 0.0, H);
+    spd_inverse<N>(H, Hi);
+    for (int r = 0; r < N; ++r)
+      for (int c = r; c < N; ++c) out.Hr[(int64_t)tri(N, r, c) * ld + i] = (R)(rho * Hi[r][c]);
+  }
   const int nL = first ? P : S;
   const int nR = last ? P : S;
-  if (out.Hd != nullptr) {
+  if (KF == 0 && out.Hd != nullptr) {
     // d(rho Htilde^-1)/dT = -rho Htilde^-1 (dHtilde/dT) Htilde^-1, with
     // dHtilde/dT = 2(1-2p) T^-2p Q(1) + rho [ -2o (o!)^2 T^(-2o-1) on left rows,
     //              -2o T^(-2o-1) f_o f_o^T on right rows, -2 T^-3 sum_s tau'_s tau'_s^T ]
@@ -177,6 +207,25 @@ __global__ void setup_kernel(SetupArgs a, SetupOut<R> out) {
       }
     }
   }
+  if constexpr (KF > 0) {
+    // y = min(0, a_k . p_s - b_k) at each sample position p_s of the chord polynomial
+#pragma unroll
+    for (int s = 0; s < M; ++s) {
+      double pv[3];
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) acc += cpos(s, j) * ct[c][j];
+        pv[c] = acc;
+      }
+      for (int k = 0; k < KF; ++k) {
+        double f[4] = {0.0, 0.0, 0.0, 1.0};
+        if (k < a.n_faces)
+          for (int q = 0; q < 4; ++q) f[q] = a.faces[(i * a.n_faces + k) * 4 + q];
+        st[(int64_t)(F_YH + k * M + s) * ld + i] = (R)fmin(0.0, f[0] * pv[0] + f[1] * pv[1] + f[2] * pv[2] - f[3]);
+      }
+    }
+  }
   if (VEL) {
 #pragma unroll
     for (int s = 0; s < M; ++s) {
@@ -198,6 +247,20 @@ template <typename R>
 hipError_t launch_setup(const Variant& v, const SetupArgs& a, const SetupOut<R>& o, hipStream_t st) {
   const int bs = 128;
   const dim3 grid((unsigned)((a.S + bs - 1) / bs)), block(bs);
+  if (v.faces != 0) {
+    if (v.faces != kFaces || v.box) return hipErrorInvalidValue;
+#define TOP_SETUP_POLY(P_, S_, V_)                                                        \
+    if (v.p == P_ && v.s == S_ && (v.vel != 0) == V_) {                                   \
+      hipLaunchKernelGGL((setup_kernel<R, P_, S_, false, V_, kFaces>), grid, block, 0, st, a, o); \
+      return hipGetLastError();                                                           \
+    }
+    TOP_SETUP_POLY(3, 3, true) TOP_SETUP_POLY(3, 3, false)
+    TOP_SETUP_POLY(3, 4, true) TOP_SETUP_POLY(3, 4, false)
+    TOP_SETUP_POLY(4, 4, true) TOP_SETUP_POLY(4, 4, false)
+    TOP_SETUP_POLY(4, 5, true) TOP_SETUP_POLY(4, 5, false)
+#undef TOP_SETUP_POLY
+    return hipErrorInvalidValue;
+  }
 #define TOP_SETUP_CASE(P_, S_, B_, V_)                                                   \
   if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_) {            \
     hipLaunchKernelGGL((setup_kernel<R, P_, S_, B_, V_>), grid, block, 0, st, a, o);    \

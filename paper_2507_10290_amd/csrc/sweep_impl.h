@@ -55,6 +55,49 @@ struct Lane {
   bool first, last, has_left, has_right, fixpos;
 };
 
+// Knot consensus and the u update after the local solves (eqs. UpdateZ, UpdateU): neighbours
+// inside the wave by shuffles, across waves through LDS (one barrier).  LT is any lane type with
+// the knot state zL, zR, uL, uR [3][S] and the neighbour flags.
+template <bool FINAL, int P, int S, typename LT, typename R>
+__device__ __forceinline__ void knot_exchange(LT& L, R (&xL)[3][S], R (&xR)[3][S], R (*xr_sh)[3 * S],
+                                              R (*xl_sh)[3 * S], int wl, int wid, int nw, R (&zfin)[3][S]) {
+  if (wl == 63) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = 0; o < S; ++o) xr_sh[wid][a * S + o] = xR[a][o];
+  }
+  if (wl == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = 0; o < S; ++o) xl_sh[wid][a * S + o] = xL[a][o];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int o = 0; o < S; ++o) {
+      R xp = __shfl_up(xR[a][o], 1);
+      R xn = __shfl_down(xL[a][o], 1);
+      if (wl == 0 && wid > 0) xp = xr_sh[wid - 1][a * S + o];
+      if (wl == 63 && wid < nw - 1) xn = xl_sh[wid + 1][a * S + o];
+      xp = L.has_left ? xp : xL[a][o];
+      xn = L.has_right ? xn : xR[a][o];
+      if constexpr (FINAL) zfin[a][o] = L.zR[a][o];
+      const bool free_o = (o > 0) || !L.fixpos;
+      const R zr_new = R(0.5) * (xR[a][o] + xn);
+      const R zl_new = R(0.5) * (xp + xL[a][o]);
+      L.zR[a][o] = (!L.last && free_o) ? zr_new : L.zR[a][o];
+      L.zL[a][o] = (!L.first && free_o) ? zl_new : L.zL[a][o];
+      const R du_l = xL[a][o] - L.zL[a][o];
+      const R du_r = xR[a][o] - L.zR[a][o];
+      L.uL[a][o] += (o < P || !L.first) ? du_l : R(0);
+      L.uR[a][o] += (o < P || !L.last) ? du_r : R(0);
+    }
+  }
+}
+
 // One sweep of one lane's segment.  With FINAL the local solve c~ and the end knot before its
 // update are returned through cfin / zfin.
 template <bool FINAL, typename R, int P, int S, bool BOX, bool VEL>
@@ -156,42 +199,7 @@ __device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh
     }
   }
 
-  // ---- knot exchange: neighbours inside the wave by shuffles, across waves through LDS
-  if (wl == 63) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int o = 0; o < S; ++o) xr_sh[wid][a * S + o] = xR[a][o];
-  }
-  if (wl == 0) {
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int o = 0; o < S; ++o) xl_sh[wid][a * S + o] = xL[a][o];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-#pragma unroll
-    for (int o = 0; o < S; ++o) {
-      R xp = __shfl_up(xR[a][o], 1);
-      R xn = __shfl_down(xL[a][o], 1);
-      if (wl == 0 && wid > 0) xp = xr_sh[wid - 1][a * S + o];
-      if (wl == 63 && wid < nw - 1) xn = xl_sh[wid + 1][a * S + o];
-      xp = L.has_left ? xp : xL[a][o];
-      xn = L.has_right ? xn : xR[a][o];
-      if constexpr (FINAL) zfin[a][o] = L.zR[a][o];
-      const bool free_o = (o > 0) || !L.fixpos;
-      const R zr_new = R(0.5) * (xR[a][o] + xn);
-      const R zl_new = R(0.5) * (xp + xL[a][o]);
-      L.zR[a][o] = (!L.last && free_o) ? zr_new : L.zR[a][o];
-      L.zL[a][o] = (!L.first && free_o) ? zl_new : L.zL[a][o];
-      const R du_l = xL[a][o] - L.zL[a][o];
-      const R du_r = xR[a][o] - L.zR[a][o];
-      L.uL[a][o] += (o < P || !L.first) ? du_l : R(0);
-      L.uR[a][o] += (o < P || !L.last) ? du_r : R(0);
-    }
-  }
+  knot_exchange<FINAL, P, S>(L, xL, xR, xr_sh, xl_sh, wl, wid, nw, zfin);
 }
 
 // REC: the instance used to replay checkpoint blocks for the reverse pass; it also stores the state
