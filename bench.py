@@ -31,8 +31,11 @@ PEAK_FP64 = 78.6e12
 HBM_PEAK = 8.0e12
 
 
-def flops_per_update(p: int, s: int, M: int, box: bool, vel: bool) -> int:
-    """Floating-point operations of one segment-update in the minimal form (FMA = 2)."""
+def flops_per_update(p: int, s: int, M: int, box: bool, vel: bool, faces: int = 0) -> int:
+    """Floating-point operations of one segment-update in the minimal form (FMA = 2).
+
+    faces = K > 0: a K-face polytope corridor instead of the box (right-hand side, rotations to
+    and from the frame of sum_k a_k a_k^T, and the face slack/dual updates)."""
     N = 2 * p
     ax = 4 * s + 2 * s + 2 * (N * s - s * (s - 1) // 2)            # knot terms of the right-hand side
     ax += 2 * N * N                                                 # (rho Htilde^-1) r
@@ -42,14 +45,18 @@ def flops_per_update(p: int, s: int, M: int, box: bool, vel: bool) -> int:
         ax += 1 + M * (2 + 2 * N) + M * (2 * N + 6)                 # box rows: rhs, evaluation, y update
     if vel:
         ax += M * (4 + 2 * (N - 1)) + M * (2 * (N - 1) + 4)         # velocity rows: rhs, evaluation, g update
-    return 3 * ax + (8 * M if vel else 0)                           # three axes + shared projections
+    shared = 8 * M if vel else 0                                    # velocity projections
+    if faces:
+        shared += M * (7 * faces + 6 * N) + 36 * N + M * (6 * N + 9 * faces)
+    return 3 * ax + shared
 
 
-def bytes_per_update(p: int, s: int, M: int, box: bool, vel: bool, rbytes: int = 4) -> int:
+def bytes_per_update(p: int, s: int, M: int, box: bool, vel: bool, rbytes: int = 4, faces: int = 0) -> int:
     """Minimal state read and written once plus read-only constants, per segment-update."""
     N = 2 * p
-    state = 6 * s + 3 * (s - 1) + (6 * M if box else 0) + (3 * M if vel else 0)
-    const = N * (N + 1) // 2 + 1 + 3 + (6 if box else 0)
+    nh = N * (N + 1) // 2
+    state = 6 * s + 3 * (s - 1) + (6 * M if box else faces * M) + (3 * M if vel else 0)
+    const = (3 * nh + 9 + 4 * faces if faces else nh) + 1 + 3 + (6 if box else 0)
     return (2 * state + const) * rbytes
 
 
@@ -57,14 +64,14 @@ def _dev_inputs(w, dev):
     import torch
     t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
     return dict(waypoints=t(w.waypoints), durations=t(w.durations), rho=t(w.rho), box_lo=t(w.box_lo),
-                box_hi=t(w.box_hi), vmax=t(w.vmax))
+                box_hi=t(w.box_hi), vmax=t(w.vmax), faces=t(w.faces))
 
 
 def _problem(w, d, **kw):
     from paper_2507_10290_amd import TopProblem
     return TopProblem(w.seg_offsets, d["waypoints"], d["durations"], d["rho"], order=w.order,
-                      n_cont=w.n_cont, box_lo=d["box_lo"], box_hi=d["box_hi"], vmax=d["vmax"],
-                      fix_interior=w.fix_interior, **kw)
+                      n_cont=w.n_cont, box_lo=d["box_lo"], box_hi=d["box_hi"], faces=d.get("faces"),
+                      vmax=d["vmax"], fix_interior=w.fix_interior, **kw)
 
 
 def solve_step(w, d, K, precision="fp32"):
@@ -370,6 +377,19 @@ def main():
         w4 = make_config(4)
         extra["fwd_bwd"] = fwd_bwd(w4, _dev_inputs(w4, dev), w4.iters, 10)
         extra["adaptive_rho"] = adaptive_leg(w, d, K, sec)
+        w5 = make_config(5)
+        d5 = _dev_inputs(w5, dev)
+        sec5 = time_steps(lambda: solve_step(w5, d5, w5.iters), 3, 1)
+        kms5, l5, plan5 = sweep_kernel_ms(w5, d5, w5.iters)
+        r5 = w5.n_seg * w5.iters / (kms5 * 1e-3)
+        extra["polytope_8_faces"] = {
+            "workload": config_summary(w5)["workload"], "n_seg": w5.n_seg,
+            "segment_updates_per_s": round(w5.n_seg * w5.iters / sec5, 1), "ms_per_solve": round(sec5 * 1e3, 3),
+            "sweep_only_segment_updates_per_s": round(r5, 1), "tile_lanes": plan5["tile_lanes"],
+            "flops_per_segment_update": flops_per_update(3, 3, 8, False, True, faces=8),
+            "alu_frac": round(flops_per_update(3, 3, 8, False, True, faces=8) * r5 / PEAK_FP32_NONPACKED, 4),
+            "hbm_yardstick_frac": round(bytes_per_update(3, 3, 8, False, True, faces=8) * r5 / HBM_PEAK, 3)}
+        del d5
     line["extra"] = extra
     if a.calib_copy:
         extra["calib_copy_bytes"] = calib_copy()

@@ -78,7 +78,8 @@ typedef struct top_options {
   int32_t halo;              /* sweeps per launch for trajectories longer than a tile (their halo
                                 width); 0 picks the default.  With a tape it must be >= 2: the
                                 reverse pass runs halo - 1 steps per launch                           */
-  int32_t use_graph;         /* 1: replay each top_iterate(k) launch sequence as a cached hipGraph    */
+  int32_t use_graph;         /* 1: a top_iterate(k) launch sequence asked for again (same k, buffer
+                                and check phase) is captured once and replayed as a hipGraph      */
   /* Stopping test and adaptive penalty (Sec. III-D.3, eqs. splitting_tolerance and UpdateRho).
      Residuals are formed every check_every sweeps, counted from Init; at each such check a
      trajectory of N segments whose ||r_p||^2 and ||r_d||^2 are both below (N tol)^2 stops (its

@@ -253,7 +253,7 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
       }
       if constexpr (VEL) {
         static_for<0, M>([&](auto s) {
-          const R b = (R(2) * f[s] - R(1)) * g[s] * iT;
+          const R b = ((R(2) * f[s] - R(1)) * iT) * g[s];
           static_for<1, N>([&](auto j) {
             constexpr R k = R(cvel(s, j));
             r[j] += k * b;

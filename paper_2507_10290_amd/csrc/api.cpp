@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -326,6 +327,7 @@ struct top_problem {
   double *rho_traj = nullptr, *ratio = nullptr;
   // launch sequences replayed as graphs, keyed by (sweeps, start buffer, sweep index mod check_every)
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+  std::set<std::tuple<int, int, int>> graph_seen;  // sequences launched once directly
   std::vector<hipGraph_t> graph_defs;
 
   template <typename T>
@@ -908,12 +910,16 @@ top_status top_iterate(top_problem* h, int32_t k) {
     return fail(TOP_E_STATE, "the tape holds %d sweeps; %d done, %d more asked", h->opt.max_taped_iters,
                 h->iters_done, k);
   // The sequence only depends on (k, start buffer) unless a tape is written.
-  const bool graph = h->opt.use_graph != 0 && h->tape == nullptr;
+  // A sequence is captured into a graph the second time it is asked for; the first call launches it
+  // directly (a one-shot solve would only pay for the capture).
+  const auto key = std::make_tuple(k, h->cur, h->opt.check_every > 0 ? h->iters_done % h->opt.check_every : 0);
+  const bool graph = h->opt.use_graph != 0 && h->tape == nullptr &&
+                     (h->graphs.count(key) != 0 || h->graph_seen.count(key) != 0);
   if (!graph) {
     top_status s = h->enqueue(k, h->cur, h->iters_done, h->stream);
     if (s != TOP_OK) return s;
+    if (h->opt.use_graph != 0 && h->tape == nullptr) h->graph_seen.insert(key);
   } else {
-    auto key = std::make_tuple(k, h->cur, h->opt.check_every > 0 ? h->iters_done % h->opt.check_every : 0);
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
       if (h->cap_stream == nullptr) TOP_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));

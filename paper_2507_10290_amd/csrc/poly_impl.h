@@ -41,14 +41,17 @@ __device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, R (*x
   constexpr int MV = LT::MV;
   constexpr int KF = LT::KF;
 
-  R f[MV];
+  R q[MV], om[MV];
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
     if constexpr (VEL) {
       const R n2 = L.g[0][s] * L.g[0][s] + L.g[1][s] * L.g[1][s] + L.g[2][s] * L.g[2][s];
-      f[s] = fmin(R(1), L.vm * inv_sqrt<R>(n2));
+      const R f = fmin(R(1), L.vm * inv_sqrt<R>(n2));
+      q[s] = (R(2) * f - R(1)) * L.iT;
+      om[s] = R(1) - f;
     } else {
-      f[s] = R(1);
+      q[s] = R(0);
+      om[s] = R(0);
     }
   }
 
@@ -89,7 +92,7 @@ __device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, R (*x
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       static_for<0, M>([&](auto s) {
-        const R b = (R(2) * f[s] - R(1)) * L.g[a][s] * L.iT;
+        const R b = q[s] * L.g[a][s];
         static_for<1, N>([&](auto j) {
           constexpr R k = R(cvel(s, j));
           r[a][j] += k * b;
@@ -115,10 +118,10 @@ __device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, R (*x
       });
     }
 #pragma unroll
-    for (int q = 0; q < 3; ++q)
+    for (int w = 0; w < 3; ++w)
 #pragma unroll
       for (int j = 0; j < N; ++j)
-        c[q][j] = L.U[3 * q] * cr[0][j] + L.U[3 * q + 1] * cr[1][j] + L.U[3 * q + 2] * cr[2][j];
+        c[w][j] = L.U[3 * w] * cr[0][j] + L.U[3 * w + 1] * cr[1][j] + L.U[3 * w + 2] * cr[2][j];
   }
 
   // ---- corridor slack/dual pairs
@@ -140,13 +143,16 @@ __device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, R (*x
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if constexpr (VEL) {
+      R ci[N];
+#pragma unroll
+      for (int j = 1; j < N; ++j) ci[j] = c[a][j] * L.iT;
       static_for<0, M>([&](auto s) {
         R vv = R(0);
         static_for<1, N>([&](auto j) {
           constexpr R k = R(cvel(s, j));
-          vv += k * c[a][j];
+          vv += k * ci[j];
         });
-        L.g[a][s] = vv * L.iT + (R(1) - f[s]) * L.g[a][s];
+        L.g[a][s] = vv + om[s] * L.g[a][s];
       });
     }
     static_for<0, S>([&](auto o) {

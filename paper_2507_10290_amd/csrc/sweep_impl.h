@@ -109,15 +109,19 @@ __device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh
   constexpr int M = LT::M;
   constexpr int MV = LT::MV;
 
-  // velocity projection factors: Proj(g) = f g with f = min(1, vmax / ||g||)
-  R f[MV];
+  // velocity projection factors: Proj(g) = f g with f = min(1, vmax / ||g||); per sample, shared by
+  // the three axes: q = (2f - 1) / T (right-hand side) and 1 - f (the g update)
+  R q[MV], om[MV];
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
     if constexpr (VEL) {
       const R n2 = L.g[0][s] * L.g[0][s] + L.g[1][s] * L.g[1][s] + L.g[2][s] * L.g[2][s];
-      f[s] = fmin(R(1), L.vm * inv_sqrt<R>(n2));
+      const R f = fmin(R(1), L.vm * inv_sqrt<R>(n2));
+      q[s] = (R(2) * f - R(1)) * L.iT;
+      om[s] = R(1) - f;
     } else {
-      f[s] = R(1);
+      q[s] = R(0);
+      om[s] = R(0);
     }
   }
 
@@ -149,7 +153,7 @@ __device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh
     }
     if constexpr (VEL) {
       static_for<0, M>([&](auto s) {
-        const R b = (R(2) * f[s] - R(1)) * L.g[a][s] * L.iT;
+        const R b = q[s] * L.g[a][s];
         static_for<1, N>([&](auto j) {
           constexpr R k = R(cvel(s, j));
           r[j] += k * b;
@@ -174,13 +178,16 @@ __device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh
       });
     }
     if constexpr (VEL) {
+      R ci[N];                                  // c~ / T: the velocity rows carry 1/T
+#pragma unroll
+      for (int j = 1; j < N; ++j) ci[j] = c[j] * L.iT;
       static_for<0, M>([&](auto s) {
         R vv = R(0);
         static_for<1, N>([&](auto j) {
           constexpr R k = R(cvel(s, j));
-          vv += k * c[j];
+          vv += k * ci[j];
         });
-        L.g[a][s] = vv * L.iT + (R(1) - f[s]) * L.g[a][s];
+        L.g[a][s] = vv + om[s] * L.g[a][s];
       });
     }
     static_for<0, S>([&](auto o) {

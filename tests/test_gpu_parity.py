@@ -174,6 +174,25 @@ def test_tiling_graph_and_split_are_bitwise_invariant():
     assert np.array_equal(c, base)
 
 
+def test_graph_replays_match_eager_launches():
+    # equal iterate(k) calls are captured on their second appearance and replayed afterwards; every
+    # step is compared with a handle that never uses graphs, with host synchronisation between them
+    from paper_2507_10290_amd import TopProblem
+    w = make_config(3, n_traj=24)
+    g = TopProblem.from_workload(w, precision="fp32", use_graph=True)
+    e = TopProblem.from_workload(w, precision="fp32", use_graph=False)
+    for step in range(7):
+        g.iterate(10)
+        e.iterate(10)
+        torch.cuda.synchronize()
+        assert torch.equal(g.coeffs(), e.coeffs()), step
+        assert torch.equal(g.cost(), e.cost()), step
+        rg, re_ = g.residuals(), e.residuals()
+        assert torch.equal(rg[0], re_[0]) and torch.equal(rg[1], re_[1]), step
+    g.close()
+    e.close()
+
+
 def test_repeat_runs_bitwise_equal():
     w = make_config(1, scale=0.25)
     a = run_gpu(w, 100, "fp32")[0]
