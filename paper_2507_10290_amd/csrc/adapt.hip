@@ -22,6 +22,7 @@ __global__ void check_kernel(CheckArgs a) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= a.B) return;
   double ratio = 1.0;
+  a.fresh[b] = 0;
   if (a.done[b] == 0) {
     a.swept[b] += a.check_every;
     const double rp = a.res[a.B + b], rd = a.res[2 * a.B + b];
@@ -29,6 +30,7 @@ __global__ void check_kernel(CheckArgs a) {
     if (a.tol > 0.0 && rp * rp < t * t && rd * rd < t * t) {
       a.done[b] = 1;
       a.stop_at[b] = a.swept[b];
+      a.fresh[b] = 1;
     } else if (a.adapt) {
       const double old = a.rho[b];
       double nw = old;
@@ -45,6 +47,26 @@ __global__ void check_kernel(CheckArgs a) {
 
 hipError_t launch_check(const CheckArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(check_kernel, dim3((a.B + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename R>
+__global__ void freeze_copy_kernel(const R* cur, R* other, const uint8_t* fresh, const int32_t* traj, int nf,
+                                   int64_t S, int64_t ld) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S || fresh[traj[i]] == 0) return;
+  for (int f = 0; f < nf; ++f) other[f * ld + i] = cur[f * ld + i];
+}
+
+hipError_t launch_freeze_copy(const void* cur, void* other, const uint8_t* fresh, const int32_t* traj, int nf,
+                              int64_t S, int64_t ld, size_t rsz, hipStream_t st) {
+  const dim3 grid((unsigned)((S + 255) / 256)), block(256);
+  if (rsz == sizeof(float))
+    hipLaunchKernelGGL(freeze_copy_kernel<float>, grid, block, 0, st, (const float*)cur, (float*)other, fresh, traj,
+                       nf, S, ld);
+  else
+    hipLaunchKernelGGL(freeze_copy_kernel<double>, grid, block, 0, st, (const double*)cur, (double*)other, fresh,
+                       traj, nf, S, ld);
   return hipGetLastError();
 }
 

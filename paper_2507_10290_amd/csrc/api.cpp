@@ -322,7 +322,7 @@ struct top_problem {
   void *blk = nullptr, *adjb[2] = {nullptr, nullptr}, *acc_iT = nullptr, *acc_hd = nullptr, *acc_z0 = nullptr;
   double *dPL = nullptr, *dPR = nullptr, *dK = nullptr, *dK0 = nullptr;
   // residual checks: per-trajectory stop flag, sweep counters, current rho and the last change
-  uint8_t* done_dev = nullptr;
+  uint8_t *done_dev = nullptr, *fresh = nullptr;
   int32_t *swept = nullptr, *stop_at = nullptr;
   double *rho_traj = nullptr, *ratio = nullptr;
   // launch sequences replayed as graphs, keyed by (sweeps, start buffer, sweep index mod check_every)
@@ -408,6 +408,8 @@ struct top_problem {
     a.coeffs = coeffs;
     a.nonfinite = flag_dev;
     a.with_res = with_res ? 1 : 0;
+    // stopped trajectories keep their partials; coefficient output needs every segment
+    a.done = (opt.check_every > 0 && coeffs == nullptr) ? done_dev : nullptr;
     hipError_t e = top::launch_finalize<R>(v, a, st);
     if (e != hipSuccess) return fail(TOP_E_HIP, "finalize launch failed: %s", hipGetErrorString(e));
     return TOP_OK;
@@ -562,12 +564,15 @@ struct top_problem {
     ca.tau_incr = opt.tau_incr;
     ca.tau_decr = opt.tau_decr;
     ca.done = done_dev;
+    ca.fresh = fresh;
     ca.swept = swept;
     ca.stop_at = stop_at;
     ca.rho = rho_traj;
     ca.ratio = ratio;
     if ((e = top::launch_check(ca, st)) != hipSuccess)
       return fail(TOP_E_HIP, "check launch failed: %s", hipGetErrorString(e));
+    if ((e = top::launch_freeze_copy(state[c], state[c ^ 1], fresh, traj, nf, S, ld, rsz, st)) != hipSuccess)
+      return fail(TOP_E_HIP, "freeze copy failed: %s", hipGetErrorString(e));
     if (!opt.adapt_rho) return TOP_OK;
     e = v.prec == 0 ? rescale_t<float>(c, st) : rescale_t<double>(c, st);
     if (e != hipSuccess) return fail(TOP_E_HIP, "rescale launch failed: %s", hipGetErrorString(e));
@@ -766,6 +771,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   if ((st = h->alloc(&h->rho_traj, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
   if (opt.check_every > 0) {
     if ((st = h->alloc(&h->done_dev, (size_t)n_traj)) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->fresh, (size_t)n_traj)) != TOP_OK) return bail(st);
     if ((st = h->alloc(&h->swept, (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
     if ((st = h->alloc(&h->stop_at, (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
     if ((st = h->alloc(&h->ratio, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);

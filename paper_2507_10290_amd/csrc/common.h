@@ -123,8 +123,8 @@ struct SweepArgs {
   int final_out;            // write c~ and the end knot before its last update, at the last sweep
   R* c_out;                 // [3n][ld]
   R* zold_out;              // [3s][ld]
-  const uint8_t* done;      // [B] nonzero: the trajectory has stopped and its state is copied through;
-                            // or null
+  const uint8_t* done;      // [B] nonzero: the trajectory has stopped; both state buffers hold its final
+                            // state and its lanes neither load nor store; or null
   R* rec;                   // recording launches (reverse-pass replay): the state after sweep i of the
   int64_t rec_slot;         // launch, i < iters - 1, goes to rec + (i + 1) * rec_slot; else null
 };
@@ -191,6 +191,7 @@ struct FinalArgs {
   double* coeffs;       // [S][3][n] or null
   int* nonfinite;
   int with_res;
+  const uint8_t* done;  // [B] or null: segments of stopped trajectories keep their partials (skipped)
 };
 
 template <typename R>
@@ -212,12 +213,17 @@ struct CheckArgs {
   int adapt;
   double tol, mu, tau_incr, tau_decr;
   uint8_t* done;          // [B] set once the stopping test passes
+  uint8_t* fresh;         // [B] 1 for the trajectories that stopped at this check, else 0
   int32_t* swept;         // [B] sweeps counted at the checks while the trajectory runs
   int32_t* stop_at;       // [B] sweeps applied when it stopped
   double* rho;            // [B] current penalty
   double* ratio;          // [B] rho_old / rho_new at this check, 1 when unchanged
 };
 hipError_t launch_check(const CheckArgs& a, hipStream_t st);
+// Copy the state of the trajectories that just stopped into the other ping-pong buffer (nf fields of
+// rsz bytes per segment), so that later sweeps can leave them alone.
+hipError_t launch_freeze_copy(const void* cur, void* other, const uint8_t* fresh, const int32_t* traj, int nf,
+                              int64_t S, int64_t ld, size_t rsz, hipStream_t st);
 
 template <typename R>
 struct RescaleArgs {

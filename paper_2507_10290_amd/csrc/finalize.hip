@@ -10,6 +10,7 @@ __global__ void finalize_kernel(FinalArgs<R> a) {
   constexpr int N = 2 * P;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.S) return;
+  if (a.done != nullptr && a.done[a.traj[i]] != 0) return;  // stopped: its partials are final
   const int64_t ld = a.ld;
   const double T = a.T[i];
   const double iT = 1.0 / T;

@@ -11,6 +11,9 @@
 //   y_{k,s} <- a_k . p_s - b_k + max(0, y_{k,s}),  p_s = (tau_s . c~_a)_a
 //                                                    [eqs. NonNegativeProject, UpdateV]
 // The knot, u and velocity rules are those of the box kernel.
+//
+// HL: the three rho Htilde_a'^-1 live in the lane's own column of dynamic LDS instead of registers
+// (used for the float32 quintic instance, which then fits two waves per SIMD).
 #pragma once
 
 #include "sweep_impl.h"
@@ -31,9 +34,9 @@ struct PolyLane {
   bool first, last, has_left, has_right, fixpos;
 };
 
-template <bool FINAL, typename R, int P, int S, bool VEL>
-__device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, R (*xr_sh)[3 * S],
-                                                R (*xl_sh)[3 * S], int wl, int wid, int nw,
+template <bool FINAL, bool HL, typename R, int P, int S, bool VEL>
+__device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, const R* Hs, int W, int lane,
+                                                R (*xr_sh)[3 * S], R (*xl_sh)[3 * S], int wl, int wid, int nw,
                                                 R (&cfin)[3][2 * P], R (&zfin)[3][S]) {
   using LT = PolyLane<R, P, S, VEL>;
   constexpr int N = LT::N;
@@ -113,7 +116,11 @@ __device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, R (*x
     for (int ax = 0; ax < 3; ++ax) {
       static_for<0, N>([&](auto i) {
         R acc = R(0);
-        static_for<0, N>([&](auto j) { acc += L.H[ax][tri(N, i, j)] * rr[ax][j]; });
+        static_for<0, N>([&](auto j) {
+          constexpr int h = tri(N, i, j);
+          const R hv = HL ? Hs[(ax * LT::NH + h) * W + lane] : L.H[ax][h];
+          acc += hv * rr[ax][j];
+        });
         cr[ax][i] = acc;
       });
     }
@@ -173,8 +180,8 @@ __device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, R (*x
   knot_exchange<FINAL, P, S>(L, xL, xR, xr_sh, xl_sh, wl, wid, nw, zfin);
 }
 
-template <typename R, int P, int S, bool VEL, int LB>
-__global__ __launch_bounds__(LB) void poly_sweep_kernel(SweepArgs<R> A) {
+template <typename R, int P, int S, bool VEL, int LB, bool HL, int WPE>
+__global__ __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(WPE))) void poly_sweep_kernel(SweepArgs<R> A) {
   using LT = PolyLane<R, P, S, VEL>;
   constexpr int N = LT::N;
   constexpr int NH = LT::NH;
@@ -213,10 +220,16 @@ __global__ __launch_bounds__(LB) void poly_sweep_kernel(SweepArgs<R> A) {
   L.fixpos = A.fixpos != 0;
 
   // ---- per-segment constants
+  extern __shared__ double poly_lds_raw[];
+  R* Hs = reinterpret_cast<R*>(poly_lds_raw);
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
-    for (int h = 0; h < NH; ++h) L.H[ax][h] = active ? A.k.Hr[(ax * NH + h) * ld + seg] : R(0);
+    for (int h = 0; h < NH; ++h) {
+      const R v = active ? A.k.Hr[(ax * NH + h) * ld + seg] : R(0);
+      if constexpr (HL) Hs[(ax * NH + h) * W + lane] = v;
+      else L.H[ax][h] = v;
+    }
 #pragma unroll
   for (int q = 0; q < 9; ++q) L.U[q] = active ? A.k.U[q * ld + seg] : R(0);
 #pragma unroll
@@ -253,13 +266,9 @@ __global__ __launch_bounds__(LB) void poly_sweep_kernel(SweepArgs<R> A) {
     for (int s = 0; s < M; ++s) L.y[k][s] = active ? in[(F_Y + k * M + s) * ld + seg] : R(0);
 
   const int wl = lane & 63, wid = lane >> 6, nw = W >> 6;
+  // stopped trajectories: both state buffers hold their state; their lanes store nothing
   const bool frozen = active && A.done != nullptr && A.done[tr] != 0;
-  auto copy_through = [&]() {
-#pragma unroll 4
-    for (int f = 0; f < NF; ++f) A.st_out[f * ld + seg] = in[f * ld + seg];
-  };
   if (__ballot(active && !frozen) == 0) {
-    if (core && frozen) copy_through();
     for (int it = 0; it < A.iters; ++it) __syncthreads();
     return;
   }
@@ -267,9 +276,9 @@ __global__ __launch_bounds__(LB) void poly_sweep_kernel(SweepArgs<R> A) {
   const int n_plain = A.final_out ? A.iters - 1 : A.iters;
   int it = 0;
   for (; it < n_plain; ++it)
-    poly_sweep_once<false>(L, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
+    poly_sweep_once<false, HL>(L, Hs, W, lane, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
   if (A.final_out && A.iters > 0) {
-    poly_sweep_once<true>(L, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
+    poly_sweep_once<true, HL>(L, Hs, W, lane, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
     if (core && !frozen) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -280,7 +289,6 @@ __global__ __launch_bounds__(LB) void poly_sweep_kernel(SweepArgs<R> A) {
       }
     }
   }
-  if (core && frozen) copy_through();
   if (core && !frozen) {
     R* out = A.st_out;
 #pragma unroll
@@ -309,9 +317,19 @@ hipError_t dispatch_poly_sweep(const Variant& v, const SweepArgs<R>& a, int n_ti
   if (v.faces != kFaces || v.box || a.rec != nullptr) return hipErrorInvalidValue;
   if (a.W <= 0 || a.W > 256 || (a.W & 63) != 0 || n_tiles <= 0) return hipErrorInvalidValue;
   dim3 grid(n_tiles), block(a.W);
+  // float32 quintic: matrices in LDS, two waves per SIMD; otherwise in registers
+  constexpr bool hl3 = std::is_same<R, float>::value;
 #define TOP_POLY_CASE(P_, S_, V_)                                                             \
   if (v.p == P_ && v.s == S_ && (v.vel != 0) == V_) {                                       \
-    hipLaunchKernelGGL((poly_sweep_kernel<R, P_, S_, V_, 256>), grid, block, 0, st, a);      \
+    constexpr bool HL_ = hl3 && P_ == 3;                                                    \
+    constexpr int NH_ = 2 * P_ * (2 * P_ + 1) / 2;                                          \
+    const size_t lds = HL_ ? (size_t)3 * NH_ * a.W * sizeof(R) : 0;                         \
+    auto k_ = poly_sweep_kernel<R, P_, S_, V_, 256, HL_, HL_ ? 2 : 1>;                      \
+    if (HL_) {                                                                              \
+      hipError_t e_ = hipFuncSetAttribute((const void*)k_, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+      if (e_ != hipSuccess) return e_;                                                      \
+    }                                                                                       \
+    hipLaunchKernelGGL(k_, grid, block, lds, st, a);                                        \
     return hipGetLastError();                                                               \
   }
   TOP_POLY_CASE(3, 3, true) TOP_POLY_CASE(3, 3, false)

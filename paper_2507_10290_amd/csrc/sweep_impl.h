@@ -288,8 +288,10 @@ __global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
   }
 
   const int wl = lane & 63, wid = lane >> 6, nw = W >> 6;
-  // A stopped trajectory keeps its state: its lanes sweep along (their neighbours belong to the same
-  // trajectory, so nothing leaks) but store their input state and leave c~ and the old knot alone.
+  // A stopped trajectory keeps its state: both state buffers already hold it, so its lanes sweep
+  // along (their neighbours belong to the same trajectory, so nothing leaks) and leave c~ and the old
+  // knot alone.  In a wave that still has live lanes they store their input state again (the same
+  // values; kept because this epilogue shape compiles to a measurably faster sweep loop).
   const bool frozen = active && A.done != nullptr && A.done[tr] != 0;
   auto copy_through = [&]() {
     constexpr int NF = F_G + (VEL ? 3 * M : 0);
@@ -298,7 +300,6 @@ __global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
   };
   // A wave with no live segment only has to keep the workgroup's barrier count (one per sweep).
   if (__ballot(active && !frozen) == 0) {
-    if (core && frozen) copy_through();
     for (int it = 0; it < A.iters; ++it) __syncthreads();
     return;
   }
