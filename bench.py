@@ -64,14 +64,14 @@ def _dev_inputs(w, dev):
     import torch
     t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to(dev)
     return dict(waypoints=t(w.waypoints), durations=t(w.durations), rho=t(w.rho), box_lo=t(w.box_lo),
-                box_hi=t(w.box_hi), vmax=t(w.vmax), faces=t(w.faces))
+                box_hi=t(w.box_hi), vmax=t(w.vmax), faces=t(w.faces), bc=t(w.bc))
 
 
 def _problem(w, d, **kw):
     from paper_2507_10290_amd import TopProblem
     return TopProblem(w.seg_offsets, d["waypoints"], d["durations"], d["rho"], order=w.order,
                       n_cont=w.n_cont, box_lo=d["box_lo"], box_hi=d["box_hi"], faces=d.get("faces"),
-                      vmax=d["vmax"], fix_interior=w.fix_interior, **kw)
+                      vmax=d["vmax"], bc=d.get("bc"), fix_interior=w.fix_interior, **kw)
 
 
 def solve_step(w, d, K, precision="fp32"):
@@ -127,6 +127,31 @@ def adaptive_leg(w, d, K, fixed_sec, check_every=10, tol=0.05):
             "segment_sweeps_applied_fraction": round(applied / (w.n_seg * K), 4),
             "rho_changed_fraction": round(float(np.mean(rho != w.rho)), 4),
             "applied_segment_updates_per_s": round(applied / sec, 1)}
+
+
+def scaling_leg(dev, K=1000, sizes=(64, 256, 1024, 4096, 16384, 65536)):
+    """Segment-count study of Sec. IV: one trajectory through N + 1 points of a parametric curve,
+    K sweeps in float32; time per solve (create to coefficients) and e_simi against the curve."""
+    from paper_2507_10290_amd.metrics import e_simi
+    from paper_2507_10290_amd.workloads import CURVE_PERIOD, curve, curve_workload
+    rows = []
+    for N in sizes:
+        w = curve_workload(N, iters=K)
+        d = _dev_inputs(w, dev)
+        out = {}
+
+        def step():
+            prob = _problem(w, d, precision="fp32")
+            prob.iterate(K)
+            out["c"] = prob.coeffs()
+            prob.close()
+
+        sec = time_steps(step, 2, 1)
+        total = float(w.durations.sum())
+        es = e_simi(out["c"].cpu().numpy(), w.durations, lambda t: curve(t * CURVE_PERIOD / total))
+        rows.append({"n_seg": N, "ms_per_solve": round(sec * 1e3, 3), "e_simi": round(es, 4),
+                     "segment_updates_per_s": round(N * K / sec, 1)})
+    return {"workload": "trefoil through N + 1 pinned points, 20 s, fp32", "iters": K, "rows": rows}
 
 
 def plain_rate(w, d_all, K, n_traj):
@@ -377,6 +402,7 @@ def main():
         w4 = make_config(4)
         extra["fwd_bwd"] = fwd_bwd(w4, _dev_inputs(w4, dev), w4.iters, 10)
         extra["adaptive_rho"] = adaptive_leg(w, d, K, sec)
+        extra["segment_count_scaling"] = scaling_leg(dev)
         w5 = make_config(5)
         d5 = _dev_inputs(w5, dev)
         sec5 = time_steps(lambda: solve_step(w5, d5, w5.iters), 3, 1)

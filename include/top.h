@@ -62,7 +62,8 @@ enum { TOP_FP32 = 0, TOP_FP64 = 1 };
 /* Problem and execution options (host struct, copied by top_create). */
 typedef struct top_options {
   int32_t order;             /* p: 3 = minimum jerk (quintic), 4 = minimum snap (septic) (Sec. III-A) */
-  int32_t n_cont;            /* s: derivative orders 0..s-1 shared at interior knots, s in {p, p+1};
+  int32_t n_cont;            /* s: derivative orders 0..s-1 shared at interior knots, s in {p, p+1,
+                                2p-1} (2p-1 is the consensus on every order 0..2p-2, without a tape);
                                 0 selects s = p (Sec. III-B, eq. Consensus_problem)                   */
   int32_t fix_interior;      /* 1: interior knot positions are pinned to the waypoints;
                                 0: they are averaged like the other orders (Sec. III-D.2)              */

@@ -140,6 +140,8 @@ hipError_t launch_rescale(const Variant& v, const RescaleArgs<R>& a, hipStream_t
     TOP_RESCALE_POLY(3, 4, true) TOP_RESCALE_POLY(3, 4, false)
     TOP_RESCALE_POLY(4, 4, true) TOP_RESCALE_POLY(4, 4, false)
     TOP_RESCALE_POLY(4, 5, true) TOP_RESCALE_POLY(4, 5, false)
+    TOP_RESCALE_POLY(3, 5, true) TOP_RESCALE_POLY(3, 5, false)
+    TOP_RESCALE_POLY(4, 7, true) TOP_RESCALE_POLY(4, 7, false)
 #undef TOP_RESCALE_POLY
     return hipErrorInvalidValue;
   }
@@ -157,6 +159,8 @@ hipError_t launch_rescale(const Variant& v, const RescaleArgs<R>& a, hipStream_t
   TOP_RESCALE_PS(3, 4)
   TOP_RESCALE_PS(4, 4)
   TOP_RESCALE_PS(4, 5)
+  TOP_RESCALE_PS(3, 5)
+  TOP_RESCALE_PS(4, 7)
 #undef TOP_RESCALE_PS
 #undef TOP_RESCALE_CASE
   return hipErrorInvalidValue;

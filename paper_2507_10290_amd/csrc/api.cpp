@@ -42,7 +42,9 @@ top_status fail(top_status s, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(TOP_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
-int max_tile(const top::Variant& v) { return (v.prec == 0 && v.p == 3 && v.faces == 0) ? 512 : 256; }
+int max_tile(const top::Variant& v) {
+  return (v.prec == 0 && v.p == 3 && v.faces == 0 && v.s != 2 * v.p - 1) ? 512 : 256;
+}
 // Handles that keep a tape also run the adjoint kernel on the same tiles: it is built for tiles of up
 // to 256 lanes, and its per-lane LDS column (box and velocity pair adjoints) must fit the device's
 // per-workgroup LDS.
@@ -374,21 +376,22 @@ struct top_problem {
 
   template <typename R>
   top_status launch_one(const Plan& pl, const int32_t* lane_map, const void* in, void* outp, int n, bool fin,
-                        hipStream_t st) {
+                        hipStream_t st, bool store_frozen) {
     top::SweepArgs<R> a = sweep_args<R>(pl, lane_map);
     a.st_in = (const R*)in;
     a.st_out = (R*)outp;
     a.iters = n;
     a.final_out = fin ? 1 : 0;
+    a.store_frozen = store_frozen ? 1 : 0;
     hipError_t e = v.faces ? top::launch_poly_sweep<R>(v, a, pl.n_tiles, st) : top::launch_sweep<R>(v, a, pl.n_tiles, st);
     if (e != hipSuccess) return fail(TOP_E_HIP, "sweep launch failed: %s", hipGetErrorString(e));
     return TOP_OK;
   }
 
   top_status sweep_launch(const Plan& pl, const int32_t* lane_map, const void* in, void* outp, int n, bool fin,
-                          hipStream_t st) {
-    return v.prec == 0 ? launch_one<float>(pl, lane_map, in, outp, n, fin, st)
-                       : launch_one<double>(pl, lane_map, in, outp, n, fin, st);
+                          hipStream_t st, bool store_frozen = false) {
+    return v.prec == 0 ? launch_one<float>(pl, lane_map, in, outp, n, fin, st, store_frozen)
+                       : launch_one<double>(pl, lane_map, in, outp, n, fin, st, store_frozen);
   }
 
   template <typename R>
@@ -693,8 +696,10 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   if (S + n_traj >= (int64_t)top::kHaloBit) return fail(TOP_E_UNSUPPORTED, "too many segments (%lld)", (long long)S);
   if (opt.order != 3 && opt.order != 4) return fail(TOP_E_UNSUPPORTED, "order must be 3 or 4 (got %d)", opt.order);
   const int s = opt.n_cont == 0 ? opt.order : opt.n_cont;
-  if (s != opt.order && s != opt.order + 1)
-    return fail(TOP_E_UNSUPPORTED, "n_cont must be p or p+1 (got %d for p = %d)", s, opt.order);
+  if (s != opt.order && s != opt.order + 1 && s != 2 * opt.order - 1)
+    return fail(TOP_E_UNSUPPORTED, "n_cont must be p, p+1 or 2p-1 (got %d for p = %d)", s, opt.order);
+  if (s == 2 * opt.order - 1 && opt.checkpoint_every > 0)
+    return fail(TOP_E_UNSUPPORTED, "n_cont = 2p-1 cannot be combined with a tape");
   if (opt.n_samples == 0) opt.n_samples = top::kSamples;
   if (opt.n_samples != top::kSamples) return fail(TOP_E_UNSUPPORTED, "only n_samples = 8 is built (got %d)", opt.n_samples);
   if (opt.precision != TOP_FP32 && opt.precision != TOP_FP64) return fail(TOP_E_INVALID, "precision must be TOP_FP32 or TOP_FP64");
@@ -1065,7 +1070,7 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
       while (remaining > 0) {
         const int n = pl.halo > 0 ? std::min(remaining, pl.halo) : remaining;
         // probe sweeps read the live state and write scratch; the iterate is not advanced
-        s = h->sweep_launch(pl, cand->dev, h->state[h->cur], h->scratch, n, false, h->stream);
+        s = h->sweep_launch(pl, cand->dev, h->state[h->cur], h->scratch, n, false, h->stream, true);
         if (s != TOP_OK) return s;
         remaining -= n;
       }

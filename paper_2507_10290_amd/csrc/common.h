@@ -125,6 +125,8 @@ struct SweepArgs {
   R* zold_out;              // [3s][ld]
   const uint8_t* done;      // [B] nonzero: the trajectory has stopped; both state buffers hold its final
                             // state and its lanes neither load nor store; or null
+  int store_frozen;         // 1: lanes of stopped trajectories in waves with live lanes store their (unchanged)
+                            // state, for an output buffer that does not hold it yet (tuning probes)
   R* rec;                   // recording launches (reverse-pass replay): the state after sweep i of the
   int64_t rec_slot;         // launch, i < iters - 1, goes to rec + (i + 1) * rec_slot; else null
 };

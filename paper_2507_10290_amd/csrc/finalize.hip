@@ -93,6 +93,8 @@ hipError_t launch_finalize(const Variant& v, const FinalArgs<R>& a, hipStream_t 
   else if (v.p == 3 && v.s == 4) hipLaunchKernelGGL((finalize_kernel<R, 3, 4>), grid, block, 0, st, a);
   else if (v.p == 4 && v.s == 4) hipLaunchKernelGGL((finalize_kernel<R, 4, 4>), grid, block, 0, st, a);
   else if (v.p == 4 && v.s == 5) hipLaunchKernelGGL((finalize_kernel<R, 4, 5>), grid, block, 0, st, a);
+  else if (v.p == 3 && v.s == 5) hipLaunchKernelGGL((finalize_kernel<R, 3, 5>), grid, block, 0, st, a);
+  else if (v.p == 4 && v.s == 7) hipLaunchKernelGGL((finalize_kernel<R, 4, 7>), grid, block, 0, st, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -336,6 +336,8 @@ hipError_t dispatch_poly_sweep(const Variant& v, const SweepArgs<R>& a, int n_ti
   TOP_POLY_CASE(3, 4, true) TOP_POLY_CASE(3, 4, false)
   TOP_POLY_CASE(4, 4, true) TOP_POLY_CASE(4, 4, false)
   TOP_POLY_CASE(4, 5, true) TOP_POLY_CASE(4, 5, false)
+  TOP_POLY_CASE(3, 5, true) TOP_POLY_CASE(3, 5, false)
+  TOP_POLY_CASE(4, 7, true) TOP_POLY_CASE(4, 7, false)
 #undef TOP_POLY_CASE
   return hipErrorInvalidValue;
 }

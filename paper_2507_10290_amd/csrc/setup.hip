@@ -258,6 +258,8 @@ hipError_t launch_setup(const Variant& v, const SetupArgs& a, const SetupOut<R>&
     TOP_SETUP_POLY(3, 4, true) TOP_SETUP_POLY(3, 4, false)
     TOP_SETUP_POLY(4, 4, true) TOP_SETUP_POLY(4, 4, false)
     TOP_SETUP_POLY(4, 5, true) TOP_SETUP_POLY(4, 5, false)
+    TOP_SETUP_POLY(3, 5, true) TOP_SETUP_POLY(3, 5, false)
+    TOP_SETUP_POLY(4, 7, true) TOP_SETUP_POLY(4, 7, false)
 #undef TOP_SETUP_POLY
     return hipErrorInvalidValue;
   }
@@ -275,6 +277,8 @@ hipError_t launch_setup(const Variant& v, const SetupArgs& a, const SetupOut<R>&
   TOP_SETUP_PS(3, 4)
   TOP_SETUP_PS(4, 4)
   TOP_SETUP_PS(4, 5)
+  TOP_SETUP_PS(3, 5)
+  TOP_SETUP_PS(4, 7)
 #undef TOP_SETUP_PS
 #undef TOP_SETUP_CASE
   return hipErrorInvalidValue;

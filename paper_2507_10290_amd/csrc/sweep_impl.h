@@ -290,8 +290,7 @@ __global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
   const int wl = lane & 63, wid = lane >> 6, nw = W >> 6;
   // A stopped trajectory keeps its state: both state buffers already hold it, so its lanes sweep
   // along (their neighbours belong to the same trajectory, so nothing leaks) and leave c~ and the old
-  // knot alone.  In a wave that still has live lanes they store their input state again (the same
-  // values; kept because this epilogue shape compiles to a measurably faster sweep loop).
+  // knot alone; with store_frozen they also store their input state into the output buffer.
   const bool frozen = active && A.done != nullptr && A.done[tr] != 0;
   auto copy_through = [&]() {
     constexpr int NF = F_G + (VEL ? 3 * M : 0);
@@ -348,15 +347,19 @@ __global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
     }
   }
 
-  if (core && frozen) copy_through();
+  if (core && frozen && A.store_frozen) copy_through();
   if (core && !frozen) store_to(A.st_out);
 }
 
-// LB3 / LB4: largest tile (launch bound) for the quintic / septic kernels.
+// LB3 / LB4: largest tile (launch bound) for the quintic / septic kernels.  The consensus on all
+// orders 0..2p-2 (s = 2p-1) carries more knot state and uses tiles of up to 256 lanes; it has no
+// recording instance (no tape).
 template <typename R, int LB3, int LB4>
 hipError_t dispatch_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st) {
   const bool rec = a.rec != nullptr;
-  const int lb = rec ? 256 : (v.p == 3) ? LB3 : LB4;
+  const bool full = v.s == 2 * v.p - 1;
+  const int lb = (rec || full) ? 256 : (v.p == 3) ? LB3 : LB4;
+  if (rec && full) return hipErrorInvalidValue;
   if (a.W <= 0 || a.W > lb || (a.W & 63) != 0 || n_tiles <= 0) return hipErrorInvalidValue;
   dim3 grid(n_tiles), block(a.W);
 #define TOP_SWEEP_CASE(P_, S_, B_, V_, LB_)                                                   \
@@ -376,10 +379,22 @@ hipError_t dispatch_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, 
   TOP_SWEEP_PS(4, 5, LB4)
 #undef TOP_SWEEP_PS
 #undef TOP_SWEEP_CASE
+#define TOP_SWEEP_FULL(P_, S_, B_, V_)                                                        \
+  if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_) {                 \
+    hipLaunchKernelGGL((sweep_kernel<R, P_, S_, B_, V_, 256>), grid, block, 0, st, a);       \
+    return hipGetLastError();                                                               \
+  }
+  TOP_SWEEP_FULL(3, 5, true, true) TOP_SWEEP_FULL(3, 5, true, false)
+  TOP_SWEEP_FULL(3, 5, false, true) TOP_SWEEP_FULL(3, 5, false, false)
+  TOP_SWEEP_FULL(4, 7, true, true) TOP_SWEEP_FULL(4, 7, true, false)
+  TOP_SWEEP_FULL(4, 7, false, true) TOP_SWEEP_FULL(4, 7, false, false)
+#undef TOP_SWEEP_FULL
   return hipErrorInvalidValue;
 }
 
 // Largest tile the kernel of this variant accepts.
-inline int max_tile_lanes(const Variant& v) { return v.prec == 0 ? (v.p == 3 ? 512 : 256) : 256; }
+inline int max_tile_lanes(const Variant& v) {
+  return (v.prec == 0 && v.p == 3 && v.s != 2 * v.p - 1) ? 512 : 256;
+}
 
 }  // namespace top

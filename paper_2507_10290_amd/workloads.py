@@ -271,6 +271,46 @@ def make_config(i: int, *, scale: Optional[float] = None, n_traj: Optional[int] 
     raise ValueError(f"no workload {i}")
 
 
+# ---------------------------------------------------------------------------
+# Segment-count scaling study (Sec. IV): points sampled from a parametric curve.
+# ---------------------------------------------------------------------------
+
+CURVE_PERIOD = 2.0 * np.pi
+
+
+def curve(theta: np.ndarray, order: int = 0) -> np.ndarray:
+    """A smooth closed 3-D curve (a trefoil knot) and its derivatives w.r.t. theta: [len(theta), 3]."""
+    th = np.asarray(theta, dtype=np.float64)
+    # x = sin t + 2 sin 2t, y = cos t - 2 cos 2t, z = -sin 3t; each term a sin/cos with a known derivative
+    terms = [(0, 1.0, 1, "s"), (0, 2.0, 2, "s"), (1, 1.0, 1, "c"), (1, -2.0, 2, "c"), (2, -1.0, 3, "s")]
+    out = np.zeros(th.shape + (3,))
+    for ax, amp, f, kind in terms:
+        # d^o/dt^o sin(f t) = f^o sin(f t + o pi/2); cos(f t) = sin(f t + pi/2)
+        phase = (np.pi / 2 if kind == "c" else 0.0) + order * np.pi / 2
+        out[..., ax] += amp * f ** order * np.sin(f * th + phase)
+    return out
+
+
+def curve_workload(n_seg: int, *, order: int = 3, total_time: float = 20.0, rho: float = 1.0,
+                   iters: int = 1000, precision: str = "fp32", n_turns: float = 1.0) -> Workload:
+    """N + 1 points sampled uniformly in the curve parameter, uniform durations, pinned interior
+    points, end states from the curve's own derivatives (time t = theta * total_time / span), no
+    corridor and no velocity bound: the trajectory must pass through the sampled points."""
+    span = CURVE_PERIOD * n_turns
+    theta = np.linspace(0.0, span, n_seg + 1)
+    P = curve(theta)
+    T = np.full(n_seg, total_time / n_seg)
+    dth = span / total_time                     # d theta / dt
+    bc = np.zeros((1, 2, order, 3))
+    for side, th in ((0, theta[0]), (1, theta[-1])):
+        for o in range(order):
+            bc[0, side, o] = curve(np.array([th]), o)[0] * dth ** o
+    return Workload(name=f"curve-N{n_seg}", order=order, n_cont=order, n_samples=8, fix_interior=True,
+                    seg_offsets=np.array([0, n_seg], dtype=np.int64), waypoints=P, durations=T,
+                    box_lo=None, box_hi=None, vmax=None, rho=np.array([float(rho)]), iters=iters,
+                    precision=precision, bc=bc, notes=f"trefoil, {n_turns} turn(s) in {total_time} s")
+
+
 def config_summary(w: Workload) -> dict:
     L = w.traj_lengths()
     return {"workload": w.name, "n_traj": w.n_traj, "n_seg": w.n_seg,
