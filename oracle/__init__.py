@@ -15,6 +15,9 @@ the oracle's own gradients), written in the paper's variables and order:
   paper's variables c, z, u, s, v, phi, w as they are printed.
 * ``minimal``     — the same iteration with the slack/dual pairs folded into
   one value per constraint row (used only to pin that algebra).
+* ``numeric``     — the iteration with the NumericSolve local update (the
+  velocity bound as a general inequality through g = max{0, h}^2 and an
+  L-BFGS minimisation of each segment's augmented Lagrangian).
 * ``adaptive``    — the stopping test and the adaptive penalty rule of
   Sec. III-D.3 around that iteration, one trajectory at a time.
 * ``references``  — direct solutions the iteration must converge to: the
