@@ -154,6 +154,25 @@ def scaling_leg(dev, K=1000, sizes=(64, 256, 1024, 4096, 16384, 65536)):
     return {"workload": "trefoil through N + 1 pinned points, 20 s, fp32", "iters": K, "rows": rows}
 
 
+def numeric_leg(w, dev, K=50, inner=10):
+    """NumericSolve (L-BFGS local update) against the closed form on the same trajectories and K."""
+    d = _dev_inputs(w, dev)
+    out = {}
+    for name, kw in (("closed_form", {}), ("numeric", {"numeric": True, "lbfgs_iters": inner})):
+        def step():
+            prob = _problem(w, d, precision="fp32", **kw)
+            prob.iterate(K)
+            prob.cost()
+            prob.close()
+        sec = time_steps(step, 2, 1)
+        out[name + "_ms"] = round(sec * 1e3, 3)
+        out[name + "_segment_updates_per_s"] = round(w.n_seg * K / sec, 1)
+    out["numeric_over_closed_form"] = round(out["numeric_ms"] / out["closed_form_ms"], 2)
+    out["workload"] = f"first {w.n_traj} trajectories of the batched workload ({w.n_seg} segments), fp32, K = {K}, " \
+                      f"{inner} L-BFGS iterations per local solve"
+    return out
+
+
 def plain_rate(w, d_all, K, n_traj):
     """Plain form: one handle per trajectory, created, iterated without a graph and read back in turn."""
     import torch
@@ -403,6 +422,7 @@ def main():
         extra["fwd_bwd"] = fwd_bwd(w4, _dev_inputs(w4, dev), w4.iters, 10)
         extra["adaptive_rho"] = adaptive_leg(w, d, K, sec)
         extra["segment_count_scaling"] = scaling_leg(dev)
+        extra["numeric_solve"] = numeric_leg(make_config(3, n_traj=256), dev)
         w5 = make_config(5)
         d5 = _dev_inputs(w5, dev)
         sec5 = time_steps(lambda: solve_step(w5, d5, w5.iters), 3, 1)

@@ -94,6 +94,13 @@ typedef struct top_options {
   double mu;                 /* residual ratio that triggers a change (> 1; the paper uses 10)        */
   double tau_incr;           /* growth factor (> 1; the paper uses 1.1)                               */
   double tau_decr;           /* shrink factor (> 1; the paper uses 1.1)                               */
+  /* Local update (Alg. 1): 0 = ClosedFormSolve; 1 = NumericSolve (Sec. III-C.3): the velocity bound
+     as the general inequality g_s = max{0, |v_s|^2 - vmax^2}^2 = 0 with scaled multipliers, each
+     segment's augmented Lagrangian minimised by lbfgs_iters L-BFGS iterations (memory 5, Armijo
+     backtracking) from its previous c.  NumericSolve needs vmax, s = p and a box or no corridor,
+     and takes no tape and no residual checks.                                                     */
+  int32_t local_solve;
+  int32_t lbfgs_iters;       /* L-BFGS iterations per local solve (>= 0; default 10)                 */
 } top_options;
 
 /* Fill *opt with the defaults: p = 3, s = p, pinned interior, M = 8, FP32, no tape, graph on,
@@ -183,6 +190,24 @@ top_status top_convergence(const top_problem* h, int32_t* iters, double* rho, ui
 /* Block on the stream; TOP_E_NONFINITE if any sweep so far produced a non-finite value. */
 top_status top_sync_status(top_problem* h);
 
+/* Copy of the iterate state (checkpoint and resume), in the iterate precision (float or double),
+ * structure of arrays: n_fields rows of ld elements (top_plan_info), row f, segment i at f * ld + i.
+ * Rows, with s = n_cont, M = 8, n = 2p, per axis a = 0..2 and order o < s, sample j < M:
+ *   z_R  (end knot of the segment, orders 0..s-1)      rows a*s + o
+ *   u_L, u_R (scaled consensus duals, start / end knot)  rows 3s + a*s + o, 6s + a*s + o
+ *   box: y_hi, y_lo folded corridor pairs               rows 9s + a*M + j, 9s + 3M + a*M + j
+ *   polytope: y of face k                                rows 9s + k*M + j
+ *   closed form with vmax: g (folded velocity pair)      rows C + a*M + j
+ *   NumericSolve: w_j, then the last c~ (c~_k = c_k T^k) rows C + j, C + M + a*n + k
+ * where C = 9s plus the corridor rows.  A folded pair y stands for the slack max(0, -y) and the
+ * scaled dual max(0, y); g for the split value Proj(g) and the scaled dual g - Proj(g).
+ *   state  [dev] n_fields * ld elements (written by top_get_state, read by top_set_state)
+ * top_set_state replaces the iterate (the next sweep starts from it); cost, residuals and
+ * coefficients keep describing the last sweep until another one runs.  Both are queued on the
+ * handle's stream. */
+top_status top_get_state(const top_problem* h, void* state);
+top_status top_set_state(top_problem* h, const void* state);
+
 /* Execution plan actually in use (host struct). */
 typedef struct top_plan_info {
   int32_t tile_lanes;        /* lanes (segments) per workgroup tile                         */
@@ -195,6 +220,8 @@ typedef struct top_plan_info {
   int32_t order;
   int32_t n_cont;
   int32_t iters_done;        /* sweeps run since top_create                                 */
+  int32_t n_fields;          /* rows of the iterate state (see top_get_state)               */
+  int64_t ld;                /* elements per state row, n_seg rounded up to a multiple of 64 */
 } top_plan_info;
 
 top_status top_get_plan(const top_problem* h, top_plan_info* info);

@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "TOP_OK", -1: "TOP_E_INVALID", -3: "TOP_E_HIP", -4: "TOP_E_ST
 
 # Every entry point declared in include/top.h.
 EXPORTED = ["top_default_options", "top_create", "top_create_polytope", "top_iterate", "top_time_sweeps", "top_residuals", "top_cost",
-            "top_coeffs", "top_backward", "top_tune", "top_convergence", "top_sync_status", "top_get_plan",
+            "top_coeffs", "top_backward", "top_tune", "top_convergence", "top_get_state", "top_set_state",
+            "top_sync_status", "top_get_plan",
             "top_destroy", "top_last_error"]
 
 
@@ -40,14 +41,15 @@ class TopOptions(ctypes.Structure):
                 ("checkpoint_every", ctypes.c_int32), ("max_taped_iters", ctypes.c_int32),
                 ("tile_lanes", ctypes.c_int32), ("halo", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("adapt_rho", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("mu", ctypes.c_double), ("tau_incr", ctypes.c_double), ("tau_decr", ctypes.c_double)]
+                ("mu", ctypes.c_double), ("tau_incr", ctypes.c_double), ("tau_decr", ctypes.c_double),
+                ("local_solve", ctypes.c_int32), ("lbfgs_iters", ctypes.c_int32)]
 
 
 class TopPlanInfo(ctypes.Structure):
     _fields_ = [("tile_lanes", ctypes.c_int32), ("n_tiles", ctypes.c_int32), ("halo", ctypes.c_int32),
                 ("n_traj", ctypes.c_int32), ("n_seg", ctypes.c_int64), ("used_lanes", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("order", ctypes.c_int32), ("n_cont", ctypes.c_int32),
-                ("iters_done", ctypes.c_int32)]
+                ("iters_done", ctypes.c_int32), ("n_fields", ctypes.c_int32), ("ld", ctypes.c_int64)]
 
 
 class TopError(RuntimeError):
@@ -90,6 +92,10 @@ def lib() -> ctypes.CDLL:
     L.top_backward.restype = ctypes.c_int
     L.top_tune.argtypes = [vp, i32]
     L.top_tune.restype = ctypes.c_int
+    L.top_get_state.argtypes = [vp, vp]
+    L.top_get_state.restype = ctypes.c_int
+    L.top_set_state.argtypes = [vp, vp]
+    L.top_set_state.restype = ctypes.c_int
     L.top_convergence.argtypes = [vp, vp, vp, vp]
     L.top_convergence.restype = ctypes.c_int
     L.top_sync_status.argtypes = [vp]
@@ -193,6 +199,14 @@ def top_convergence(h: int, iters, rho, done) -> None:
     _check(lib().top_convergence(ctypes.c_void_p(h), _ptr(iters), _ptr(rho), _ptr(done)))
 
 
+def top_get_state(h: int, state) -> None:
+    _check(lib().top_get_state(ctypes.c_void_p(h), _ptr(state)))
+
+
+def top_set_state(h: int, state) -> None:
+    _check(lib().top_set_state(ctypes.c_void_p(h), _ptr(state)))
+
+
 def top_sync_status(h: int) -> None:
     _check(lib().top_sync_status(ctypes.c_void_p(h)))
 
@@ -219,7 +233,8 @@ class TopProblem:
                  fix_interior: bool = True, checkpoint_every: int = 0, max_taped_iters: int = 0,
                  tile_lanes: int = 0, halo: int = 0, use_graph: bool = True, check_every: int = 0,
                  adapt_rho: bool = False, tol: float = 0.05, mu: float = 10.0, tau_incr: float = 1.1,
-                 tau_decr: float = 1.1, device: str = "cuda:0", stream=None):
+                 tau_decr: float = 1.1, numeric: bool = False, lbfgs_iters: int = 10, device: str = "cuda:0",
+                 stream=None):
         import torch
         self.device = torch.device(device)
         self.seg_offsets = np.asarray(seg_offsets, dtype=np.int64)
@@ -240,6 +255,8 @@ class TopProblem:
         o.check_every = int(check_every)
         o.adapt_rho = 1 if adapt_rho else 0
         o.tol, o.mu, o.tau_incr, o.tau_decr = float(tol), float(mu), float(tau_incr), float(tau_decr)
+        o.local_solve = 1 if numeric else 0
+        o.lbfgs_iters = int(lbfgs_iters)
         self.options = o
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         args = [_dev(x, self.device) for x in (waypoints, durations, rho, bc, box_lo, box_hi, vmax, faces)]
@@ -304,6 +321,24 @@ class TopProblem:
         rho = self._empty(self.B)
         top_convergence(self.h, it, rho, done)
         return it, rho, done.bool()
+
+    def get_state(self):
+        """The iterate state as a device tensor [n_fields, ld] in the iterate precision."""
+        import torch
+        info = self.plan()
+        dt = torch.float64 if self.options.precision == TOP_FP64 else torch.float32
+        st = torch.empty(info["n_fields"], info["ld"], dtype=dt, device=self.device)
+        top_get_state(self.h, st)
+        return st
+
+    def set_state(self, state) -> None:
+        """Replace the iterate (a tensor shaped and typed like get_state's)."""
+        import torch
+        dt = torch.float64 if self.options.precision == TOP_FP64 else torch.float32
+        info = self.plan()
+        if tuple(state.shape) != (info["n_fields"], info["ld"]) or state.dtype != dt:
+            raise ValueError("state must be shaped and typed like get_state()")
+        top_set_state(self.h, state.contiguous())
 
     def sync_status(self) -> None:
         top_sync_status(self.h)

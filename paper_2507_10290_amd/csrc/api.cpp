@@ -43,6 +43,7 @@ top_status fail(top_status s, const char* fmt, ...) {
   } while (0)
 
 int max_tile(const top::Variant& v) {
+  if (v.num) return 64;
   return (v.prec == 0 && v.p == 3 && v.faces == 0 && v.s != 2 * v.p - 1) ? 512 : 256;
 }
 // Handles that keep a tape also run the adjoint kernel on the same tiles: it is built for tiles of up
@@ -364,6 +365,7 @@ struct top_problem {
     a.k.bcL = (const R*)bcL;
     a.k.U = (const R*)Urot;
     a.k.fa = (const R*)fa;
+    a.k.rho = rho_seg;
     a.k.ld = ld;
     a.lane_seg = lane_map;
     a.W = pl.W;
@@ -383,7 +385,10 @@ struct top_problem {
     a.iters = n;
     a.final_out = fin ? 1 : 0;
     a.store_frozen = store_frozen ? 1 : 0;
-    hipError_t e = v.faces ? top::launch_poly_sweep<R>(v, a, pl.n_tiles, st) : top::launch_sweep<R>(v, a, pl.n_tiles, st);
+    a.inner = opt.lbfgs_iters;
+    hipError_t e = v.num     ? top::launch_numeric_sweep<R>(v, a, pl.n_tiles, st)
+                 : v.faces ? top::launch_poly_sweep<R>(v, a, pl.n_tiles, st)
+                           : top::launch_sweep<R>(v, a, pl.n_tiles, st);
     if (e != hipSuccess) return fail(TOP_E_HIP, "sweep launch failed: %s", hipGetErrorString(e));
     return TOP_OK;
   }
@@ -427,7 +432,7 @@ struct top_problem {
   top_status backward_t(const double* dcost, double* dP, double* dT) {
     const int K = iters_done, m = opt.checkpoint_every;
     const size_t sl = (size_t)nf * ld;
-    top::Layout L{v.p, v.s, v.box, v.vel, v.faces};
+    top::Layout L{v.p, v.s, v.box, v.vel, v.faces, v.num};
     top_status s;
     if (blk == nullptr) {
       if ((s = alloc(&blk, (size_t)m * sl * sizeof(R))) != TOP_OK) return s;
@@ -661,6 +666,8 @@ void top_default_options(top_options* opt) {
   opt->mu = 10.0;
   opt->tau_incr = 1.1;
   opt->tau_decr = 1.1;
+  opt->local_solve = 0;
+  opt->lbfgs_iters = 10;
 }
 
 const char* top_last_error(void) { return g_err.c_str(); }
@@ -707,7 +714,14 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   if (opt.checkpoint_every < 0 || (opt.checkpoint_every > 0 && opt.max_taped_iters < 1))
     return fail(TOP_E_INVALID, "checkpoint_every >= 0, and max_taped_iters >= 1 when it is > 0");
   top::Variant v{opt.precision == TOP_FP64 ? 1 : 0, opt.order, s, box_lo != nullptr, vmax != nullptr,
-                 faces != nullptr ? top::kFaces : 0};
+                 faces != nullptr ? top::kFaces : 0, opt.local_solve == 1 ? 1 : 0};
+  if (opt.local_solve != 0 && opt.local_solve != 1) return fail(TOP_E_INVALID, "local_solve must be 0 or 1");
+  if (v.num) {
+    if (vmax == nullptr) return fail(TOP_E_UNSUPPORTED, "NumericSolve needs a velocity bound (vmax)");
+    if (faces != nullptr || s != opt.order || opt.checkpoint_every > 0 || opt.check_every > 0)
+      return fail(TOP_E_UNSUPPORTED, "NumericSolve takes s = p, a box or no corridor, no tape and no checks");
+    if (opt.lbfgs_iters < 0) return fail(TOP_E_INVALID, "lbfgs_iters must be >= 0");
+  }
   const bool taped = opt.checkpoint_every > 0;
   if (faces != nullptr && taped) return fail(TOP_E_UNSUPPORTED, "a polytope corridor cannot be combined with a tape");
   if (opt.tile_lanes != 0 &&
@@ -744,7 +758,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   h->rsz = v.prec == 0 ? sizeof(float) : sizeof(double);
   h->off.assign(seg_offsets, seg_offsets + n_traj + 1);
   h->stream = stream;
-  top::Layout L{v.p, v.s, v.box, v.vel, v.faces};
+  top::Layout L{v.p, v.s, v.box, v.vel, v.faces, v.num};
   h->nf = L.nf();
 
   auto bail = [&](top_status st) { top_destroy(h); return st; };
@@ -1033,6 +1047,23 @@ top_status top_get_plan(const top_problem* h, top_plan_info* info) {
   info->order = h->opt.order;
   info->n_cont = h->opt.n_cont;
   info->iters_done = h->iters_done;
+  info->n_fields = h->nf;
+  info->ld = h->ld;
+  return TOP_OK;
+}
+
+top_status top_get_state(const top_problem* h, void* state) {
+  if (h == nullptr || state == nullptr) return fail(TOP_E_INVALID, "handle and state must be non-NULL");
+  TOP_HIP(hipMemcpyAsync(state, h->state[h->cur], (size_t)h->nf * h->ld * h->rsz, hipMemcpyDeviceToDevice,
+                         h->stream));
+  return TOP_OK;
+}
+
+top_status top_set_state(top_problem* h, const void* state) {
+  if (h == nullptr || state == nullptr) return fail(TOP_E_INVALID, "handle and state must be non-NULL");
+  if (h->tape != nullptr) return fail(TOP_E_STATE, "the iterate of a handle that records a tape cannot be replaced");
+  TOP_HIP(hipMemcpyAsync(h->state[h->cur], state, (size_t)h->nf * h->ld * h->rsz, hipMemcpyDeviceToDevice,
+                         h->stream));
   return TOP_OK;
 }
 

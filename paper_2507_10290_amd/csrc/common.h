@@ -82,6 +82,7 @@ __host__ __device__ constexpr int tri(int n, int i, int j) {
 struct Layout {
   int p, s, box, vel;
   int faces = 0;             // kFaces for a polytope corridor, else 0
+  int num = 0;               // NumericSolve: velocity multipliers w [M] and the last c~ [3n] instead of g
   __host__ __device__ int n() const { return 2 * p; }
   __host__ __device__ int nh() const { return n() * (n() + 1) / 2; }
   __host__ __device__ int zR() const { return 0; }
@@ -90,7 +91,7 @@ struct Layout {
   __host__ __device__ int yh() const { return 9 * s; }
   __host__ __device__ int yl() const { return 9 * s + (box ? 3 * kSamples : 0); }
   __host__ __device__ int g() const { return 9 * s + (box ? 6 * kSamples : faces * kSamples); }
-  __host__ __device__ int nf() const { return g() + (vel ? 3 * kSamples : 0); }
+  __host__ __device__ int nf() const { return g() + (num ? kSamples + 3 * n() : (vel ? 3 * kSamples : 0)); }
   // rho * Htilde^-1 rows: one matrix, or one per rotated axis for a polytope
   __host__ __device__ int nhr() const { return faces ? 3 * nh() : nh(); }
 };
@@ -104,6 +105,7 @@ struct SegConsts {
   const R* hi;          // [3]
   const R* U;           // polytope: [9] rotation to the axes of sum_k a_k a_k^T, U[3 q + a'] = U_{q a'}
   const R* fa;          // polytope: [kFaces][4] faces a_x, a_y, a_z, b
+  const double* rho;    // [S] rho of the segment's trajectory (NumericSolve)
   const R* vmax;        // velocity bound of the segment's trajectory
   const uint8_t* flags; // kFirst | kLast
   const int32_t* traj;  // trajectory of the segment
@@ -125,6 +127,7 @@ struct SweepArgs {
   R* zold_out;              // [3s][ld]
   const uint8_t* done;      // [B] nonzero: the trajectory has stopped; both state buffers hold its final
                             // state and its lanes neither load nor store; or null
+  int inner;                // NumericSolve: L-BFGS iterations per local solve
   int store_frozen;         // 1: lanes of stopped trajectories in waves with live lanes store their (unchanged)
                             // state, for an output buffer that does not hold it yet (tuning probes)
   R* rec;                   // recording launches (reverse-pass replay): the state after sweep i of the
@@ -135,6 +138,7 @@ struct Variant {
   int prec;  // 0 fp32, 1 fp64
   int p, s, box, vel;
   int faces = 0;  // kFaces: general polytope corridor (box is then 0)
+  int num = 0;    // 1: NumericSolve local update (L-BFGS) instead of the closed form
 };
 
 template <typename R>
@@ -142,6 +146,9 @@ hipError_t launch_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hi
 // the same launch for a general polytope corridor (v.faces = kFaces)
 template <typename R>
 hipError_t launch_poly_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
+// the same launch with the NumericSolve local update (v.num = 1)
+template <typename R>
+hipError_t launch_numeric_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
 
 // One-time setup (precompute + Init), float64 arithmetic, output in R.
 struct SetupArgs {

@@ -1,0 +1,11 @@
+// FP64 instantiations of the NumericSolve sweep kernel (64-lane tiles).
+#include "numeric_impl.h"
+
+namespace top {
+
+template <>
+hipError_t launch_numeric_sweep<double>(const Variant& v, const SweepArgs<double>& a, int n_tiles, hipStream_t st) {
+  return dispatch_numeric_sweep<double>(v, a, n_tiles, st);
+}
+
+}  // namespace top

@@ -64,8 +64,9 @@ __device__ inline double end_state(const SetupArgs& a, int P, int b, int side, i
   return o == 0 ? a.waypoints[wp_row * 3 + c] : 0.0;
 }
 
-// KF = kFaces: general polytope corridor (BOX is then false).
-template <typename R, int P, int S, bool BOX, bool VEL, int KF = 0>
+// KF = kFaces: general polytope corridor (BOX is then false).  NUM: NumericSolve state (velocity
+// multipliers w = 0 and the Init c~ kept as the first L-BFGS start) instead of the velocity split g.
+template <typename R, int P, int S, bool BOX, bool VEL, int KF = 0, bool NUM = false>
 __global__ void setup_kernel(SetupArgs a, SetupOut<R> out) {
   constexpr int N = 2 * P;
   constexpr int M = kSamples;
@@ -226,7 +227,11 @@ __global__ void setup_kernel(SetupArgs a, SetupOut<R> out) {
       }
     }
   }
-  if (VEL) {
+  if constexpr (NUM) {
+    for (int s = 0; s < M; ++s) st[(int64_t)(F_G + s) * ld + i] = (R)0;
+    for (int c = 0; c < 3; ++c)
+      for (int j = 0; j < N; ++j) st[(int64_t)(F_G + M + c * N + j) * ld + i] = (R)ct[c][j];
+  } else if (VEL) {
 #pragma unroll
     for (int s = 0; s < M; ++s) {
       double v[3];
@@ -247,6 +252,17 @@ template <typename R>
 hipError_t launch_setup(const Variant& v, const SetupArgs& a, const SetupOut<R>& o, hipStream_t st) {
   const int bs = 128;
   const dim3 grid((unsigned)((a.S + bs - 1) / bs)), block(bs);
+  if (v.num != 0) {
+    if (!v.vel || v.faces || v.s != v.p) return hipErrorInvalidValue;
+#define TOP_SETUP_NUM(P_, B_)                                                             \
+    if (v.p == P_ && (v.box != 0) == B_) {                                                \
+      hipLaunchKernelGGL((setup_kernel<R, P_, P_, B_, true, 0, true>), grid, block, 0, st, a, o); \
+      return hipGetLastError();                                                           \
+    }
+    TOP_SETUP_NUM(3, true) TOP_SETUP_NUM(3, false) TOP_SETUP_NUM(4, true) TOP_SETUP_NUM(4, false)
+#undef TOP_SETUP_NUM
+    return hipErrorInvalidValue;
+  }
   if (v.faces != 0) {
     if (v.faces != kFaces || v.box) return hipErrorInvalidValue;
 #define TOP_SETUP_POLY(P_, S_, V_)                                                        \

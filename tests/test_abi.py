@@ -61,9 +61,17 @@ def test_host_argument_errors():
     st, h, msg = _create(1, [0, 3], o)
     assert st == binding.TOP_E_UNSUPPORTED and "order" in msg
     o = binding.default_options()
-    o.n_cont = 5
+    o.n_cont = 6                      # p = 3 takes s in {3, 4, 5}
     st, h, msg = _create(1, [0, 3], o)
     assert st == binding.TOP_E_UNSUPPORTED and "n_cont" in msg
+    o = binding.default_options()
+    o.local_solve = 2
+    st, h, msg = _create(1, [0, 3], o)
+    assert st == binding.TOP_E_INVALID and "local_solve" in msg
+    o = binding.default_options()
+    o.check_every = -1
+    st, h, msg = _create(1, [0, 3], o)
+    assert st == binding.TOP_E_INVALID and "check_every" in msg
     o = binding.default_options()
     o.n_samples = 6
     st, h, msg = _create(1, [0, 3], o)
