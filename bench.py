@@ -6,7 +6,8 @@ minimum-jerk trajectories of 8..512 segments, about 1.05 M segments, box
 corridors and velocity balls, rho per trajectory, fp32 iterates, K = 200
 sweeps): top_create (intake, float64 precompute, Init) -> top_iterate(200) ->
 cost, residuals and coefficients -> top_destroy.  Inputs are float64 device
-tensors resident in HBM before the timed region starts.
+tensors resident in HBM before the timed region starts; the tile plan is
+autotuned (top_tune) once per shape class before it.
 
 value = segment-updates/s = (segments x sweeps) / (wall time per step).
 
@@ -368,6 +369,10 @@ def main():
     d = _dev_inputs(w, dev)
     torch.cuda.synchronize()
 
+    # the execution plan is autotuned once per shape class (top_tune), outside the timed region
+    pt = _problem(w, d, precision="fp32")
+    pt.tune(20)
+    pt.close()
     sec = time_steps(lambda: solve_step(w, d, K), a.steps, a.warmup)
     value = w.n_seg * K / sec
 
@@ -407,6 +412,9 @@ def main():
         extra["batched_over_plain"] = round(value / pr, 1)
         w2 = make_config(2)
         d2 = _dev_inputs(w2, dev)
+        pt = _problem(w2, d2, precision="fp32")
+        pt.tune(32)
+        pt.close()
         sec2 = time_steps(lambda: solve_step(w2, d2, w2.iters), 2, 1)
         kms2, l2, plan2 = sweep_kernel_ms(w2, d2, w2.iters)
         extra["septic_65536"] = {

@@ -30,6 +30,7 @@ struct AdjArgs {
   int W;
   int fixpos;
   const R* blk;              // forward state before sweep t of this launch at blk + t * slot
+  const R* blk0;             // or, for t = 0, here when non-null (the block's checkpoint in the tape)
   int64_t slot;
   int steps;
   const R* adj_in;           // adjoint of the state after the last sweep of this launch
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
     for (int o = 0; o < S; ++o) az0[a][o] = R(0);
 
   for (int t = A.steps - 1; t >= 0; --t) {
-    const R* st = A.blk + (int64_t)t * A.slot;
+    const R* st = (t == 0 && A.blk0 != nullptr) ? A.blk0 : A.blk + (int64_t)t * A.slot;
     const bool cost_step = A.with_cost && (t == A.steps - 1);
     const int buf = t & 1;
 

@@ -324,6 +324,8 @@ struct top_problem {
   double *wp64 = nullptr, *lo64 = nullptr, *hi64 = nullptr, *vmax64 = nullptr, *bc64 = nullptr;
   void *blk = nullptr, *adjb[2] = {nullptr, nullptr}, *acc_iT = nullptr, *acc_hd = nullptr, *acc_z0 = nullptr;
   double *dPL = nullptr, *dPR = nullptr, *dK = nullptr, *dK0 = nullptr;
+  hipStream_t rstream = nullptr;  // reverse pass: replays overlap the adjoint of the previous block
+  hipEvent_t ev_start = nullptr, ev_rep[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
   // residual checks: per-trajectory stop flag, sweep counters, current rho and the last change
   uint8_t *done_dev = nullptr, *fresh = nullptr;
   int32_t *swept = nullptr, *stop_at = nullptr;
@@ -435,7 +437,7 @@ struct top_problem {
     top::Layout L{v.p, v.s, v.box, v.vel, v.faces, v.num};
     top_status s;
     if (blk == nullptr) {
-      if ((s = alloc(&blk, (size_t)m * sl * sizeof(R))) != TOP_OK) return s;
+      if ((s = alloc(&blk, 2 * (size_t)m * sl * sizeof(R))) != TOP_OK) return s;
       for (int q = 0; q < 2; ++q)
         if ((s = alloc(&adjb[q], sl * sizeof(R))) != TOP_OK) return s;
       if ((s = alloc(&acc_iT, ld * sizeof(R))) != TOP_OK) return s;
@@ -451,28 +453,55 @@ struct top_problem {
     if ((s = chk(top::launch_fill<R>((R*)acc_iT, ld, R(0), stream))) != TOP_OK) return s;
     if ((s = chk(top::launch_fill<R>((R*)acc_hd, ld, R(0), stream))) != TOP_OK) return s;
     if ((s = chk(top::launch_fill<R>((R*)acc_z0, 3 * v.s * ld, R(0), stream))) != TOP_OK) return s;
-    int ai = 0;
-    const int nblk = (K + m - 1) / m;
-    for (int j = nblk - 1; j >= 0; --j) {
-      const int k_lo = j * m;
-      const int n = std::min(K, k_lo + m) - k_lo;
-      // replay the block from its checkpoint, keeping the state before every sweep
-      TOP_HIP(hipMemcpyAsync(blk, (char*)tape + (size_t)j * sl * sizeof(R), sl * sizeof(R),
-                             hipMemcpyDeviceToDevice, stream));
+    // Block j is replayed from its checkpoint (read in place from the tape) into block buffer j % 2,
+    // keeping the state before every sweep, then reversed.  The replay of block j - 1 needs only the
+    // tape, so it runs on a second stream while block j is reversed; the buffer it fills was last
+    // read by the reversal of block j + 1.
+    if (rstream == nullptr) {
+      TOP_HIP(hipStreamCreateWithFlags(&rstream, hipStreamNonBlocking));
+      for (hipEvent_t* e : {&ev_start, &ev_rep[0], &ev_rep[1], &ev_adj[0], &ev_adj[1]})
+        TOP_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
+    }
+    auto buf_of = [&](int q) { return (R*)blk + (size_t)q * m * sl; };
+    auto replay = [&](int j, hipStream_t st) -> top_status {
+      const int n = std::min(K, j * m + m) - j * m;
+      R* b = buf_of(j % 2);
+      const R* ckpt = (const R*)tape + (size_t)j * sl;
       // one recording launch per replay chunk (halo sweeps at most on split trajectories): the launch
-      // from slot t0 stores the states after its sweeps in slots t0+1 .. t0+cnt
+      // from slot t0 stores the states after its sweeps in slots t0+1 .. t0+cnt (slot 0 stays unused)
       for (int t0 = 0; t0 < n - 1;) {
         const int cnt = plan_ref().halo > 0 ? std::min(n - 1 - t0, plan_ref().halo) : n - 1 - t0;
         top::SweepArgs<R> a = sweep_args<R>(plan_ref(), lanes());
-        a.st_in = (const R*)blk + (size_t)t0 * sl;
-        a.st_out = (R*)blk + (size_t)(t0 + cnt) * sl;
+        a.st_in = t0 == 0 ? ckpt : b + (size_t)t0 * sl;
+        a.st_out = b + (size_t)(t0 + cnt) * sl;
         a.iters = cnt;
         a.final_out = 0;
-        a.rec = (R*)blk + (size_t)t0 * sl;
+        a.rec = b + (size_t)t0 * sl;
         a.rec_slot = (int64_t)sl;
-        if ((s = chk(top::launch_sweep<R>(v, a, plan_ref().n_tiles, stream))) != TOP_OK) return s;
+        top_status r = chk(top::launch_sweep<R>(v, a, plan_ref().n_tiles, st));
+        if (r != TOP_OK) return r;
         t0 += cnt;
       }
+      return TOP_OK;
+    };
+    int ai = 0;
+    const int nblk = (K + m - 1) / m;
+    TOP_HIP(hipEventRecord(ev_start, stream));
+    TOP_HIP(hipStreamWaitEvent(rstream, ev_start, 0));
+    if ((s = replay(nblk - 1, rstream)) != TOP_OK) return s;
+    TOP_HIP(hipEventRecord(ev_rep[(nblk - 1) % 2], rstream));
+    for (int j = nblk - 1; j >= 0; --j) {
+      const int k_lo = j * m;
+      const int n = std::min(K, k_lo + m) - k_lo;
+      const int q = j % 2;
+      if (j >= 1) {
+        if (j + 1 < nblk) TOP_HIP(hipStreamWaitEvent(rstream, ev_adj[(j - 1) % 2], 0));
+        if ((s = replay(j - 1, rstream)) != TOP_OK) return s;
+        TOP_HIP(hipEventRecord(ev_rep[(j - 1) % 2], rstream));
+      }
+      TOP_HIP(hipStreamWaitEvent(stream, ev_rep[q], 0));
+      const R* ckpt = (const R*)tape + (size_t)j * sl;
+      R* b = buf_of(q);
       int t_hi = n;
       while (t_hi > 0) {
         // Reverse steps per launch on split trajectories: halo - 1.  A wrong value entering at a
@@ -487,7 +516,8 @@ struct top_problem {
         a.lane_seg = lanes();
         a.W = plan_ref().W;
         a.fixpos = opt.fix_interior;
-        a.blk = (const R*)blk + (size_t)t_lo * sl;
+        a.blk = b + (size_t)t_lo * sl;
+        a.blk0 = t_lo == 0 ? ckpt : nullptr;
         a.slot = (int64_t)sl;
         a.steps = cnt;
         a.adj_in = (const R*)adjb[ai];
@@ -501,6 +531,7 @@ struct top_problem {
         ai ^= 1;
         t_hi = t_lo;
       }
+      TOP_HIP(hipEventRecord(ev_adj[q], stream));
     }
     top::InitAdjArgs<R> ia{};
     ia.waypoints = wp64;
@@ -677,6 +708,12 @@ void top_destroy(top_problem* h) {
   (void)hipStreamSynchronize(h->stream);
   h->drop_graphs();
   if (h->cap_stream != nullptr) (void)hipStreamDestroy(h->cap_stream);
+  if (h->rstream != nullptr) {
+    (void)hipStreamSynchronize(h->rstream);
+    (void)hipStreamDestroy(h->rstream);
+  }
+  for (hipEvent_t e : {h->ev_start, h->ev_rep[0], h->ev_rep[1], h->ev_adj[0], h->ev_adj[1]})
+    if (e != nullptr) (void)hipEventDestroy(e);
   for (auto& b : h->allocs) pool_put(b.p, b.bytes, b.dev);
   delete h;
 }
