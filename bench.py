@@ -224,32 +224,110 @@ def fwd_bwd(w, d, K, m, reps=3):
             "fwd_plus_bwd_segment_updates_per_s": round(w.n_seg * K / (f + b), 1)}
 
 
-def cpu_baseline(w, K, target_s=12.0):
-    """The float64 CPU oracle, as it stands, on the first trajectories of the same workload."""
-    import torch
-    from oracle import cadmm
-    # size the sample from a short probe so the run takes roughly target_s seconds
-    probe = w.subset(range(4))
-    pr = cadmm.problem_from_workload(probe)
-    t0 = time.perf_counter()
-    cadmm.run(pr, 10)
-    rate = probe.n_seg * 10 / (time.perf_counter() - t0)
-    want = rate * target_s / K
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _first_trajectories(w, n_seg_wanted):
     nb, segs = 0, 0
     L = w.traj_lengths()
-    while nb < w.n_traj and segs + L[nb] <= max(want, L[0]):
+    while nb < w.n_traj and segs + L[nb] <= max(n_seg_wanted, L[0]):
         segs += int(L[nb])
         nb += 1
-    nb = max(nb, 1)
-    sub = w.subset(range(nb))
-    pr = cadmm.problem_from_workload(sub)
-    t0 = time.perf_counter()
-    cadmm.run(pr, K)
-    dt = time.perf_counter() - t0
-    return {"value": sub.n_seg * K / dt, "unit": "segment-updates/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"first {nb} trajectories ({sub.n_seg} segments) x {K} sweeps, float64 torch-CPU, "
-                      f"{dt:.1f} s"}
+    return max(nb, 1)
+
+
+def cpu_baseline(w, K, run_s=4.0):
+    """The float64 CPU oracle, as it stands, on the first trajectories of the same workload.
+
+    Median of three runs on all host threads, each sized to about run_s seconds, plus one run on a
+    single thread (the sequential analogue) on a sample sized the same way.
+    """
+    import torch
+    from oracle import cadmm
+
+    def rate_probe():
+        probe = w.subset(range(4))
+        pr = cadmm.problem_from_workload(probe)
+        t0 = time.perf_counter()
+        cadmm.run(pr, 10)
+        return probe.n_seg * 10 / (time.perf_counter() - t0)
+
+    def timed(nb):
+        sub = w.subset(range(nb))
+        pr = cadmm.problem_from_workload(sub)
+        t0 = time.perf_counter()
+        cadmm.run(pr, K)
+        return sub.n_seg, time.perf_counter() - t0
+
+    threads = torch.get_num_threads()
+    nb = _first_trajectories(w, rate_probe() * run_s / K)
+    # the short probe under-states the rate of larger samples: resize once from a full-K run
+    n0, dt0 = timed(nb)
+    if dt0 < 0.6 * run_s:
+        nb = _first_trajectories(w, n0 * run_s / dt0)
+    runs = [timed(nb) for _ in range(3)]
+    n_seg = runs[0][0]
+    dts = sorted(dt for _, dt in runs)
+    torch.set_num_threads(1)
+    try:
+        nb1 = _first_trajectories(w, rate_probe() * run_s / K)
+        n1, dt1 = timed(nb1)
+    finally:
+        torch.set_num_threads(threads)
+    return {"value": n_seg * K / dts[1], "unit": "segment-updates/s", "cores": threads,
+            "kind": "oracle", "cpu_model": _cpu_model(),
+            "sample": f"first {nb} trajectories ({n_seg} segments) x {K} sweeps, float64 torch-CPU, "
+                      f"median of 3 runs ({', '.join(f'{dt:.1f}' for dt in dts)} s)",
+            "single_thread": {"value": n1 * K / dt1, "cores": 1,
+                              "sample": f"first {nb1} trajectories ({n1} segments) x {K} sweeps, {dt1:.1f} s"}}
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Device-to-device copy rate (bytes read + written per second), median of reps, HIP events."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    times = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    return 2 * nbytes / sorted(times)[reps // 2]
+
+
+def phase_ms(w, d, K, reps=3):
+    """Median host wall time of create, iterate(K) and outputs + destroy, each ended by a device sync."""
+    import torch
+    acc = {"create": [], "iterate": [], "outputs_and_destroy": []}
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob = _problem(w, d, precision="fp32")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        prob.iterate(K)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        _ = (prob.cost(), prob.residuals(), prob.coeffs())
+        prob.close()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        for k, v in zip(acc, (t1 - t0, t2 - t1, t3 - t2)):
+            acc[k].append(v * 1e3)
+    return {k: round(sorted(v)[reps // 2], 3) for k, v in acc.items()}
 
 
 def calib_copy(nbytes=1 << 30):
@@ -398,12 +476,16 @@ def main():
                        "constraints": "box+velocity", "tile_lanes": plan["tile_lanes"],
                        "n_tiles": plan["n_tiles"]},
             "roofline": roofline}
+    copy_bps = copy_bandwidth()
     hbm = {"bytes_per_segment_update": bpu,
            "equiv_GBps": round(bpu * sweep_rate / 1e9, 1),
            "frac_of_8TBps": round(bpu * sweep_rate / HBM_PEAK, 3),
+           "measured_copy_GBps": round(copy_bps / 1e9, 1),
+           "frac_of_measured_copy": round(bpu * sweep_rate / copy_bps, 3),
            "regime": "state stays on chip across sweeps (VALU-bound); the yardstick counts one read "
                      "and one write of the minimal state per segment-update"}
-    extra = {"sweep_only_segment_updates_per_s": round(sweep_rate, 1), "hbm_yardstick": hbm}
+    extra = {"sweep_only_segment_updates_per_s": round(sweep_rate, 1), "hbm_yardstick": hbm,
+             "phases_ms": phase_ms(w, d, K)}
     if not a.no_extras:
         nplain = 128
         pr = plain_rate(w, d, K, nplain)
@@ -416,11 +498,13 @@ def main():
         pt.tune(32)
         pt.close()
         sec2 = time_steps(lambda: solve_step(w2, d2, w2.iters), 2, 1)
+        ph2 = phase_ms(w2, d2, w2.iters)
         kms2, l2, plan2 = sweep_kernel_ms(w2, d2, w2.iters)
         extra["septic_65536"] = {
             "segment_updates_per_s": round(w2.n_seg * w2.iters / sec2, 1),
             "sweep_only_segment_updates_per_s": round(w2.n_seg * w2.iters / (kms2 * 1e-3), 1),
-            "ms_per_solve": round(sec2 * 1e3, 3), "tile_lanes": plan2["tile_lanes"], "halo": plan2["halo"],
+            "ms_per_solve": round(sec2 * 1e3, 3), "phases_ms": ph2, "tile_lanes": plan2["tile_lanes"],
+            "halo": plan2["halo"],
             "alu_frac": round(flops_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters / (kms2 * 1e-3)
                               / PEAK_FP32_NONPACKED, 4),
             "hbm_yardstick_frac": round(bytes_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters

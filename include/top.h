@@ -191,7 +191,8 @@ top_status top_convergence(const top_problem* h, int32_t* iters, double* rho, ui
 top_status top_sync_status(top_problem* h);
 
 /* Copy of the iterate state (checkpoint and resume), in the iterate precision (float or double),
- * structure of arrays: n_fields rows of ld elements (top_plan_info), row f, segment i at f * ld + i.
+ * structure of arrays: n_fields rows of ld elements (top_plan_info), row f, segment i at f * ld + i;
+ * columns S..ld-1 are padding (zero unless a set state put other values there; never read).
  * Rows, with s = n_cont, M = 8, n = 2p, per axis a = 0..2 and order o < s, sample j < M:
  *   z_R  (end knot of the segment, orders 0..s-1)      rows a*s + o
  *   u_L, u_R (scaled consensus duals, start / end knot)  rows 3s + a*s + o, 6s + a*s + o

@@ -308,6 +308,23 @@ struct top_problem {
   double *Tdev = nullptr, *rho_seg = nullptr, *part = nullptr, *out = nullptr;
   int64_t* off_dev = nullptr;
   int* flag_dev = nullptr;
+  // chunked per-trajectory reduction (host copies stay alive until the uploads have run)
+  std::vector<int32_t> chunk_traj_h, chunk_off_h;
+  int32_t *chunk_traj = nullptr, *chunk_off = nullptr;
+  double* chunk_sum = nullptr;
+  top::ReduceArgs reduce_args() const {
+    top::ReduceArgs a{};
+    a.part = part;
+    a.S = S;
+    a.off = off_dev;
+    a.B = B;
+    a.chunk_traj = chunk_traj;
+    a.chunk_off = chunk_off;
+    a.n_chunks = (int)chunk_traj_h.size();
+    a.chunk_sum = chunk_sum;
+    a.out = out;
+    return a;
+  }
   std::shared_ptr<PlanEntry> pe;
   Plan empty_plan;
   const Plan& plan_ref() const { return pe ? pe->plan : empty_plan; }
@@ -590,7 +607,7 @@ struct top_problem {
     top_status s = finalize(nullptr, true, true, st);
     cur = save;
     if (s != TOP_OK) return s;
-    hipError_t e = top::launch_reduce(part, S, off_dev, B, out, st);
+    hipError_t e = top::launch_reduce(reduce_args(), st);
     if (e != hipSuccess) return fail(TOP_E_HIP, "reduce launch failed: %s", hipGetErrorString(e));
     top::CheckArgs ca{};
     ca.res = out;
@@ -670,7 +687,7 @@ struct top_problem {
     top_status s = finalize(nullptr, true, true, st);
     cur = save;
     if (s != TOP_OK) return s;
-    hipError_t e = top::launch_reduce(part, S, off_dev, B, out, st);
+    hipError_t e = top::launch_reduce(reduce_args(), st);
     if (e != hipSuccess) return fail(TOP_E_HIP, "reduce launch failed: %s", hipGetErrorString(e));
     return TOP_OK;
   }
@@ -812,8 +829,15 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   if ((st = h->alloc(&h->hi, 3 * ld * R)) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->vmax, ld * R)) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->bcL, (size_t)n_traj * 3 * s * R)) != TOP_OK) return bail(st);
-  for (int q = 0; q < 2; ++q)
+  for (int q = 0; q < 2; ++q) {
     if ((st = h->alloc(&h->state[q], (size_t)h->nf * ld * R)) != TOP_OK) return bail(st);
+    // no lane owns the padding columns S..ld-1; zero them so exported states are deterministic
+    if (ld > (size_t)S) {
+      hipError_t e = hipMemset2DAsync((char*)h->state[q] + (size_t)S * R, ld * R, 0, (ld - (size_t)S) * R,
+                                      (size_t)h->nf, stream);
+      if (e != hipSuccess) return bail(fail(TOP_E_HIP, "state padding reset failed: %s", hipGetErrorString(e)));
+    }
+  }
   if ((st = h->alloc(&h->cbuf, 3 * (size_t)L.n() * ld * R)) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->zold, 3 * (size_t)s * ld * R)) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->flags, ld)) != TOP_OK) return bail(st);
@@ -825,6 +849,24 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   if ((st = h->alloc(&h->off_dev, (size_t)(n_traj + 1) * sizeof(int64_t))) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->flag_dev, 2 * sizeof(int))) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->rho_traj, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
+  h->chunk_off_h.resize((size_t)n_traj + 1);
+  h->chunk_off_h[0] = 0;
+  for (int b = 0; b < n_traj; ++b) {
+    const int64_t nc = (seg_offsets[b + 1] - seg_offsets[b] + top::kReduceChunk - 1) / top::kReduceChunk;
+    h->chunk_off_h[b + 1] = h->chunk_off_h[b] + (int32_t)nc;
+    for (int64_t j = 0; j < nc; ++j) h->chunk_traj_h.push_back(b);
+  }
+  {
+    const size_t nc = h->chunk_traj_h.size();
+    if ((st = h->alloc(&h->chunk_off, ((size_t)n_traj + 1) * sizeof(int32_t))) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->chunk_traj, std::max<size_t>(nc, 1) * sizeof(int32_t))) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->chunk_sum, 3 * std::max<size_t>(nc, 1) * sizeof(double))) != TOP_OK) return bail(st);
+    hipError_t e = hipMemcpyAsync(h->chunk_off, h->chunk_off_h.data(), ((size_t)n_traj + 1) * sizeof(int32_t),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && nc > 0)
+      e = hipMemcpyAsync(h->chunk_traj, h->chunk_traj_h.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "copy of the reduction chunks failed: %s", hipGetErrorString(e)));
+  }
   if (opt.check_every > 0) {
     if ((st = h->alloc(&h->done_dev, (size_t)n_traj)) != TOP_OK) return bail(st);
     if ((st = h->alloc(&h->fresh, (size_t)n_traj)) != TOP_OK) return bail(st);
@@ -917,7 +959,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   // cost of the Init guess (residuals stay undefined until the first sweep)
   if ((st = h->finalize(nullptr, false, true, stream)) != TOP_OK) return bail(st);
   {
-    hipError_t e = top::launch_reduce(h->part, S, h->off_dev, n_traj, h->out, stream);
+    hipError_t e = top::launch_reduce(h->reduce_args(), stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "reduce launch failed: %s", hipGetErrorString(e)));
   }
   // execution plan: explicit, tuned for this shape class, or the default

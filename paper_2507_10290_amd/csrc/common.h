@@ -206,10 +206,24 @@ struct FinalArgs {
 template <typename R>
 hipError_t launch_finalize(const Variant& v, const FinalArgs<R>& a, hipStream_t st);
 
-// Per-trajectory sums of the partials in a fixed order: out[0][b] = cost, out[1][b] = ||r_p||,
-// out[2][b] = ||r_d|| (square roots taken).
-hipError_t launch_reduce(const double* part, int64_t S, const int64_t* seg_off, int B, double* out,
-                         hipStream_t st);
+// Per-trajectory sums of the per-segment partials part[3][S] in a fixed order: out[0][b] = cost,
+// out[1][b] = ||r_p||, out[2][b] = ||r_d|| (square roots taken).  Each trajectory is cut into chunks of
+// kReduceChunk segments (chunk j of trajectory b covers segments off[b] + j*kReduceChunk onwards); one
+// workgroup sums a chunk, then one lane per trajectory adds its chunk sums in order.  The order depends
+// only on the segment offsets, not on the sweep's tiling.
+constexpr int kReduceChunk = 4096;
+struct ReduceArgs {
+  const double* part;        // [3][S]
+  int64_t S;
+  const int64_t* off;        // [B + 1] segment offsets
+  int B;
+  const int32_t* chunk_traj; // [n_chunks] trajectory of each chunk (chunks of a trajectory are consecutive)
+  const int32_t* chunk_off;  // [B + 1] first chunk of each trajectory
+  int n_chunks;
+  double* chunk_sum;         // [3][n_chunks] scratch
+  double* out;               // [3][B]
+};
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 
 hipError_t launch_copy_rows(const double* src, double* dst, int B, hipStream_t st);
 

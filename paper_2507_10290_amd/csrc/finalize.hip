@@ -102,24 +102,54 @@ hipError_t launch_finalize(const Variant& v, const FinalArgs<R>& a, hipStream_t 
 template hipError_t launch_finalize<float>(const Variant&, const FinalArgs<float>&, hipStream_t);
 template hipError_t launch_finalize<double>(const Variant&, const FinalArgs<double>&, hipStream_t);
 
-// One 64-lane wave per trajectory; lane l sums segments l, l+64, ... in order, then a fixed
-// shuffle tree: the result does not depend on how the sweep was tiled.
-__global__ void reduce_kernel(const double* part, int64_t S, const int64_t* off, int B, double* out) {
-  const int b = blockIdx.x;
-  const int lane = threadIdx.x;
-  if (b >= B) return;
-  const int64_t s0 = off[b], s1 = off[b + 1];
-  for (int q = 0; q < 3; ++q) {
-    double acc = 0.0;
-    for (int64_t i = s0 + lane; i < s1; i += 64) acc += part[q * S + i];
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o);
-    if (lane == 0) out[(int64_t)q * B + b] = (q == 0) ? acc : sqrt(acc);
+// Stage 1: one 256-lane workgroup per chunk.  Lane l sums segments l, l+256, ... of the chunk in
+// order, each wave folds its lanes with a fixed shuffle tree, and lane 0 adds the four wave sums in
+// order.  The three quantities are summed together so their loads overlap.
+__global__ void __launch_bounds__(256) reduce_chunks_kernel(ReduceArgs a) {
+  __shared__ double wsum[3][4];
+  const int c = blockIdx.x;
+  if (c >= a.n_chunks) return;
+  const int b = a.chunk_traj[c];
+  const int64_t s0 = a.off[b] + (int64_t)(c - a.chunk_off[b]) * kReduceChunk;
+  const int64_t s1 = s0 + kReduceChunk < a.off[b + 1] ? s0 + kReduceChunk : a.off[b + 1];
+  const int t = threadIdx.x;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  for (int64_t i = s0 + t; i < s1; i += 256) {
+    acc0 += a.part[i];
+    acc1 += a.part[a.S + i];
+    acc2 += a.part[2 * a.S + i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    acc0 += __shfl_down(acc0, o);
+    acc1 += __shfl_down(acc1, o);
+    acc2 += __shfl_down(acc2, o);
+  }
+  if ((t & 63) == 0) {
+    wsum[0][t >> 6] = acc0;
+    wsum[1][t >> 6] = acc1;
+    wsum[2][t >> 6] = acc2;
+  }
+  __syncthreads();
+  if (t < 3) {
+    const double v = ((wsum[t][0] + wsum[t][1]) + wsum[t][2]) + wsum[t][3];
+    a.chunk_sum[(int64_t)t * a.n_chunks + c] = v;
   }
 }
 
-hipError_t launch_reduce(const double* part, int64_t S, const int64_t* off, int B, double* out,
-                         hipStream_t st) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(B), dim3(64), 0, st, part, S, off, B, out);
+// Stage 2: one lane per trajectory adds its chunk sums in chunk order.
+__global__ void reduce_traj_kernel(ReduceArgs a) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= a.B) return;
+  for (int q = 0; q < 3; ++q) {
+    double acc = 0.0;
+    for (int c = a.chunk_off[b]; c < a.chunk_off[b + 1]; ++c) acc += a.chunk_sum[(int64_t)q * a.n_chunks + c];
+    a.out[(int64_t)q * a.B + b] = (q == 0) ? acc : sqrt(acc);
+  }
+}
+
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st) {
+  if (a.n_chunks > 0) hipLaunchKernelGGL(reduce_chunks_kernel, dim3(a.n_chunks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(reduce_traj_kernel, dim3((a.B + 255) / 256), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

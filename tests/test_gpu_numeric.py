@@ -82,7 +82,7 @@ def _check_steps(w, inner, Ks, floor, rel, box, **kw):
         if K > done:
             prob.iterate(K - done)
             done = K
-        st = prob.get_state().cpu().numpy().astype(np.float64)
+        st = prob.get_state()[:, :pr.S].cpu().numpy().astype(np.float64)
         ost = _oracle_state(pr, mats, st, box)
         nxt, cj = _jitter_step(pr, mats, ost, inner, rel)
         prob.iterate(1)
@@ -134,7 +134,9 @@ def test_fp32_numeric_steps_close_to_oracle():
 def test_state_round_trip_and_resume():
     w = random_walk_batch("numrt", [5, 4], [28, 29], order=3, vmax=1.5, precision="fp64")
     a, b = _problem(w, 8), _problem(w, 8)
+    assert a.get_state().shape[1] > a.S and (a.get_state()[:, a.S:] == 0).all()   # padding columns
     a.iterate(6)
+    assert (a.get_state()[:, a.S:] == 0).all()
     b.set_state(a.get_state())
     a.iterate(3)
     b.iterate(3)

@@ -155,6 +155,24 @@ def test_config2_full_light_cone_samples():
         assert e <= 1e-4
 
 
+def test_long_trajectory_reductions_fp64():
+    # one trajectory of 9,000 segments (three reduction chunks of 4,096, the last ragged) between
+    # two short ones: cost and both residual norms against the oracle
+    w = random_walk_batch("longred", [5, 9000, 3], [41, 42, 43], order=3, rho=1.0, precision="fp64")
+    _check(w, 3, "fp64")
+
+
+def test_config2_full_cost_sums_its_coefficients():
+    # the reported cost of the 65,536-segment trajectory equals the float64 cost of its own coefficients
+    from oracle import cadmm
+    w = make_config(2)
+    cg, Jg, _, _ = run_gpu(w, 4, "fp32")
+    pr = cadmm.problem_from_workload(w)
+    Jc = cadmm.cost(pr, torch.from_numpy(cg).reshape(w.n_seg, -1)).numpy()
+    print(f"[parity] config2 cost {Jg[0]:.12e} vs own coefficients {Jc[0]:.12e}", flush=True)
+    assert rel(Jg, Jc) <= 1e-9
+
+
 # ---------------------------------------------------------------------------
 # Execution-form invariances (bitwise).
 # ---------------------------------------------------------------------------
