@@ -364,14 +364,16 @@ def sweep_source_digest() -> str:
 
 
 def _counter_rows(path, counter):
-    """(kernel name, value) per dispatch of one counter from a rocprofv3 counter_collection.csv."""
+    """(kernel name, grid size, value) per dispatch of one counter, in dispatch order, from a rocprofv3
+    counter_collection.csv."""
     import csv
     rows = []
     with open(path) as fh:
         for r in csv.DictReader(fh):
             if r.get("Counter_Name") == counter:
-                rows.append((r.get("Kernel_Name", ""), float(r["Counter_Value"])))
-    return rows
+                rows.append((int(r.get("Dispatch_Id", 0)), r.get("Kernel_Name", ""), int(r.get("Grid_Size", 0)),
+                             float(r["Counter_Value"])))
+    return [x[1:] for x in sorted(rows)]
 
 
 def counters_summary(fetch_csv, write_csv, calib_bytes=1 << 30):
@@ -380,8 +382,11 @@ def counters_summary(fetch_csv, write_csv, calib_bytes=1 << 30):
     out = {}
     for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         rows = _counter_rows(path, name)
-        sweep = [v for k, v in rows if "sweep_kernel" in k and "float, 3, 3, true, true" in k]
-        calib = [v for k, v in rows if CALIB_KERNEL in k.lower() and "elementwise" in k.lower()]
+        # the timed launches: the batched plan's kernel and grid, as used by the last sweep dispatch
+        # (autotune probes of other tile shapes run before it)
+        cand = [(k, g, v) for k, g, v in rows if "sweep_kernel<float, 3, 3, true, true, 512" in k]
+        sweep = [v for k, g, v in cand if cand and g == cand[-1][1]]
+        calib = [v for k, g, v in rows if CALIB_KERNEL in k.lower() and "elementwise" in k.lower()]
         if not sweep or not calib:
             raise SystemExit(f"{path}: no {name} rows for the sweep kernel or the calibration copy")
         kib_cal = max(calib)                  # the 1 GiB copy is the largest elementwise mul dispatch
