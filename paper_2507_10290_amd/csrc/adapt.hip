@@ -72,7 +72,7 @@ hipError_t launch_freeze_copy(const void* cur, void* other, const uint8_t* fresh
 
 // KF = kFaces: polytope corridor (one y per face and sample, one matrix per rotated axis).
 template <typename R, int P, int S, bool BOX, bool VEL, int KF = 0>
-__global__ void rescale_kernel(RescaleArgs<R> a) {
+__global__ void __launch_bounds__(128) rescale_kernel(RescaleArgs<R> a) {
   constexpr int N = 2 * P;
   constexpr int M = kSamples;
   constexpr int F_UL = 3 * S, F_YH = 9 * S;

@@ -6,7 +6,7 @@
 namespace top {
 
 template <typename R, int P, int S>
-__global__ void finalize_kernel(FinalArgs<R> a) {
+__global__ void __launch_bounds__(256) finalize_kernel(FinalArgs<R> a) {
   constexpr int N = 2 * P;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= a.S) return;

@@ -22,7 +22,7 @@ template hipError_t launch_fill<float>(float*, int64_t, float, hipStream_t);
 template hipError_t launch_fill<double>(double*, int64_t, double, hipStream_t);
 
 template <typename R, int P, int S, bool BOX, bool VEL>
-__global__ void init_adjoint_kernel(InitAdjArgs<R> a) {
+__global__ void __launch_bounds__(128) init_adjoint_kernel(InitAdjArgs<R> a) {
   constexpr int N = 2 * P;
   constexpr int M = kSamples;
   constexpr int F_ZR = 0, F_YH = 9 * S;

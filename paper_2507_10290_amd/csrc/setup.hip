@@ -14,46 +14,45 @@
 
 namespace top {
 
-__global__ void validate_kernel(SetupArgs a, int p, int* bad) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Every input array is checked as a flat array, one element per lane and grid-stride, so the loads
+// are coalesced whatever the array's row length (a polytope row is 4 * n_faces doubles).
+__global__ void __launch_bounds__(256) validate_kernel(SetupArgs a, int p, int* bad) {
+  const int64_t n_box = 3 * a.S, n_faces = a.faces != nullptr ? (int64_t)4 * a.n_faces * a.S : 0;
+  const int64_t n_wp = 3 * (a.S + a.B), n_bc = a.bc != nullptr ? (int64_t)6 * p * a.B : 0;
+  int64_t n = a.S > n_box ? a.S : n_box;
+  n = n > n_faces ? n : n_faces;
+  n = n > n_wp ? n : n_wp;
+  n = n > n_bc ? n : n_bc;
   int flag = 0;
-  if (i < a.S) {
-    const double T = a.durations[i];
-    if (!(T > 0.0) || !isfinite(T)) flag |= 1;
-    if (a.box_lo != nullptr) {
-      for (int c = 0; c < 3; ++c) {
-        const double lo = a.box_lo[i * 3 + c], hi = a.box_hi[i * 3 + c];
-        if (!isfinite(lo) || !isfinite(hi) || !(lo < hi)) flag |= 2;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < a.S) {
+      const double T = a.durations[i];
+      if (!(T > 0.0) || !isfinite(T)) flag |= 1;
+    }
+    if (a.box_lo != nullptr && i < n_box) {
+      const double lo = a.box_lo[i], hi = a.box_hi[i];
+      if (!isfinite(lo) || !isfinite(hi) || !(lo < hi)) flag |= 2;
+    }
+    if (i < n_faces && !isfinite(a.faces[i])) flag |= 64;
+    if (i < n_wp && !isfinite(a.waypoints[i])) flag |= 4;
+    if (i < a.B) {
+      const double r = a.rho[i];
+      if (!(r > 0.0) || !isfinite(r)) flag |= 8;
+      if (a.vmax != nullptr) {
+        const double v = a.vmax[i];
+        if (!(v > 0.0) || !isfinite(v)) flag |= 16;
       }
     }
-  }
-  if (i < a.S && a.faces != nullptr) {
-    for (int q = 0; q < 4 * a.n_faces; ++q)
-      if (!isfinite(a.faces[i * 4 * a.n_faces + q])) flag |= 64;
-  }
-  if (i < a.S + a.B) {
-    for (int c = 0; c < 3; ++c)
-      if (!isfinite(a.waypoints[i * 3 + c])) flag |= 4;
-  }
-  if (i < a.B) {
-    const double r = a.rho[i];
-    if (!(r > 0.0) || !isfinite(r)) flag |= 8;
-    if (a.vmax != nullptr) {
-      const double v = a.vmax[i];
-      if (!(v > 0.0) || !isfinite(v)) flag |= 16;
-    }
-    if (a.bc != nullptr) {
-      for (int q = 0; q < 2 * p * 3; ++q)
-        if (!isfinite(a.bc[i * 2 * p * 3 + q])) flag |= 32;
-    }
+    if (i < n_bc && !isfinite(a.bc[i])) flag |= 32;
   }
   if (flag) atomicOr(bad, flag);
 }
 
 hipError_t launch_validate(const SetupArgs& a, int p, int* bad, hipStream_t st) {
-  const int64_t n = a.S + a.B;
+  const int64_t n = 4 * (int64_t)(a.faces != nullptr ? a.n_faces : 1) * a.S + 3 * (int64_t)a.B;
   const int bs = 256;
-  const int64_t nb = (n + bs - 1) / bs;
+  int64_t nb = (n + bs - 1) / bs;
+  if (nb > 4096) nb = 4096;  // grid-stride beyond 4096 workgroups
   hipLaunchKernelGGL(validate_kernel, dim3((unsigned)nb), dim3(bs), 0, st, a, p, bad);
   return hipGetLastError();
 }
@@ -67,7 +66,7 @@ __device__ inline double end_state(const SetupArgs& a, int P, int b, int side, i
 // KF = kFaces: general polytope corridor (BOX is then false).  NUM: NumericSolve state (velocity
 // multipliers w = 0 and the Init c~ kept as the first L-BFGS start) instead of the velocity split g.
 template <typename R, int P, int S, bool BOX, bool VEL, int KF = 0, bool NUM = false>
-__global__ void setup_kernel(SetupArgs a, SetupOut<R> out) {
+__global__ void __launch_bounds__(128) setup_kernel(SetupArgs a, SetupOut<R> out) {
   constexpr int N = 2 * P;
   constexpr int M = kSamples;
   constexpr int F_ZR = 0, F_UL = 3 * S, F_UR = 6 * S, F_YH = 9 * S;

@@ -252,7 +252,26 @@ def test_invalid_device_inputs_are_rejected():
     lo[0, 0] = w.box_hi[0, 0] + 1
     with pytest.raises(TopError, match="box"):
         TopProblem(w.seg_offsets, w.waypoints, w.durations, w.rho, box_lo=lo, box_hi=w.box_hi)
-    prob = TopProblem(w.seg_offsets, w.waypoints, w.durations, w.rho)
+    # last elements of each flat array (the check runs one element per lane)
+    bad = w.waypoints.copy()
+    bad[-1, 2] = np.inf
+    with pytest.raises(TopError, match="waypoints"):
+        TopProblem(w.seg_offsets, bad, w.durations, w.rho)
+    hi = w.box_hi.copy()
+    hi[-1, 2] = np.nan
+    with pytest.raises(TopError, match="box"):
+        TopProblem(w.seg_offsets, w.waypoints, w.durations, w.rho, box_lo=w.box_lo, box_hi=hi)
+    T = w.durations.copy()
+    T[-1] = -1.0
+    with pytest.raises(TopError, match="durations"):
+        TopProblem(w.seg_offsets, w.waypoints, T, w.rho)
+    with pytest.raises(TopError, match="vmax"):
+        TopProblem(w.seg_offsets, w.waypoints, w.durations, w.rho, vmax=np.zeros_like(w.rho))
+    bc = np.zeros((w.n_traj, 2, 3, 3))
+    bc[-1, 1, 2, 2] = np.nan
+    with pytest.raises(TopError, match="bc"):
+        TopProblem(w.seg_offsets, w.waypoints, w.durations, w.rho, bc=bc)
+    prob = TopProblem(w.seg_offsets, w.waypoints, w.durations, w.rho, bc=np.zeros((w.n_traj, 2, 3, 3)))
     with pytest.raises(TopError, match="TOP_E_STATE"):
         prob.residuals()
     prob.close()

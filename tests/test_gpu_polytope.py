@@ -135,3 +135,7 @@ def test_polytope_errors():
     wn.faces[1, 2, 3] = np.nan
     with pytest.raises(TopError, match="faces"):
         TopProblem.from_workload(wn)
+    wn = copy.deepcopy(w)
+    wn.faces[-1, -1, 0] = np.inf                 # the last element of the flat face array
+    with pytest.raises(TopError, match="faces"):
+        TopProblem.from_workload(wn)
