@@ -27,7 +27,9 @@
  *     every output buffer.
  *   - Every call that launches work is asynchronous on the handle's stream:
  *     outputs are ready once that stream has been synchronised.
- *   - A handle is not thread-safe; use one handle per host thread.
+ *   - A handle is not thread-safe; use one handle per host thread.  It belongs
+ *     to the device that was current at top_create (its stream's device):
+ *     make that device current for every later call on it.
  *   - Errors: every call returns a top_status.  Argument errors are reported
  *     before any work is queued and leave the handle unchanged.  A non-finite
  *     iterate is flagged on the device and reported by top_sync_status.
@@ -171,7 +173,9 @@ top_status top_coeffs(const top_problem* h, double* coeffs);
  *   dcost       [dev] float64 [B]
  *   dwaypoints  [dev] float64 [S+B][3] (overwritten), or NULL
  *   ddurations  [dev] float64 [S] (overwritten), or NULL
- * TOP_E_STATE without a tape or after too many sweeps. */
+ * TOP_E_STATE without a tape or after too many sweeps.  The block replays run on a second stream
+ * the handle creates on first use (default priority), joined back into the handle's stream before
+ * any reverse step that needs them; the call is asynchronous on the handle's stream like the others. */
 top_status top_backward(top_problem* h, const double* dcost, double* dwaypoints, double* ddurations);
 
 /* Time the candidate tile shapes on this problem (k_probe sweeps each, on scratch state, leaving the

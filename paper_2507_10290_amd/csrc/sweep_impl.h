@@ -209,10 +209,19 @@ __device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh
   knot_exchange<FINAL, P, S>(L, xL, xR, xr_sh, xl_sh, wl, wid, nw, zfin);
 }
 
+// Waves per SIMD the compiler must leave room for.  The float32 septic box + velocity instance
+// needs a few VGPRs more than half the file; held to two waves per SIMD, a CU keeps two 256-lane
+// tiles resident, which pays when a launch has more tiles than CUs (one long trajectory).
+template <typename R, int P, int S, bool BOX, bool VEL, bool REC>
+constexpr int sweep_min_waves() {
+  return (sizeof(R) == 4 && P == 4 && S == 4 && BOX && VEL && !REC) ? 2 : 1;
+}
+
 // REC: the instance used to replay checkpoint blocks for the reverse pass; it also stores the state
 // after every sweep but the last (the ordinary instance never stores inside its sweep loop).
 template <typename R, int P, int S, bool BOX, bool VEL, int LB, bool REC = false>
-__global__ __launch_bounds__(LB) void sweep_kernel(SweepArgs<R> A) {
+__global__ __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<R, P, S, BOX, VEL, REC>())))
+void sweep_kernel(SweepArgs<R> A) {
   using LT = Lane<R, P, S, BOX, VEL>;
   constexpr int N = LT::N;
   constexpr int NH = LT::NH;
