@@ -231,7 +231,10 @@ typedef struct top_plan_info {
 
 top_status top_get_plan(const top_problem* h, top_plan_info* info);
 
-/* Release the handle and every device buffer it owns (waits for its stream first). NULL is a no-op. */
+/* Release the handle; NULL is a no-op.  Its device buffers return to the library's pool without
+ * waiting for the work still queued on the handle's stream: a later handle on the same stream reuses
+ * them in stream order, one on another stream first waits (on the device) for that work.  Handles
+ * that captured graphs or ran top_backward wait for their stream first. */
 void top_destroy(top_problem* h);
 
 /* Thread-local text of the last error reported by this library on the calling thread. */

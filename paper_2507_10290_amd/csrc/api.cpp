@@ -171,15 +171,31 @@ void tune_cache_store() {
 
 // ---- device memory pool: blocks released by top_destroy are kept per (device, size class) and
 // handed to the next handle that asks for the same size class, so repeated problems of one shape
-// do not call hipMalloc/hipFree.  Released blocks were synchronised with their stream first.
+// do not call hipMalloc/hipFree.  top_destroy does not wait for the handle's queued work: each
+// released block carries the stream it was last used on and an event recorded there at release.
+// A handle on the same stream reuses it at once (stream order puts its work after the old work);
+// a handle on another stream first makes its stream wait for that event.
 size_t size_class(size_t b) {
   const size_t g = b < (size_t(2) << 20) ? size_t(4096) : (size_t(2) << 20);
   return (b + g - 1) / g * g;
 }
 
+struct ReleaseEvent {  // shared by the blocks of one released handle
+  hipEvent_t ev = nullptr;
+  ~ReleaseEvent() {
+    if (ev != nullptr) (void)hipEventDestroy(ev);
+  }
+};
+
+struct PoolBlock {
+  void* p;
+  hipStream_t stream;                   // last used on this stream
+  std::shared_ptr<ReleaseEvent> done;   // recorded there at release; null: no pending work
+};
+
 struct Pool {
   std::mutex mu;
-  std::multimap<std::pair<int, size_t>, void*> blocks;
+  std::multimap<std::pair<int, size_t>, PoolBlock> blocks;
   size_t cached = 0;
   size_t cap() const {
     const char* e = std::getenv("TOP_POOL_MAX_BYTES");
@@ -188,33 +204,47 @@ struct Pool {
 };
 Pool g_pool;
 
-hipError_t pool_get(size_t bytes, void** out, int* dev_out) {
+hipError_t pool_get(size_t bytes, hipStream_t stream, void** out, int* dev_out) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
   const size_t sc = size_class(bytes);
   *dev_out = dev;
+  PoolBlock blk{nullptr, nullptr, nullptr};
   {
     std::lock_guard<std::mutex> lk(g_pool.mu);
-    auto it = g_pool.blocks.find({dev, sc});
-    if (it != g_pool.blocks.end()) {
-      *out = it->second;
-      g_pool.blocks.erase(it);
+    auto range = g_pool.blocks.equal_range({dev, sc});
+    auto pick = range.first;
+    for (auto it = range.first; it != range.second; ++it)
+      if (it->second.stream == stream) { pick = it; break; }   // prefer a block of this stream
+    if (pick != range.second) {
+      blk = pick->second;
+      g_pool.blocks.erase(pick);
       g_pool.cached -= sc;
-      return hipSuccess;
     }
   }
-  return hipMalloc(out, sc);
+  if (blk.p == nullptr) return hipMalloc(out, sc);
+  if (blk.done && blk.stream != stream) {
+    e = hipStreamWaitEvent(stream, blk.done->ev, 0);
+    if (e != hipSuccess) {
+      std::lock_guard<std::mutex> lk(g_pool.mu);
+      g_pool.blocks.insert({{dev, sc}, blk});
+      g_pool.cached += sc;
+      return e;
+    }
+  }
+  *out = blk.p;
+  return hipSuccess;
 }
 
-void pool_put(void* p, size_t bytes, int dev) {
+void pool_put(void* p, size_t bytes, int dev, hipStream_t stream, const std::shared_ptr<ReleaseEvent>& done) {
   const size_t sc = size_class(bytes);
   std::lock_guard<std::mutex> lk(g_pool.mu);
   if (g_pool.cached + sc > g_pool.cap()) {
-    (void)hipFree(p);
+    (void)hipFree(p);  // hipFree waits for the device's queued work
     return;
   }
-  g_pool.blocks.insert({{dev, sc}, p});
+  g_pool.blocks.insert({{dev, sc}, PoolBlock{p, stream, done}});
   g_pool.cached += sc;
 }
 
@@ -332,6 +362,7 @@ struct top_problem {
   int cur = 0;
   int iters_done = 0;
   bool have_sweep = false;
+  bool init_cost_ready = false;  // out[0] holds the Init guess's cost (computed on first request)
   bool explicit_tile = false;
   // tape: slot j holds the state before sweep j * checkpoint_every
   void* tape = nullptr;
@@ -357,7 +388,7 @@ struct top_problem {
     void* q = nullptr;
     if (bytes == 0) bytes = 256;
     int dev = 0;
-    hipError_t e = pool_get(bytes, &q, &dev);
+    hipError_t e = pool_get(bytes, stream, &q, &dev);
     if (e != hipSuccess) return fail(TOP_E_NOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
     allocs.push_back({q, bytes, dev});
     *p = reinterpret_cast<T*>(q);
@@ -722,7 +753,19 @@ const char* top_last_error(void) { return g_err.c_str(); }
 
 void top_destroy(top_problem* h) {
   if (h == nullptr) return;
-  (void)hipStreamSynchronize(h->stream);
+  // Handles with graphs or a reverse-pass stream wait for their work; a plain handle releases its
+  // buffers behind an event recorded on its stream and returns at once.
+  std::shared_ptr<ReleaseEvent> done;
+  if (!h->graphs.empty() || h->cap_stream != nullptr || h->rstream != nullptr) {
+    (void)hipStreamSynchronize(h->stream);
+  } else {
+    done = std::make_shared<ReleaseEvent>();
+    if (hipEventCreateWithFlags(&done->ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(done->ev, h->stream) != hipSuccess) {
+      (void)hipStreamSynchronize(h->stream);
+      done.reset();
+    }
+  }
   h->drop_graphs();
   if (h->cap_stream != nullptr) (void)hipStreamDestroy(h->cap_stream);
   if (h->rstream != nullptr) {
@@ -731,7 +774,7 @@ void top_destroy(top_problem* h) {
   }
   for (hipEvent_t e : {h->ev_start, h->ev_rep[0], h->ev_rep[1], h->ev_adj[0], h->ev_adj[1]})
     if (e != nullptr) (void)hipEventDestroy(e);
-  for (auto& b : h->allocs) pool_put(b.p, b.bytes, b.dev);
+  for (auto& b : h->allocs) pool_put(b.p, b.bytes, b.dev, h->stream, done);
   delete h;
 }
 
@@ -956,12 +999,6 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     hipError_t e = hipMemcpyAsync(h->tape, h->state[0], (size_t)h->nf * ld * R, hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "tape copy failed: %s", hipGetErrorString(e)));
   }
-  // cost of the Init guess (residuals stay undefined until the first sweep)
-  if ((st = h->finalize(nullptr, false, true, stream)) != TOP_OK) return bail(st);
-  {
-    hipError_t e = top::launch_reduce(h->reduce_args(), stream);
-    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "reduce launch failed: %s", hipGetErrorString(e)));
-  }
   // execution plan: explicit, tuned for this shape class, or the default
   int W = opt.tile_lanes, halo = opt.halo;
   h->explicit_tile = W != 0;
@@ -1078,6 +1115,15 @@ top_status top_residuals(const top_problem* h, double* r_primal, double* r_dual)
 
 top_status top_cost(const top_problem* h, double* cost) {
   if (h == nullptr || cost == nullptr) return fail(TOP_E_INVALID, "handle and cost must be non-NULL");
+  if (!h->have_sweep && !h->init_cost_ready) {
+    // before any sweep: the cost of the Init guess, reduced on first request only
+    top_problem* m = const_cast<top_problem*>(h);
+    top_status st = m->finalize(nullptr, false, true, h->stream);
+    if (st != TOP_OK) return st;
+    hipError_t e = top::launch_reduce(m->reduce_args(), h->stream);
+    if (e != hipSuccess) return fail(TOP_E_HIP, "reduce launch failed: %s", hipGetErrorString(e));
+    m->init_cost_ready = true;
+  }
   TOP_HIP(hipMemcpyAsync(cost, h->out, h->B * sizeof(double), hipMemcpyDeviceToDevice, h->stream));
   return TOP_OK;
 }
