@@ -44,7 +44,8 @@ top_status fail(top_status s, const char* fmt, ...) {
 
 int max_tile(const top::Variant& v) {
   if (v.num) return 64;
-  return (v.prec == 0 && v.p == 3 && v.faces == 0 && v.s != 2 * v.p - 1) ? 512 : 256;
+  if (v.faces) return (v.prec == 0 && v.p == 3) ? 512 : 256;  // the polytope kernel's LDS-matrix instance
+  return (v.prec == 0 && v.p == 3 && v.s != 2 * v.p - 1) ? 512 : 256;
 }
 // Handles that keep a tape also run the adjoint kernel on the same tiles: it is built for tiles of up
 // to 256 lanes, and its per-lane LDS column (box and velocity pair adjoints) must fit the device's

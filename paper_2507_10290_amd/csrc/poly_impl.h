@@ -315,16 +315,19 @@ __global__ __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(WPE))) void 
 template <typename R>
 hipError_t dispatch_poly_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st) {
   if (v.faces != kFaces || v.box || a.rec != nullptr) return hipErrorInvalidValue;
-  if (a.W <= 0 || a.W > 256 || (a.W & 63) != 0 || n_tiles <= 0) return hipErrorInvalidValue;
+  if (a.W <= 0 || (a.W & 63) != 0 || n_tiles <= 0) return hipErrorInvalidValue;
   dim3 grid(n_tiles), block(a.W);
-  // float32 quintic: matrices in LDS, two waves per SIMD; otherwise in registers
+  // float32 quintic: matrices in LDS (252 bytes per lane, 129 KB for a 512-lane tile, within the
+  // 160 KB a workgroup may hold), tiles up to 512 lanes, two waves per SIMD; otherwise matrices in
+  // registers and tiles up to 256 lanes
   constexpr bool hl3 = std::is_same<R, float>::value;
 #define TOP_POLY_CASE(P_, S_, V_)                                                             \
   if (v.p == P_ && v.s == S_ && (v.vel != 0) == V_) {                                       \
     constexpr bool HL_ = hl3 && P_ == 3;                                                    \
     constexpr int NH_ = 2 * P_ * (2 * P_ + 1) / 2;                                          \
+    if (a.W > (HL_ ? 512 : 256)) return hipErrorInvalidValue;                               \
     const size_t lds = HL_ ? (size_t)3 * NH_ * a.W * sizeof(R) : 0;                         \
-    auto k_ = poly_sweep_kernel<R, P_, S_, V_, 256, HL_, HL_ ? 2 : 1>;                      \
+    auto k_ = poly_sweep_kernel<R, P_, S_, V_, HL_ ? 512 : 256, HL_, HL_ ? 2 : 1>;          \
     if (HL_) {                                                                              \
       hipError_t e_ = hipFuncSetAttribute((const void*)k_, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
       if (e_ != hipSuccess) return e_;                                                      \

@@ -91,10 +91,13 @@ def test_fp64_box_as_faces_equals_box_path():
     assert np.allclose(a["J"], b["J"], rtol=1e-11)
 
 
-def test_fp32_polytope_batched_subset():
+@pytest.mark.parametrize("tile", [0, 256])
+def test_fp32_polytope_batched_subset(tile):
+    # default tiles (512 lanes: whole trajectories) and 256-lane tiles (the longer ones split)
     w = _tighten(make_config(5, n_traj=6), h=0.15)
+    assert w.traj_lengths().max() > 256
     K = 100
-    g = _gpu(w, K)
+    g = _gpu(w, K, tile_lanes=tile)
     co, res = _oracle(w, K)
     _check(w, g, co, res, 1e-4, 1e-3, "batched subset fp32")
 
