@@ -76,8 +76,12 @@ typedef struct top_options {
   int32_t checkpoint_every;  /* m > 0 records the state every m sweeps so top_backward can run;
                                 0 records nothing                                                     */
   int32_t max_taped_iters;   /* sweeps the tape can hold when checkpoint_every > 0                    */
-  int32_t tile_lanes;        /* segments per workgroup tile, a multiple of 64 in [64, 1024];
-                                0 picks the default (or the tuned value after top_tune)               */
+  int32_t tile_lanes;        /* segments per workgroup tile, a multiple of 64 from 64 up to the
+                                variant's maximum (TOP_E_INVALID above it): 512 for float32 order 3
+                                (closed form with n_cont < 2p-1, or a polytope corridor), 64 for
+                                NumericSolve, 256 otherwise; with a tape at most 256, less where the
+                                adjoint's LDS column would not fit.  0 picks the maximum (or the
+                                tuned value after top_tune)                                           */
   int32_t halo;              /* sweeps per launch for trajectories longer than a tile (their halo
                                 width); 0 picks the default.  With a tape it must be >= 2: the
                                 reverse pass runs halo - 1 steps per launch                           */
