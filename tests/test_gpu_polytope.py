@@ -102,6 +102,27 @@ def test_fp32_polytope_batched_subset(tile):
     _check(w, g, co, res, 1e-4, 1e-3, "batched subset fp32")
 
 
+def test_fp32_polytope_full_workload_sampled():
+    # the benchmark's 8-face batched workload at full size, in the configuration bench.py times
+    # (default 512-lane tiles, K = 200); whole trajectories checked against the oracle
+    w = make_config(5)
+    K = w.iters
+    print(f"[poly] full S={w.n_seg} K={K}", flush=True)
+    g = _gpu(w, K)
+    assert np.isfinite(g["c"]).all() and np.isfinite(g["J"]).all()
+    L = w.traj_lengths()
+    picks = sorted({int(np.argmin(L)), int(np.argmax(L)), 0, 2047, 4095})
+    sub = w.subset(picks)
+    co, res = _oracle(sub, K)
+    for k, t in enumerate(picks):
+        s0, s1 = int(w.seg_offsets[t]), int(w.seg_offsets[t + 1])
+        q0, q1 = int(sub.seg_offsets[k]), int(sub.seg_offsets[k + 1])
+        e = np.linalg.norm(g["c"][s0:s1] - co[q0:q1]) / np.linalg.norm(co[q0:q1])
+        eJ = abs(g["J"][t] - res.J[k].item()) / abs(res.J[k].item())
+        print(f"[poly]   traj {t} (N={s1 - s0}) coeff {e:.2e} cost {eJ:.2e}", flush=True)
+        assert e <= 1e-4 and eJ <= 1e-3
+
+
 def test_fp64_polytope_halo_tiles():
     w = _tighten(random_walk_batch("polyhalo", [150], [51], order=3, precision="fp64", faces=8), h=0.1)
     K = 40
