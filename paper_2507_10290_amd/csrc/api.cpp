@@ -266,16 +266,22 @@ std::mutex g_plan_mu;
 // shut down at process exit.
 std::map<uint64_t, std::shared_ptr<PlanEntry>>& g_plans = *new std::map<uint64_t, std::shared_ptr<PlanEntry>>();
 
-uint64_t plan_key(const std::vector<int64_t>& off, int W, int halo, int device) {
-  uint64_t h = 1469598103934665603ull;  // FNV-1a over the offsets and the shape parameters
+// Hash of the offsets and shape parameters (64-bit words folded in with a multiply-xorshift mix; the
+// caches compare the offsets themselves on a hit, so collisions only cost a rebuild).
+uint64_t offsets_hash(const std::vector<int64_t>& off, std::initializer_list<int64_t> extra) {
+  uint64_t h = 0x9e3779b97f4a7c15ull;
   auto mix = [&](uint64_t v) {
-    for (int i = 0; i < 8; ++i) { h ^= (v >> (8 * i)) & 0xff; h *= 1099511628211ull; }
+    h ^= v + 0x9e3779b97f4a7c15ull + (h << 6) + (h >> 2);
+    h *= 0xff51afd7ed558ccdull;
+    h ^= h >> 33;
   };
   for (int64_t o : off) mix((uint64_t)o);
-  mix((uint64_t)W);
-  mix((uint64_t)halo);
-  mix((uint64_t)device);
+  for (int64_t x : extra) mix((uint64_t)x);
   return h;
+}
+
+uint64_t plan_key(const std::vector<int64_t>& off, int W, int halo, int device) {
+  return offsets_hash(off, {W, halo, device});
 }
 
 // The cached plan of this shape, building and uploading it on first use.
@@ -314,6 +320,96 @@ top_status get_plan(const std::vector<int64_t>& off, int W, int halo, std::share
   return TOP_OK;
 }
 
+// ---- shape cache: the device copy of a CSR shape's offsets and the chunk tables of its
+// per-trajectory reduction, shared (read-only) by every handle of that shape on a device.
+struct ShapeEntry {
+  std::vector<int64_t> off;
+  int device = 0;
+  int64_t* off_dev = nullptr;        // [B + 1]
+  int32_t* chunk_off = nullptr;      // [B + 1] first reduction chunk of each trajectory
+  int32_t* chunk_traj = nullptr;     // [n_chunks] trajectory of each chunk
+  int n_chunks = 0;
+  ~ShapeEntry() {
+    for (void* q : {(void*)off_dev, (void*)chunk_off, (void*)chunk_traj})
+      if (q != nullptr) (void)hipFree(q);
+  }
+};
+
+std::mutex g_shape_mu;
+std::map<uint64_t, std::shared_ptr<ShapeEntry>>& g_shapes = *new std::map<uint64_t, std::shared_ptr<ShapeEntry>>();
+
+top_status get_shape(const std::vector<int64_t>& off, std::shared_ptr<ShapeEntry>* out) {
+  int dev = 0;
+  TOP_HIP(hipGetDevice(&dev));
+  const uint64_t key = offsets_hash(off, {dev});
+  {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    auto it = g_shapes.find(key);
+    if (it != g_shapes.end() && it->second->device == dev && it->second->off == off) {
+      *out = it->second;
+      return TOP_OK;
+    }
+  }
+  auto e = std::make_shared<ShapeEntry>();
+  e->off = off;
+  e->device = dev;
+  const int B = (int)off.size() - 1;
+  std::vector<int32_t> c_off((size_t)B + 1), c_traj;
+  c_off[0] = 0;
+  for (int b = 0; b < B; ++b) {
+    const int64_t nc = (off[b + 1] - off[b] + top::kReduceChunk - 1) / top::kReduceChunk;
+    c_off[b + 1] = c_off[b] + (int32_t)nc;
+    for (int64_t j = 0; j < nc; ++j) c_traj.push_back(b);
+  }
+  e->n_chunks = (int)c_traj.size();
+  hipError_t he = hipMalloc((void**)&e->off_dev, off.size() * sizeof(int64_t));
+  if (he == hipSuccess) he = hipMalloc((void**)&e->chunk_off, c_off.size() * sizeof(int32_t));
+  if (he == hipSuccess) he = hipMalloc((void**)&e->chunk_traj, std::max<size_t>(c_traj.size(), 1) * sizeof(int32_t));
+  if (he != hipSuccess) return fail(TOP_E_NOMEM, "device allocation for the shape tables failed");
+  he = hipMemcpy(e->off_dev, off.data(), off.size() * sizeof(int64_t), hipMemcpyHostToDevice);
+  if (he == hipSuccess) he = hipMemcpy(e->chunk_off, c_off.data(), c_off.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (he == hipSuccess && !c_traj.empty())
+    he = hipMemcpy(e->chunk_traj, c_traj.data(), c_traj.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (he != hipSuccess) return fail(TOP_E_HIP, "shape table upload failed: %s", hipGetErrorString(he));
+  std::lock_guard<std::mutex> lk(g_shape_mu);
+  if (g_shapes.size() >= 16) {  // keep at most 16 shapes; drop the ones no handle uses any more
+    for (auto it = g_shapes.begin(); it != g_shapes.end();) {
+      if (it->second.use_count() == 1) it = g_shapes.erase(it); else ++it;
+    }
+  }
+  g_shapes[key] = e;
+  *out = e;
+  return TOP_OK;
+}
+
+// ---- pinned host words for the validation flags, so create can read them back without blocking
+// the launches queued behind the check.
+std::mutex g_pin_mu;
+int* g_pin = nullptr;
+std::vector<int> g_pin_free;
+constexpr int kPinSlots = 1024;  // two words each
+
+int* pin_get() {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  if (g_pin == nullptr) {
+    if (hipHostMalloc((void**)&g_pin, 2 * kPinSlots * sizeof(int), hipHostMallocDefault) != hipSuccess) {
+      g_pin = nullptr;
+      return nullptr;
+    }
+    for (int k = kPinSlots - 1; k >= 0; --k) g_pin_free.push_back(k);
+  }
+  if (g_pin_free.empty()) return nullptr;
+  const int k = g_pin_free.back();
+  g_pin_free.pop_back();
+  return g_pin + 2 * k;
+}
+
+void pin_put(int* p) {
+  if (p == nullptr) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.push_back((int)((p - g_pin) / 2));
+}
+
 }  // namespace
 
 struct top_problem {
@@ -337,11 +433,13 @@ struct top_problem {
   uint8_t* flags = nullptr;
   int32_t* traj = nullptr;
   double *Tdev = nullptr, *rho_seg = nullptr, *part = nullptr, *out = nullptr;
-  int64_t* off_dev = nullptr;
+  std::shared_ptr<ShapeEntry> shape;   // device offsets and reduction chunk tables of this CSR shape
+  const int64_t* off_dev = nullptr;
   int* flag_dev = nullptr;
-  // chunked per-trajectory reduction (host copies stay alive until the uploads have run)
-  std::vector<int32_t> chunk_traj_h, chunk_off_h;
-  int32_t *chunk_traj = nullptr, *chunk_off = nullptr;
+  int* pin = nullptr;                // pinned host words receiving the input check's flags
+  hipEvent_t ev_valid = nullptr;     // recorded after their readback
+  const int32_t *chunk_traj = nullptr, *chunk_off = nullptr;
+  int n_chunks = 0;
   double* chunk_sum = nullptr;
   top::ReduceArgs reduce_args() const {
     top::ReduceArgs a{};
@@ -351,7 +449,7 @@ struct top_problem {
     a.B = B;
     a.chunk_traj = chunk_traj;
     a.chunk_off = chunk_off;
-    a.n_chunks = (int)chunk_traj_h.size();
+    a.n_chunks = n_chunks;
     a.chunk_sum = chunk_sum;
     a.out = out;
     return a;
@@ -775,6 +873,11 @@ void top_destroy(top_problem* h) {
   }
   for (hipEvent_t e : {h->ev_start, h->ev_rep[0], h->ev_rep[1], h->ev_adj[0], h->ev_adj[1]})
     if (e != nullptr) (void)hipEventDestroy(e);
+  if (h->ev_valid != nullptr) {
+    (void)hipEventSynchronize(h->ev_valid);  // the readback into the pinned word has landed
+    (void)hipEventDestroy(h->ev_valid);
+  }
+  pin_put(h->pin);
   for (auto& b : h->allocs) pool_put(b.p, b.bytes, b.dev, h->stream, done);
   delete h;
 }
@@ -873,15 +976,8 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   if ((st = h->alloc(&h->hi, 3 * ld * R)) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->vmax, ld * R)) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->bcL, (size_t)n_traj * 3 * s * R)) != TOP_OK) return bail(st);
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < 2; ++q)  // the setup zeroes the padding columns S..ld-1 of both
     if ((st = h->alloc(&h->state[q], (size_t)h->nf * ld * R)) != TOP_OK) return bail(st);
-    // no lane owns the padding columns S..ld-1; zero them so exported states are deterministic
-    if (ld > (size_t)S) {
-      hipError_t e = hipMemset2DAsync((char*)h->state[q] + (size_t)S * R, ld * R, 0, (ld - (size_t)S) * R,
-                                      (size_t)h->nf, stream);
-      if (e != hipSuccess) return bail(fail(TOP_E_HIP, "state padding reset failed: %s", hipGetErrorString(e)));
-    }
-  }
   if ((st = h->alloc(&h->cbuf, 3 * (size_t)L.n() * ld * R)) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->zold, 3 * (size_t)s * ld * R)) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->flags, ld)) != TOP_OK) return bail(st);
@@ -890,27 +986,14 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   if ((st = h->alloc(&h->rho_seg, ld * sizeof(double))) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->part, 3 * (size_t)S * sizeof(double))) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->out, 3 * (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->off_dev, (size_t)(n_traj + 1) * sizeof(int64_t))) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->flag_dev, 2 * sizeof(int))) != TOP_OK) return bail(st);
   if ((st = h->alloc(&h->rho_traj, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
-  h->chunk_off_h.resize((size_t)n_traj + 1);
-  h->chunk_off_h[0] = 0;
-  for (int b = 0; b < n_traj; ++b) {
-    const int64_t nc = (seg_offsets[b + 1] - seg_offsets[b] + top::kReduceChunk - 1) / top::kReduceChunk;
-    h->chunk_off_h[b + 1] = h->chunk_off_h[b] + (int32_t)nc;
-    for (int64_t j = 0; j < nc; ++j) h->chunk_traj_h.push_back(b);
-  }
-  {
-    const size_t nc = h->chunk_traj_h.size();
-    if ((st = h->alloc(&h->chunk_off, ((size_t)n_traj + 1) * sizeof(int32_t))) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->chunk_traj, std::max<size_t>(nc, 1) * sizeof(int32_t))) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->chunk_sum, 3 * std::max<size_t>(nc, 1) * sizeof(double))) != TOP_OK) return bail(st);
-    hipError_t e = hipMemcpyAsync(h->chunk_off, h->chunk_off_h.data(), ((size_t)n_traj + 1) * sizeof(int32_t),
-                                  hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess && nc > 0)
-      e = hipMemcpyAsync(h->chunk_traj, h->chunk_traj_h.data(), nc * sizeof(int32_t), hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "copy of the reduction chunks failed: %s", hipGetErrorString(e)));
-  }
+  if ((st = get_shape(h->off, &h->shape)) != TOP_OK) return bail(st);
+  h->off_dev = h->shape->off_dev;
+  h->chunk_off = h->shape->chunk_off;
+  h->chunk_traj = h->shape->chunk_traj;
+  h->n_chunks = h->shape->n_chunks;
+  if ((st = h->alloc(&h->chunk_sum, 3 * std::max<size_t>(h->n_chunks, 1) * sizeof(double))) != TOP_OK) return bail(st);
   if (opt.check_every > 0) {
     if ((st = h->alloc(&h->done_dev, (size_t)n_traj)) != TOP_OK) return bail(st);
     if ((st = h->alloc(&h->fresh, (size_t)n_traj)) != TOP_OK) return bail(st);
@@ -952,32 +1035,24 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "input copy failed: %s", hipGetErrorString(e)));
   }
   {
-    hipError_t e = hipMemcpyAsync(h->off_dev, seg_offsets, (n_traj + 1) * sizeof(int64_t),
-                                  hipMemcpyHostToDevice, stream);
-    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "copy of seg_offsets failed: %s", hipGetErrorString(e)));
-    const int zero2[2] = {0, 0};
-    e = hipMemcpyAsync(h->flag_dev, zero2, sizeof zero2, hipMemcpyHostToDevice, stream);
+    hipError_t e = hipMemsetAsync(h->flag_dev, 0, 2 * sizeof(int), stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "flag reset failed: %s", hipGetErrorString(e)));
   }
   top::SetupArgs sa{waypoints, durations, bc, box_lo, box_hi, faces, n_faces, vmax, rho, h->off_dev, n_traj, S,
                     opt.fix_interior};
+  // The device-side input check runs first and its flags come back through a pinned host word behind
+  // an event, so the setup is queued before the host waits for them (the setup is memory-safe
+  // whatever the input values: every index it forms derives from the host-checked offsets).  Invalid
+  // inputs then release the handle.
   {
     hipError_t e = top::launch_validate(sa, v.p, h->flag_dev, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "validation launch failed: %s", hipGetErrorString(e)));
-    int bad[2] = {0, 0};
-    e = hipMemcpyAsync(bad, h->flag_dev, sizeof bad, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "validation failed: %s", hipGetErrorString(e)));
-    if (bad[0] != 0) {
-      std::string what;
-      if (bad[0] & 1) what += " durations (need finite T > 0);";
-      if (bad[0] & 2) what += " box (need finite lo < hi);";
-      if (bad[0] & 4) what += " waypoints (need finite);";
-      if (bad[0] & 8) what += " rho (need finite > 0);";
-      if (bad[0] & 16) what += " vmax (need finite > 0);";
-      if (bad[0] & 32) what += " bc (need finite);";
-      if (bad[0] & 64) what += " faces (need finite);";
-      return bail(fail(TOP_E_INVALID, "invalid input:%s", what.c_str()));
+    h->pin = pin_get();
+    if (h->pin != nullptr) {
+      e = hipMemcpyAsync(h->pin, h->flag_dev, 2 * sizeof(int), hipMemcpyDeviceToHost, stream);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_valid, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventRecord(h->ev_valid, stream);
+      if (e != hipSuccess) return bail(fail(TOP_E_HIP, "validation readback failed: %s", hipGetErrorString(e)));
     }
   }
   {
@@ -985,13 +1060,14 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     if (v.prec == 0) {
       top::SetupOut<float> o{(float*)h->Hr, (float*)h->iT, (float*)h->lo, (float*)h->hi, (float*)h->vmax,
                              h->flags, h->traj, (float*)h->bcL, (float*)h->state[0], (float*)h->cbuf,
-                             h->ld, h->Tdev, h->rho_seg, (float*)h->Hd, (float*)h->Urot, (float*)h->fa, h->lam};
+                             h->ld, h->Tdev, h->rho_seg, (float*)h->Hd, (float*)h->Urot, (float*)h->fa, h->lam,
+                             (float*)h->state[1], h->nf};
       e = top::launch_setup<float>(v, sa, o, stream);
     } else {
       top::SetupOut<double> o{(double*)h->Hr, (double*)h->iT, (double*)h->lo, (double*)h->hi, (double*)h->vmax,
                               h->flags, h->traj, (double*)h->bcL, (double*)h->state[0], (double*)h->cbuf,
                               h->ld, h->Tdev, h->rho_seg, (double*)h->Hd, (double*)h->Urot, (double*)h->fa,
-                              h->lam};
+                              h->lam, (double*)h->state[1], h->nf};
       e = top::launch_setup<double>(v, sa, o, stream);
     }
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "setup launch failed: %s", hipGetErrorString(e)));
@@ -1020,6 +1096,32 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     halo = 2;
   }
   if ((st = get_plan(h->off, W, halo, &h->pe)) != TOP_OK) return bail(st);
+  // the input check's verdict
+  int bad = 0;
+  {
+    hipError_t e;
+    if (h->pin != nullptr) {
+      e = hipEventSynchronize(h->ev_valid);
+      bad = h->pin[0];
+    } else {  // no pinned word free: read back through pageable memory (waits for the setup too)
+      int b2[2] = {0, 0};
+      e = hipMemcpyAsync(b2, h->flag_dev, sizeof b2, hipMemcpyDeviceToHost, stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(stream);
+      bad = b2[0];
+    }
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "validation failed: %s", hipGetErrorString(e)));
+  }
+  if (bad != 0) {
+    std::string what;
+    if (bad & 1) what += " durations (need finite T > 0);";
+    if (bad & 2) what += " box (need finite lo < hi);";
+    if (bad & 4) what += " waypoints (need finite);";
+    if (bad & 8) what += " rho (need finite > 0);";
+    if (bad & 16) what += " vmax (need finite > 0);";
+    if (bad & 32) what += " bc (need finite);";
+    if (bad & 64) what += " faces (need finite);";
+    return bail(fail(TOP_E_INVALID, "invalid input:%s", what.c_str()));
+  }
   *out = h;
   return TOP_OK;
 }

@@ -177,6 +177,8 @@ struct SetupOut {
   R* U;                      // polytope: [9][ld] rotation
   R* fa;                     // polytope: [kFaces * 4][ld] faces (padded)
   double* lam;               // polytope: [3][ld] eigenvalues of sum_k a_k a_k^T
+  R* state1;                 // the second state buffer (its padding columns are zeroed too), or null
+  int nf;                    // state rows
 };
 
 template <typename R>

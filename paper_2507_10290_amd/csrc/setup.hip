@@ -73,8 +73,16 @@ __global__ void __launch_bounds__(128) setup_kernel(SetupArgs a, SetupOut<R> out
   constexpr int F_YL = F_YH + (BOX ? 3 * M : 0);
   constexpr int F_G = 9 * S + (BOX ? 6 * M : KF * M);
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.S) return;
   const int64_t ld = out.ld;
+  if (i >= a.S) {
+    // padding columns S..ld-1: owned by no lane; zeroed so that exported states are deterministic
+    if (i < ld)
+      for (int f = 0; f < out.nf; ++f) {
+        out.state[(int64_t)f * ld + i] = R(0);
+        if (out.state1 != nullptr) out.state1[(int64_t)f * ld + i] = R(0);
+      }
+    return;
+  }
 
   // trajectory of segment i: last b with seg_off[b] <= i
   int lo_b = 0, hi_b = a.B;  // invariant seg_off[lo_b] <= i < seg_off[hi_b]
@@ -250,7 +258,7 @@ __global__ void __launch_bounds__(128) setup_kernel(SetupArgs a, SetupOut<R> out
 template <typename R>
 hipError_t launch_setup(const Variant& v, const SetupArgs& a, const SetupOut<R>& o, hipStream_t st) {
   const int bs = 128;
-  const dim3 grid((unsigned)((a.S + bs - 1) / bs)), block(bs);
+  const dim3 grid((unsigned)((o.ld + bs - 1) / bs)), block(bs);  // ld >= S: the padding columns too
   if (v.num != 0) {
     if (!v.vel || v.faces || v.s != v.p) return hipErrorInvalidValue;
 #define TOP_SETUP_NUM(P_, B_)                                                             \
