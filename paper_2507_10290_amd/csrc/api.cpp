@@ -1233,7 +1233,11 @@ top_status top_cost(const top_problem* h, double* cost) {
 
 top_status top_coeffs(const top_problem* h, double* coeffs) {
   if (h == nullptr || coeffs == nullptr) return fail(TOP_E_INVALID, "handle and coeffs must be non-NULL");
-  return const_cast<top_problem*>(h)->finalize(coeffs, false, false, h->stream);
+  hipError_t e = h->v.prec == 0
+      ? top::launch_coeffs<float>(h->v.p, (const float*)h->cbuf, h->Tdev, h->S, h->ld, coeffs, h->stream)
+      : top::launch_coeffs<double>(h->v.p, (const double*)h->cbuf, h->Tdev, h->S, h->ld, coeffs, h->stream);
+  if (e != hipSuccess) return fail(TOP_E_HIP, "coefficient output launch failed: %s", hipGetErrorString(e));
+  return TOP_OK;
 }
 
 top_status top_backward(top_problem* h, const double* dcost, double* dwaypoints, double* ddurations) {

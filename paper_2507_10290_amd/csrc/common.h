@@ -208,6 +208,10 @@ struct FinalArgs {
 template <typename R>
 hipError_t launch_finalize(const Variant& v, const FinalArgs<R>& a, hipStream_t st);
 
+// Monomial coefficients c_{a,j} = c~_{a,j} / T^j in float64, [S][3][2p], from c~ [3*2p][ld].
+template <typename R>
+hipError_t launch_coeffs(int p, const R* c, const double* T, int64_t S, int64_t ld, double* out, hipStream_t st);
+
 // Per-trajectory sums of the per-segment partials part[3][S] in a fixed order: out[0][b] = cost,
 // out[1][b] = ||r_p||, out[2][b] = ||r_d|| (square roots taken).  Each trajectory is cut into chunks of
 // kReduceChunk segments (chunk j of trajectory b covers segments off[b] + j*kReduceChunk onwards); one

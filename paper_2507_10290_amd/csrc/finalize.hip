@@ -85,6 +85,44 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs<R> a) {
   }
 }
 
+// A workgroup converts 128 consecutive segments into LDS, then writes their 128 * 3n contiguous
+// output values with consecutive lanes (one segment's 3n values are 144 or 192 bytes apart from the
+// next one's, so per-lane stores straight from registers would not coalesce).
+template <typename R, int P>
+__global__ void __launch_bounds__(128) coeffs_kernel(const R* c, const double* T, int64_t S, int64_t ld,
+                                                     double* out) {
+  constexpr int N = 2 * P, K = 3 * N;
+  __shared__ double buf[128 * K];
+  const int t = threadIdx.x;
+  const int64_t s0 = (int64_t)blockIdx.x * 128;
+  const int64_t i = s0 + t;
+  if (i < S) {
+    const double iT = 1.0 / T[i];
+    double iTp = 1.0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+#pragma unroll
+      for (int ax = 0; ax < 3; ++ax) buf[t * K + ax * N + j] = (double)c[(int64_t)(ax * N + j) * ld + i] * iTp;
+      iTp *= iT;
+    }
+  }
+  __syncthreads();
+  const int64_t nseg = S - s0 < 128 ? S - s0 : 128;
+  const int total = (int)nseg * K;
+  for (int q = t; q < total; q += 128) out[s0 * K + q] = buf[q];
+}
+
+template <typename R>
+hipError_t launch_coeffs(int p, const R* c, const double* T, int64_t S, int64_t ld, double* out, hipStream_t st) {
+  const dim3 grid((unsigned)((S + 127) / 128)), block(128);
+  if (p == 3) hipLaunchKernelGGL((coeffs_kernel<R, 3>), grid, block, 0, st, c, T, S, ld, out);
+  else if (p == 4) hipLaunchKernelGGL((coeffs_kernel<R, 4>), grid, block, 0, st, c, T, S, ld, out);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+template hipError_t launch_coeffs<float>(int, const float*, const double*, int64_t, int64_t, double*, hipStream_t);
+template hipError_t launch_coeffs<double>(int, const double*, const double*, int64_t, int64_t, double*, hipStream_t);
+
 template <typename R>
 hipError_t launch_finalize(const Variant& v, const FinalArgs<R>& a, hipStream_t st) {
   const int bs = 256;
