@@ -50,12 +50,23 @@ hipError_t launch_check(const CheckArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// A lane copies its segment's state column; the loads of a batch of rows are all issued before
+// their stores, so a lane waits for memory once per batch rather than once per row.
 template <typename R>
-__global__ void freeze_copy_kernel(const R* cur, R* other, const uint8_t* fresh, const int32_t* traj, int nf,
-                                   int64_t S, int64_t ld) {
+__global__ void __launch_bounds__(256) freeze_copy_kernel(const R* cur, R* other, const uint8_t* fresh,
+                                                          const int32_t* traj, int nf, int64_t S, int64_t ld) {
+  constexpr int kBatch = 16;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S || fresh[traj[i]] == 0) return;
-  for (int f = 0; f < nf; ++f) other[f * ld + i] = cur[f * ld + i];
+  for (int f0 = 0; f0 < nf; f0 += kBatch) {
+    R v[kBatch];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k)
+      if (f0 + k < nf) v[k] = cur[(int64_t)(f0 + k) * ld + i];
+#pragma unroll
+    for (int k = 0; k < kBatch; ++k)
+      if (f0 + k < nf) other[(int64_t)(f0 + k) * ld + i] = v[k];
+  }
 }
 
 hipError_t launch_freeze_copy(const void* cur, void* other, const uint8_t* fresh, const int32_t* traj, int nf,

@@ -258,6 +258,21 @@ void sweep_kernel(SweepArgs<R> A) {
   }
   L.fixpos = A.fixpos != 0;
 
+  // A stopped trajectory keeps its state: both state buffers already hold it, so its lanes sweep
+  // along (their neighbours belong to the same trajectory, so nothing leaks) and leave c~ and the old
+  // knot alone; with store_frozen they also store their input state into the output buffer.
+  const int tr = active ? A.k.traj[seg] : 0;
+  const bool frozen = active && A.done != nullptr && A.done[tr] != 0;
+  if (A.done != nullptr) {
+    // Before any state is loaded: a tile with no live segment is done; a wave with none only keeps
+    // the workgroup's barrier count (one per sweep).
+    if (__syncthreads_or(active && !frozen) == 0) return;
+    if (__ballot(active && !frozen) == 0) {
+      for (int it = 0; it < A.iters; ++it) __syncthreads();
+      return;
+    }
+  }
+
   // ---- per-segment constants
 #pragma unroll
   for (int h = 0; h < NH; ++h) L.H[h] = active ? A.k.Hr[h * ld + seg] : R(0);
@@ -274,7 +289,6 @@ void sweep_kernel(SweepArgs<R> A) {
 
   // ---- state
   const R* in = A.st_in;
-  const int tr = active ? A.k.traj[seg] : 0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
 #pragma unroll
@@ -297,20 +311,11 @@ void sweep_kernel(SweepArgs<R> A) {
   }
 
   const int wl = lane & 63, wid = lane >> 6, nw = W >> 6;
-  // A stopped trajectory keeps its state: both state buffers already hold it, so its lanes sweep
-  // along (their neighbours belong to the same trajectory, so nothing leaks) and leave c~ and the old
-  // knot alone; with store_frozen they also store their input state into the output buffer.
-  const bool frozen = active && A.done != nullptr && A.done[tr] != 0;
   auto copy_through = [&]() {
     constexpr int NF = F_G + (VEL ? 3 * M : 0);
 #pragma unroll 4
     for (int f = 0; f < NF; ++f) A.st_out[f * ld + seg] = in[f * ld + seg];
   };
-  // A wave with no live segment only has to keep the workgroup's barrier count (one per sweep).
-  if (__ballot(active && !frozen) == 0) {
-    for (int it = 0; it < A.iters; ++it) __syncthreads();
-    return;
-  }
   auto store_to = [&](R* out) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
