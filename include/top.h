@@ -93,7 +93,8 @@ typedef struct top_options {
      coefficients, cost and residuals stay those of that sweep; later sweeps leave it unchanged),
      and otherwise, with adapt_rho, its rho is multiplied by tau_incr when ||r_p|| > mu ||r_d||
      or divided by tau_decr when ||r_d|| > mu ||r_p||, the scaled duals being multiplied by
-     rho_old / rho_new.  Not available together with a tape.                                       */
+     rho_old / rho_new.  Not available together with a tape, nor for trajectories of more than
+     65535 * 128 segments (TOP_E_UNSUPPORTED).                                                     */
   int32_t check_every;       /* sweeps between checks; 0 disables checks (fixed rho, no stopping)    */
   int32_t adapt_rho;         /* 1: apply the penalty rule at every check                             */
   double tol;                /* E of the stopping test; <= 0 never stops (the paper uses 0.05)        */

@@ -50,50 +50,49 @@ hipError_t launch_check(const CheckArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// A lane copies its segment's state column; the loads of a batch of rows are all issued before
-// their stores, so a lane waits for memory once per batch rather than once per row.
+// Trajectory-major grid (the workgroups of trajectories that did not just stop leave at once); a
+// lane copies a segment's state column, issuing the loads of a batch of rows before their stores,
+// so it waits for memory once per batch rather than once per row.
 template <typename R>
 __global__ void __launch_bounds__(256) freeze_copy_kernel(const R* cur, R* other, const uint8_t* fresh,
-                                                          const int32_t* traj, int nf, int64_t S, int64_t ld) {
+                                                          const int64_t* off, int nf, int64_t ld) {
   constexpr int kBatch = 16;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= S || fresh[traj[i]] == 0) return;
-  for (int f0 = 0; f0 < nf; f0 += kBatch) {
-    R v[kBatch];
+  const int b = blockIdx.x;
+  if (fresh[b] == 0) return;
+  const int64_t i = off[b] + (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  if (i < off[b + 1]) {
+    for (int f0 = 0; f0 < nf; f0 += kBatch) {
+      R v[kBatch];
 #pragma unroll
-    for (int k = 0; k < kBatch; ++k)
-      if (f0 + k < nf) v[k] = cur[(int64_t)(f0 + k) * ld + i];
+      for (int k = 0; k < kBatch; ++k)
+        if (f0 + k < nf) v[k] = cur[(int64_t)(f0 + k) * ld + i];
 #pragma unroll
-    for (int k = 0; k < kBatch; ++k)
-      if (f0 + k < nf) other[(int64_t)(f0 + k) * ld + i] = v[k];
+      for (int k = 0; k < kBatch; ++k)
+        if (f0 + k < nf) other[(int64_t)(f0 + k) * ld + i] = v[k];
+    }
   }
 }
 
-hipError_t launch_freeze_copy(const void* cur, void* other, const uint8_t* fresh, const int32_t* traj, int nf,
-                              int64_t S, int64_t ld, size_t rsz, hipStream_t st) {
-  const dim3 grid((unsigned)((S + 255) / 256)), block(256);
+hipError_t launch_freeze_copy(const void* cur, void* other, const uint8_t* fresh, const int64_t* off, int B,
+                              int64_t max_len, int nf, int64_t ld, size_t rsz, hipStream_t st) {
+  const dim3 grid((unsigned)B, (unsigned)((max_len + 255) / 256)), block(256);
   if (rsz == sizeof(float))
-    hipLaunchKernelGGL(freeze_copy_kernel<float>, grid, block, 0, st, (const float*)cur, (float*)other, fresh, traj,
-                       nf, S, ld);
+    hipLaunchKernelGGL(freeze_copy_kernel<float>, grid, block, 0, st, (const float*)cur, (float*)other, fresh, off,
+                       nf, ld);
   else
     hipLaunchKernelGGL(freeze_copy_kernel<double>, grid, block, 0, st, (const double*)cur, (double*)other, fresh,
-                       traj, nf, S, ld);
+                       off, nf, ld);
   return hipGetLastError();
 }
 
-// KF = kFaces: polytope corridor (one y per face and sample, one matrix per rotated axis).
-template <typename R, int P, int S, bool BOX, bool VEL, int KF = 0>
-__global__ void __launch_bounds__(128) rescale_kernel(RescaleArgs<R> a) {
+// The rescaling of one segment of a trajectory whose rho changed by r = rho_old / rho_new.
+template <typename R, int P, int S, bool BOX, bool VEL, int KF>
+__device__ void rescale_segment(const RescaleArgs<R>& a, int64_t i, int b, double r) {
   constexpr int N = 2 * P;
   constexpr int M = kSamples;
   constexpr int F_UL = 3 * S, F_YH = 9 * S;
   constexpr int NY = BOX ? 6 * M : KF * M;   // corridor pairs
   constexpr int F_G = 9 * S + NY;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.S) return;
-  const int b = a.traj[i];
-  const double r = a.ratio[b];
-  if (r == 1.0) return;
   const int64_t ld = a.ld;
   R* st = a.state;
   const R rr = (R)r;
@@ -136,10 +135,22 @@ __global__ void __launch_bounds__(128) rescale_kernel(RescaleArgs<R> a) {
   }
 }
 
+// KF = kFaces: polytope corridor (one y per face and sample, one matrix per rotated axis).
+// Trajectory-major grid (x = trajectory, y = chunk of 128 of its segments); the workgroups of
+// trajectories whose rho did not change leave at once.
+template <typename R, int P, int S, bool BOX, bool VEL, int KF = 0>
+__global__ void __launch_bounds__(128) rescale_kernel(RescaleArgs<R> a) {
+  const int b = blockIdx.x;
+  const double r = a.ratio[b];
+  if (r == 1.0) return;
+  const int64_t i = a.off[b] + (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  if (i < a.off[b + 1]) rescale_segment<R, P, S, BOX, VEL, KF>(a, i, b, r);
+}
+
 template <typename R>
 hipError_t launch_rescale(const Variant& v, const RescaleArgs<R>& a, hipStream_t st) {
   const int bs = 128;
-  const dim3 grid((unsigned)((a.S + bs - 1) / bs)), block(bs);
+  const dim3 grid((unsigned)a.B, (unsigned)((a.max_len + bs - 1) / bs)), block(bs);
   if (v.faces != 0) {
     if (v.faces != kFaces || v.box || a.lam == nullptr) return hipErrorInvalidValue;
 #define TOP_RESCALE_POLY(P_, S_, V_)                                                        \

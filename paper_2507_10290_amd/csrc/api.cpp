@@ -440,6 +440,7 @@ struct top_problem {
   hipEvent_t ev_valid = nullptr;     // recorded after their readback
   const int32_t *chunk_traj = nullptr, *chunk_off = nullptr;
   int n_chunks = 0;
+  int64_t max_len = 0;                 // segments of the longest trajectory
   double* chunk_sum = nullptr;
   top::ReduceArgs reduce_args() const {
     top::ReduceArgs a{};
@@ -567,6 +568,9 @@ struct top_problem {
     a.with_res = with_res ? 1 : 0;
     // stopped trajectories keep their partials; coefficient output needs every segment
     a.done = (opt.check_every > 0 && coeffs == nullptr) ? done_dev : nullptr;
+    a.off = off_dev;
+    a.B = B;
+    a.max_len = max_len;
     hipError_t e = top::launch_finalize<R>(v, a, st);
     if (e != hipSuccess) return fail(TOP_E_HIP, "finalize launch failed: %s", hipGetErrorString(e));
     return TOP_OK;
@@ -757,7 +761,8 @@ struct top_problem {
     ca.ratio = ratio;
     if ((e = top::launch_check(ca, st)) != hipSuccess)
       return fail(TOP_E_HIP, "check launch failed: %s", hipGetErrorString(e));
-    if ((e = top::launch_freeze_copy(state[c], state[c ^ 1], fresh, traj, nf, S, ld, rsz, st)) != hipSuccess)
+    if ((e = top::launch_freeze_copy(state[c], state[c ^ 1], fresh, off_dev, B, max_len, nf, ld, rsz, st)) !=
+        hipSuccess)
       return fail(TOP_E_HIP, "freeze copy failed: %s", hipGetErrorString(e));
     if (!opt.adapt_rho) return TOP_OK;
     e = v.prec == 0 ? rescale_t<float>(c, st) : rescale_t<double>(c, st);
@@ -780,6 +785,9 @@ struct top_problem {
     ra.vmax = (const R*)vmax;
     ra.S = S;
     ra.ld = ld;
+    ra.off = off_dev;
+    ra.B = B;
+    ra.max_len = max_len;
     return top::launch_rescale<R>(v, ra, st);
   }
 
@@ -933,6 +941,11 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   if (opt.check_every < 0) return fail(TOP_E_INVALID, "check_every must be >= 0 (got %d)", opt.check_every);
   if (opt.check_every > 0) {
     if (taped) return fail(TOP_E_UNSUPPORTED, "residual checks cannot be combined with a tape");
+    int64_t longest = 0;
+    for (int b = 0; b < n_traj; ++b) longest = std::max<int64_t>(longest, seg_offsets[b + 1] - seg_offsets[b]);
+    if (longest > 65535LL * 128)  // the check kernels' trajectory-major grids
+      return fail(TOP_E_UNSUPPORTED, "residual checks support trajectories of at most %lld segments",
+                  65535LL * 128);
     if (opt.adapt_rho != 0 && opt.adapt_rho != 1) return fail(TOP_E_INVALID, "adapt_rho must be 0 or 1");
     if (!std::isfinite(opt.tol)) return fail(TOP_E_INVALID, "tol must be finite");
     if (opt.adapt_rho && !(opt.mu > 1.0 && opt.tau_incr > 1.0 && opt.tau_decr > 1.0 && std::isfinite(opt.mu) &&
@@ -958,6 +971,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   h->ld = (S + 63) / 64 * 64;
   h->rsz = v.prec == 0 ? sizeof(float) : sizeof(double);
   h->off.assign(seg_offsets, seg_offsets + n_traj + 1);
+  for (int b = 0; b < n_traj; ++b) h->max_len = std::max<int64_t>(h->max_len, seg_offsets[b + 1] - seg_offsets[b]);
   h->stream = stream;
   top::Layout L{v.p, v.s, v.box, v.vel, v.faces, v.num};
   h->nf = L.nf();

@@ -203,6 +203,9 @@ struct FinalArgs {
   int* nonfinite;
   int with_res;
   const uint8_t* done;  // [B] or null: segments of stopped trajectories keep their partials (skipped)
+  const int64_t* off;   // [B + 1] segment offsets (used with done: a trajectory-major grid)
+  int B;
+  int64_t max_len;      // segments of the longest trajectory
 };
 
 template <typename R>
@@ -251,8 +254,10 @@ struct CheckArgs {
 hipError_t launch_check(const CheckArgs& a, hipStream_t st);
 // Copy the state of the trajectories that just stopped into the other ping-pong buffer (nf fields of
 // rsz bytes per segment), so that later sweeps can leave them alone.
-hipError_t launch_freeze_copy(const void* cur, void* other, const uint8_t* fresh, const int32_t* traj, int nf,
-                              int64_t S, int64_t ld, size_t rsz, hipStream_t st);
+// off [B + 1] are the segment offsets; the grid is trajectory-major (x = trajectory, y = chunk of
+// 256 of its segments, max_len = the longest trajectory's segment count).
+hipError_t launch_freeze_copy(const void* cur, void* other, const uint8_t* fresh, const int64_t* off, int B,
+                              int64_t max_len, int nf, int64_t ld, size_t rsz, hipStream_t st);
 
 template <typename R>
 struct RescaleArgs {
@@ -267,6 +272,9 @@ struct RescaleArgs {
   const int32_t* traj;
   const R* vmax;
   int64_t S, ld;
+  const int64_t* off;     // [B + 1] segment offsets (trajectory-major grid)
+  int B;
+  int64_t max_len;        // segments of the longest trajectory
 };
 template <typename R>
 hipError_t launch_rescale(const Variant& v, const RescaleArgs<R>& a, hipStream_t st);

@@ -6,11 +6,8 @@
 namespace top {
 
 template <typename R, int P, int S>
-__global__ void __launch_bounds__(256) finalize_kernel(FinalArgs<R> a) {
+__device__ void finalize_segment(const FinalArgs<R>& a, int64_t i) {
   constexpr int N = 2 * P;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.S) return;
-  if (a.done != nullptr && a.done[a.traj[i]] != 0) return;  // stopped: its partials are final
   const int64_t ld = a.ld;
   const double T = a.T[i];
   const double iT = 1.0 / T;
@@ -85,6 +82,22 @@ __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs<R> a) {
   }
 }
 
+// With a stop flag per trajectory (residual checks) the grid is trajectory-major: x = trajectory,
+// y = 256-segment chunk of it, and the workgroups of stopped trajectories leave at once (their
+// partials are final); otherwise one lane per segment.
+template <typename R, int P, int S>
+__global__ void __launch_bounds__(256) finalize_kernel(FinalArgs<R> a) {
+  if (a.done != nullptr) {
+    const int b = blockIdx.x;
+    if (a.done[b] != 0) return;
+    const int64_t i = a.off[b] + (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (i < a.off[b + 1]) finalize_segment<R, P, S>(a, i);
+    return;
+  }
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < a.S) finalize_segment<R, P, S>(a, i);
+}
+
 // A workgroup converts 128 consecutive segments into LDS, then writes their 128 * 3n contiguous
 // output values with consecutive lanes (one segment's 3n values are 144 or 192 bytes apart from the
 // next one's, so per-lane stores straight from registers would not coalesce).
@@ -126,7 +139,9 @@ template hipError_t launch_coeffs<double>(int, const double*, const double*, int
 template <typename R>
 hipError_t launch_finalize(const Variant& v, const FinalArgs<R>& a, hipStream_t st) {
   const int bs = 256;
-  const dim3 grid((unsigned)((a.S + bs - 1) / bs)), block(bs);
+  const dim3 grid = a.done != nullptr ? dim3((unsigned)a.B, (unsigned)((a.max_len + bs - 1) / bs))
+                                      : dim3((unsigned)((a.S + bs - 1) / bs));
+  const dim3 block(bs);
   if (v.p == 3 && v.s == 3) hipLaunchKernelGGL((finalize_kernel<R, 3, 3>), grid, block, 0, st, a);
   else if (v.p == 3 && v.s == 4) hipLaunchKernelGGL((finalize_kernel<R, 3, 4>), grid, block, 0, st, a);
   else if (v.p == 4 && v.s == 4) hipLaunchKernelGGL((finalize_kernel<R, 4, 4>), grid, block, 0, st, a);
