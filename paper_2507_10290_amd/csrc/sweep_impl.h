@@ -28,10 +28,14 @@
 
 namespace top {
 
+// 1/sqrt(x).  For fp32 the hardware reciprocal square root alone: the library form adds a rescaling
+// of denormal inputs (five more instructions).  A denormal x only arises from a velocity split of
+// norm below 1e-19, where rsq of the flushed input is +inf and the projection factor min(1, vmax/|g|)
+// is 1 either way; for normal x both forms are the same instruction.
 template <typename R>
 __device__ inline R inv_sqrt(R x);
 template <>
-__device__ inline float inv_sqrt<float>(float x) { return rsqrtf(x); }
+__device__ inline float inv_sqrt<float>(float x) { return __builtin_amdgcn_rsqf(x); }
 template <>
 __device__ inline double inv_sqrt<double>(double x) { return 1.0 / sqrt(x); }
 
