@@ -178,9 +178,10 @@ top_status top_coeffs(const top_problem* h, double* coeffs);
  *   dcost       [dev] float64 [B]
  *   dwaypoints  [dev] float64 [S+B][3] (overwritten), or NULL
  *   ddurations  [dev] float64 [S] (overwritten), or NULL
- * TOP_E_STATE without a tape or after too many sweeps.  The block replays run on a second stream
- * the handle creates on first use (default priority), joined back into the handle's stream before
- * any reverse step that needs them; the call is asynchronous on the handle's stream like the others. */
+ * TOP_E_STATE without a tape or after too many sweeps.  The block replays run on a second stream of
+ * the device (default priority, created on first use and shared by all handles), joined back into
+ * the handle's stream before any reverse step that needs them; the call is asynchronous on the
+ * handle's stream like the others. */
 top_status top_backward(top_problem* h, const double* dcost, double* dwaypoints, double* ddurations);
 
 /* Time the candidate tile shapes on this problem (k_probe sweeps each, on scratch state, leaving the
@@ -239,7 +240,7 @@ top_status top_get_plan(const top_problem* h, top_plan_info* info);
 /* Release the handle; NULL is a no-op.  Its device buffers return to the library's pool without
  * waiting for the work still queued on the handle's stream: a later handle on the same stream reuses
  * them in stream order, one on another stream first waits (on the device) for that work.  Handles
- * that captured graphs or ran top_backward wait for their stream first. */
+ * that captured graphs wait for their stream first. */
 void top_destroy(top_problem* h);
 
 /* Thread-local text of the last error reported by this library on the calling thread. */

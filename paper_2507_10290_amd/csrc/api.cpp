@@ -382,6 +382,35 @@ top_status get_shape(const std::vector<int64_t>& off, std::shared_ptr<ShapeEntry
   return TOP_OK;
 }
 
+// ---- per-device second stream (default priority) and events of the reverse pass, created on first
+// use and kept for the process's lifetime.
+struct ReverseAux {
+  std::mutex mu;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+std::mutex g_aux_mu;
+std::map<int, ReverseAux*>& g_aux = *new std::map<int, ReverseAux*>();
+
+top_status reverse_aux(ReverseAux** out) {
+  int dev = 0;
+  TOP_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_aux_mu);
+  ReverseAux*& a = g_aux[dev];
+  if (a == nullptr) {
+    auto* n = new ReverseAux();
+    hipError_t e = hipStreamCreateWithFlags(&n->stream, hipStreamNonBlocking);
+    for (int k = 0; k < 5 && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&n->ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      delete n;  // its stream and events are left to the process's end
+      return fail(TOP_E_HIP, "reverse-pass stream setup failed: %s", hipGetErrorString(e));
+    }
+    a = n;
+  }
+  *out = a;
+  return TOP_OK;
+}
+
 // ---- pinned host words for the validation flags, so create can read them back without blocking
 // the launches queued behind the check.
 std::mutex g_pin_mu;
@@ -472,8 +501,6 @@ struct top_problem {
   double *wp64 = nullptr, *lo64 = nullptr, *hi64 = nullptr, *vmax64 = nullptr, *bc64 = nullptr;
   void *blk = nullptr, *adjb[2] = {nullptr, nullptr}, *acc_iT = nullptr, *acc_hd = nullptr, *acc_z0 = nullptr;
   double *dPL = nullptr, *dPR = nullptr, *dK = nullptr, *dK0 = nullptr;
-  hipStream_t rstream = nullptr;  // reverse pass: replays overlap the adjoint of the previous block
-  hipEvent_t ev_start = nullptr, ev_rep[2] = {nullptr, nullptr}, ev_adj[2] = {nullptr, nullptr};
   // residual checks: per-trajectory stop flag, sweep counters, current rho and the last change
   uint8_t *done_dev = nullptr, *fresh = nullptr;
   int32_t *swept = nullptr, *stop_at = nullptr;
@@ -608,11 +635,13 @@ struct top_problem {
     // keeping the state before every sweep, then reversed.  The replay of block j - 1 needs only the
     // tape, so it runs on a second stream while block j is reversed; the buffer it fills was last
     // read by the reversal of block j + 1.
-    if (rstream == nullptr) {
-      TOP_HIP(hipStreamCreateWithFlags(&rstream, hipStreamNonBlocking));
-      for (hipEvent_t* e : {&ev_start, &ev_rep[0], &ev_rep[1], &ev_adj[0], &ev_adj[1]})
-        TOP_HIP(hipEventCreateWithFlags(e, hipEventDisableTiming));
-    }
+    // The second stream and the events are the device's (created once): a backward call holds them
+    // while it queues its work; the waits it queues refer to the records it made.
+    ReverseAux* aux = nullptr;
+    if ((s = reverse_aux(&aux)) != TOP_OK) return s;
+    std::lock_guard<std::mutex> aux_lock(aux->mu);
+    hipStream_t rstream = aux->stream;
+    hipEvent_t ev_start = aux->ev[0], ev_rep[2] = {aux->ev[1], aux->ev[2]}, ev_adj[2] = {aux->ev[3], aux->ev[4]};
     auto buf_of = [&](int q) { return (R*)blk + (size_t)q * m * sl; };
     auto replay = [&](int j, hipStream_t st) -> top_status {
       const int n = std::min(K, j * m + m) - j * m;
@@ -863,7 +892,7 @@ void top_destroy(top_problem* h) {
   // Handles with graphs or a reverse-pass stream wait for their work; a plain handle releases its
   // buffers behind an event recorded on its stream and returns at once.
   std::shared_ptr<ReleaseEvent> done;
-  if (!h->graphs.empty() || h->cap_stream != nullptr || h->rstream != nullptr) {
+  if (!h->graphs.empty() || h->cap_stream != nullptr) {
     (void)hipStreamSynchronize(h->stream);
   } else {
     done = std::make_shared<ReleaseEvent>();
@@ -875,12 +904,6 @@ void top_destroy(top_problem* h) {
   }
   h->drop_graphs();
   if (h->cap_stream != nullptr) (void)hipStreamDestroy(h->cap_stream);
-  if (h->rstream != nullptr) {
-    (void)hipStreamSynchronize(h->rstream);
-    (void)hipStreamDestroy(h->rstream);
-  }
-  for (hipEvent_t e : {h->ev_start, h->ev_rep[0], h->ev_rep[1], h->ev_adj[0], h->ev_adj[1]})
-    if (e != nullptr) (void)hipEventDestroy(e);
   if (h->ev_valid != nullptr) {
     (void)hipEventSynchronize(h->ev_valid);  // the readback into the pinned word has landed
     (void)hipEventDestroy(h->ev_valid);
