@@ -13,8 +13,14 @@ value = segment-updates/s = (segments x sweeps) / (wall time per step).
 
 Prints one JSON line.  Extra measurements beside it (not part of `value`):
 the sweep kernel alone (HIP events on the library's stream) with its ALU
-roofline, the plain per-trajectory launch on a sample, the 65,536-segment
-septic trajectory, and the CPU oracle timed on a bounded sample on the host.
+roofline and the HBM traffic from the committed counter summary, the phases
+of a step (create / iterate / outputs), a measured device copy rate beside
+the one-pass HBM yardstick, the plain per-trajectory launch on a sample, the
+65,536-segment septic trajectory, forward and backward of the differentiation
+workload, residual checks with adaptive rho, the segment-count study on a
+parametric curve, NumericSolve against the closed form, the 8-face polytope
+workload, and the CPU oracle timed on a bounded sample on the host (median of
+three, plus one single-thread run).
 """
 from __future__ import annotations
 
