@@ -85,6 +85,10 @@ def test_host_argument_errors():
     o.max_taped_iters = 0
     st, h, msg = _create(1, [0, 3], o)
     assert st == binding.TOP_E_INVALID
+    o = binding.default_options()
+    o.check_every = 10                 # residual checks: trajectory-major grids bound the length
+    st, h, msg = _create(2, [0, 3, 3 + 65535 * 128 + 1], o)
+    assert st == binding.TOP_E_UNSUPPORTED and "at most" in msg
 
 
 def test_null_handle_calls():

@@ -241,6 +241,26 @@ def test_buffers_reused_across_streams_after_destroy():
     s1.synchronize()
 
 
+def test_many_live_handles_use_the_pageable_check_fallback():
+    # more live handles than pinned words for the input check (1024): the later ones read the
+    # check back through pageable memory; results and error reporting stay the same
+    from paper_2507_10290_amd import TopError, TopProblem
+    w = make_config(1, scale=4 / 1024)
+    ref = run_gpu(w, 20, "fp64")[0]
+    hs = [TopProblem.from_workload(w, precision="fp64", use_graph=False) for _ in range(1030)]
+    try:
+        bad = w.waypoints.copy()
+        bad[1, 0] = np.nan
+        with pytest.raises(TopError, match="waypoints"):
+            TopProblem(w.seg_offsets, bad, w.durations, w.rho)
+        hs[-1].iterate(20)
+        c = hs[-1].coeffs().cpu().numpy()
+    finally:
+        for h in hs:
+            h.close()
+    assert np.array_equal(c, ref)
+
+
 def test_autotune_keeps_results():
     w = make_config(3, n_traj=64)
     from paper_2507_10290_amd import TopProblem
