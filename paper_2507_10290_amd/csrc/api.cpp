@@ -500,6 +500,10 @@ struct top_problem {
   void* Hd = nullptr;
   double *wp64 = nullptr, *lo64 = nullptr, *hi64 = nullptr, *vmax64 = nullptr, *bc64 = nullptr;
   void *blk = nullptr, *adjb[2] = {nullptr, nullptr}, *acc_iT = nullptr, *acc_hd = nullptr, *acc_z0 = nullptr;
+  // The forward records the states of the block holding the last sweep of each top_iterate call into
+  // block buffer (block % 2), so the reverse pass need not replay that block: rec_block is the block,
+  // rec_upto the number of leading states of it present (state 0 is the block's checkpoint).
+  int rec_block = -1, rec_upto = 0;
   double *dPL = nullptr, *dPR = nullptr, *dK = nullptr, *dK0 = nullptr;
   // residual checks: per-trajectory stop flag, sweep counters, current rho and the last change
   uint8_t *done_dev = nullptr, *fresh = nullptr;
@@ -555,7 +559,7 @@ struct top_problem {
 
   template <typename R>
   top_status launch_one(const Plan& pl, const int32_t* lane_map, const void* in, void* outp, int n, bool fin,
-                        hipStream_t st, bool store_frozen) {
+                        hipStream_t st, bool store_frozen, void* rec) {
     top::SweepArgs<R> a = sweep_args<R>(pl, lane_map);
     a.st_in = (const R*)in;
     a.st_out = (R*)outp;
@@ -563,6 +567,10 @@ struct top_problem {
     a.final_out = fin ? 1 : 0;
     a.store_frozen = store_frozen ? 1 : 0;
     a.inner = opt.lbfgs_iters;
+    if (rec != nullptr) {  // recording launch: the state after sweep i < n - 1 goes to slot i + 1
+      a.rec = (R*)rec;
+      a.rec_slot = (int64_t)nf * ld;
+    }
     hipError_t e = v.num     ? top::launch_numeric_sweep<R>(v, a, pl.n_tiles, st)
                  : v.faces ? top::launch_poly_sweep<R>(v, a, pl.n_tiles, st)
                            : top::launch_sweep<R>(v, a, pl.n_tiles, st);
@@ -571,9 +579,15 @@ struct top_problem {
   }
 
   top_status sweep_launch(const Plan& pl, const int32_t* lane_map, const void* in, void* outp, int n, bool fin,
-                          hipStream_t st, bool store_frozen = false) {
-    return v.prec == 0 ? launch_one<float>(pl, lane_map, in, outp, n, fin, st, store_frozen)
-                       : launch_one<double>(pl, lane_map, in, outp, n, fin, st, store_frozen);
+                          hipStream_t st, bool store_frozen = false, void* rec = nullptr) {
+    return v.prec == 0 ? launch_one<float>(pl, lane_map, in, outp, n, fin, st, store_frozen, rec)
+                       : launch_one<double>(pl, lane_map, in, outp, n, fin, st, store_frozen, rec);
+  }
+
+  // Block buffers of the reverse pass (two blocks of checkpoint_every states), allocated on first use.
+  top_status ensure_blk() {
+    if (blk != nullptr) return TOP_OK;
+    return alloc(&blk, 2 * (size_t)opt.checkpoint_every * nf * ld * rsz);
   }
 
   template <typename R>
@@ -614,8 +628,8 @@ struct top_problem {
     const size_t sl = (size_t)nf * ld;
     top::Layout L{v.p, v.s, v.box, v.vel, v.faces, v.num};
     top_status s;
-    if (blk == nullptr) {
-      if ((s = alloc(&blk, 2 * (size_t)m * sl * sizeof(R))) != TOP_OK) return s;
+    if ((s = ensure_blk()) != TOP_OK) return s;
+    if (adjb[0] == nullptr) {
       for (int q = 0; q < 2; ++q)
         if ((s = alloc(&adjb[q], sl * sizeof(R))) != TOP_OK) return s;
       if ((s = alloc(&acc_iT, ld * sizeof(R))) != TOP_OK) return s;
@@ -666,10 +680,15 @@ struct top_problem {
     };
     int ai = 0;
     const int nblk = (K + m - 1) / m;
+    // the last block was recorded by the forward when its states are all in its buffer
+    const bool recorded = rec_block == nblk - 1 && rec_upto >= K - (nblk - 1) * m;
+    rec_block = -1;  // the replays below overwrite the block buffers
     TOP_HIP(hipEventRecord(ev_start, stream));
     TOP_HIP(hipStreamWaitEvent(rstream, ev_start, 0));
-    if ((s = replay(nblk - 1, rstream)) != TOP_OK) return s;
-    TOP_HIP(hipEventRecord(ev_rep[(nblk - 1) % 2], rstream));
+    if (!recorded) {
+      if ((s = replay(nblk - 1, rstream)) != TOP_OK) return s;
+      TOP_HIP(hipEventRecord(ev_rep[(nblk - 1) % 2], rstream));
+    }
     for (int j = nblk - 1; j >= 0; --j) {
       const int k_lo = j * m;
       const int n = std::min(K, k_lo + m) - k_lo;
@@ -679,7 +698,7 @@ struct top_problem {
         if ((s = replay(j - 1, rstream)) != TOP_OK) return s;
         TOP_HIP(hipEventRecord(ev_rep[(j - 1) % 2], rstream));
       }
-      TOP_HIP(hipStreamWaitEvent(stream, ev_rep[q], 0));
+      if (!(recorded && j == nblk - 1)) TOP_HIP(hipStreamWaitEvent(stream, ev_rep[q], 0));
       const R* ckpt = (const R*)tape + (size_t)j * sl;
       R* b = buf_of(q);
       int t_hi = n;
@@ -827,13 +846,37 @@ struct top_problem {
     const size_t sbytes = (size_t)nf * ld * rsz;
     if (ev0 != nullptr) TOP_HIP(hipEventRecord(ev0, st));
     bool checked_last = false;
+    const int m = opt.checkpoint_every;
+    const int j_last = tape != nullptr ? (done0 + k - 1) / m : -1;  // block of this call's last sweep
     while (remaining > 0) {
       const int n = chunk(remaining, done);
       const bool check = opt.check_every > 0 && (done + n) % opt.check_every == 0;
       const bool fin = (n == remaining) || check;
-      top_status s = sweep_launch(plan_ref(), lanes(), state[c], state[c ^ 1], n, fin, st);
+      // record the states of block j_last (launches never cross a checkpoint boundary)
+      void* rec = nullptr;
+      const int t0 = tape != nullptr ? done - j_last * m : 0;
+      if (tape != nullptr && done / m == j_last) {
+        if (t0 == 0) {
+          rec_block = j_last;
+          rec_upto = 1;
+        }
+        if (rec_block == j_last && rec_upto == t0 + 1) {
+          top_status s = ensure_blk();
+          if (s != TOP_OK) return s;
+          rec = (char*)blk + ((size_t)(j_last % 2) * m + t0) * sbytes;
+        }
+      }
+      top_status s = sweep_launch(plan_ref(), lanes(), state[c], state[c ^ 1], n, fin, st, false, rec);
       if (s != TOP_OK) return s;
       c ^= 1;
+      if (rec != nullptr) {
+        if (t0 + n < m) {  // the block goes on in a later launch: keep the state it starts from
+          TOP_HIP(hipMemcpyAsync((char*)rec + (size_t)n * sbytes, state[c], sbytes, hipMemcpyDeviceToDevice, st));
+          rec_upto = t0 + n + 1;
+        } else {
+          rec_upto = m;
+        }
+      }
       remaining -= n;
       done += n;
       checked_last = check;

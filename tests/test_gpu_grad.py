@@ -131,6 +131,28 @@ def test_central_differences_fp64():
     assert checked == 8
 
 
+@pytest.mark.parametrize("precision,splits,m,kw", [("fp64", [25], 7, {}), ("fp64", [9, 4, 12], 5, {}),
+                                                  ("fp32", [17, 8], 6, {"tile_lanes": 64, "halo": 4})])
+def test_recorded_last_block_equals_its_replay(precision, splits, m, kw):
+    # the forward keeps the states of the block holding its last sweep, so the reverse pass skips
+    # replaying it; a second reverse pass finds the buffers overwritten and replays every block.
+    # Both must give the same gradients bit for bit, whatever the iterate calls' split.
+    from paper_2507_10290_amd import TopProblem
+    w = make_config(1, scale=150 / 1024)
+    w.precision = precision
+    K = sum(splits)
+    dc = torch.ones(1, dtype=torch.float64)
+    prob = TopProblem.from_workload(w, precision=precision, checkpoint_every=m, max_taped_iters=K, **kw)
+    for k in splits:
+        prob.iterate(k)
+    a = [x.cpu().numpy() for x in prob.backward(dc)]
+    b = [x.cpu().numpy() for x in prob.backward(dc)]
+    prob.close()
+    ref = gpu_grad(w, K, m, precision, [1.0], **kw)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[0], ref[1]) and np.array_equal(a[1], ref[2])
+
+
 def test_autograd_function_matches_backward():
     from paper_2507_10290_amd import top_cost_fn
     w = make_config(4, n_traj=3)
