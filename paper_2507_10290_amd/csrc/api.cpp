@@ -629,22 +629,22 @@ struct top_problem {
     top::Layout L{v.p, v.s, v.box, v.vel, v.faces, v.num};
     top_status s;
     if ((s = ensure_blk()) != TOP_OK) return s;
+    // Everything that starts at zero sits in one allocation, cleared by one launch: the adjoint of
+    // the state after the last sweep (adjb[0]) and the per-segment accumulators.
+    const int64_t nzero = (int64_t)sl + (2 + 3 * (int64_t)v.s) * ld;
     if (adjb[0] == nullptr) {
-      for (int q = 0; q < 2; ++q)
-        if ((s = alloc(&adjb[q], sl * sizeof(R))) != TOP_OK) return s;
-      if ((s = alloc(&acc_iT, ld * sizeof(R))) != TOP_OK) return s;
-      if ((s = alloc(&acc_hd, ld * sizeof(R))) != TOP_OK) return s;
-      if ((s = alloc(&acc_z0, 3 * (size_t)v.s * ld * sizeof(R))) != TOP_OK) return s;
+      if ((s = alloc(&adjb[0], (size_t)nzero * sizeof(R))) != TOP_OK) return s;
+      if ((s = alloc(&adjb[1], sl * sizeof(R))) != TOP_OK) return s;
+      acc_iT = (R*)adjb[0] + sl;
+      acc_hd = (R*)acc_iT + ld;
+      acc_z0 = (R*)acc_hd + ld;
       for (double** p : {&dPL, &dPR, &dK, &dK0})
         if ((s = alloc(p, (size_t)S * 3 * sizeof(double))) != TOP_OK) return s;
     }
     auto chk = [](hipError_t e) -> top_status {
       return e == hipSuccess ? TOP_OK : fail(TOP_E_HIP, "backward launch failed: %s", hipGetErrorString(e));
     };
-    if ((s = chk(top::launch_fill<R>((R*)adjb[0], (int64_t)sl, R(0), stream))) != TOP_OK) return s;
-    if ((s = chk(top::launch_fill<R>((R*)acc_iT, ld, R(0), stream))) != TOP_OK) return s;
-    if ((s = chk(top::launch_fill<R>((R*)acc_hd, ld, R(0), stream))) != TOP_OK) return s;
-    if ((s = chk(top::launch_fill<R>((R*)acc_z0, 3 * v.s * ld, R(0), stream))) != TOP_OK) return s;
+    if ((s = chk(top::launch_fill<R>((R*)adjb[0], nzero, R(0), stream))) != TOP_OK) return s;
     // Block j is replayed from its checkpoint (read in place from the tape) into block buffer j % 2,
     // keeping the state before every sweep, then reversed.  The replay of block j - 1 needs only the
     // tape, so it runs on a second stream while block j is reversed; the buffer it fills was last
