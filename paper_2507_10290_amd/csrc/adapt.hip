@@ -31,6 +31,7 @@ __global__ void check_kernel(CheckArgs a) {
       a.done[b] = 1;
       a.stop_at[b] = a.swept[b];
       a.fresh[b] = 1;
+      a.lists[atomicAdd(&a.counts[0], 1)] = b;   // list order is irrelevant: entries are independent
     } else if (a.adapt) {
       const double old = a.rho[b];
       double nw = old;
@@ -39,6 +40,7 @@ __global__ void check_kernel(CheckArgs a) {
       if (nw != old) {
         ratio = old / nw;
         a.rho[b] = nw;
+        a.lists[a.B + atomicAdd(&a.counts[1], 1)] = b;
       }
     }
   }
@@ -50,17 +52,32 @@ hipError_t launch_check(const CheckArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-// Trajectory-major grid (the workgroups of trajectories that did not just stop leave at once); a
-// lane copies a segment's state column, issuing the loads of a batch of rows before their stores,
-// so it waits for memory once per batch rather than once per row.
+__global__ void reset_counts_kernel(int32_t* counts) {
+  if (threadIdx.x < 2) counts[threadIdx.x] = 0;
+}
+
+hipError_t launch_reset_counts(int32_t* counts, hipStream_t st) {
+  hipLaunchKernelGGL(reset_counts_kernel, dim3(1), dim3(64), 0, st, counts);
+  return hipGetLastError();
+}
+
+// Workgroups walk the list of a check (x, grid-stride) and a trajectory's segments in chunks of the
+// workgroup size (y); with an empty list every workgroup leaves at once.
+constexpr int kListBlocks = 256;
+
+// Over the trajectories that stopped at this check; a lane copies a segment's state column, issuing
+// the loads of a batch of rows before their stores, so it waits for memory once per batch rather
+// than once per row.
 template <typename R>
-__global__ void __launch_bounds__(256) freeze_copy_kernel(const R* cur, R* other, const uint8_t* fresh,
-                                                          const int64_t* off, int nf, int64_t ld) {
+__global__ void __launch_bounds__(256) freeze_copy_kernel(const R* cur, R* other, const int32_t* list,
+                                                          const int32_t* count, const int64_t* off, int nf,
+                                                          int64_t ld) {
   constexpr int kBatch = 16;
-  const int b = blockIdx.x;
-  if (fresh[b] == 0) return;
-  const int64_t i = off[b] + (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-  if (i < off[b + 1]) {
+  const int n = *count;
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const int b = list[q];
+    const int64_t i = off[b] + (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (i >= off[b + 1]) continue;
     for (int f0 = 0; f0 < nf; f0 += kBatch) {
       R v[kBatch];
 #pragma unroll
@@ -73,15 +90,16 @@ __global__ void __launch_bounds__(256) freeze_copy_kernel(const R* cur, R* other
   }
 }
 
-hipError_t launch_freeze_copy(const void* cur, void* other, const uint8_t* fresh, const int64_t* off, int B,
-                              int64_t max_len, int nf, int64_t ld, size_t rsz, hipStream_t st) {
-  const dim3 grid((unsigned)B, (unsigned)((max_len + 255) / 256)), block(256);
+hipError_t launch_freeze_copy(const void* cur, void* other, const int32_t* list, const int32_t* count,
+                              const int64_t* off, int B, int64_t max_len, int nf, int64_t ld, size_t rsz,
+                              hipStream_t st) {
+  const dim3 grid((unsigned)std::min(B, kListBlocks), (unsigned)((max_len + 255) / 256)), block(256);
   if (rsz == sizeof(float))
-    hipLaunchKernelGGL(freeze_copy_kernel<float>, grid, block, 0, st, (const float*)cur, (float*)other, fresh, off,
-                       nf, ld);
-  else
-    hipLaunchKernelGGL(freeze_copy_kernel<double>, grid, block, 0, st, (const double*)cur, (double*)other, fresh,
+    hipLaunchKernelGGL(freeze_copy_kernel<float>, grid, block, 0, st, (const float*)cur, (float*)other, list, count,
                        off, nf, ld);
+  else
+    hipLaunchKernelGGL(freeze_copy_kernel<double>, grid, block, 0, st, (const double*)cur, (double*)other, list,
+                       count, off, nf, ld);
   return hipGetLastError();
 }
 
@@ -135,22 +153,22 @@ __device__ void rescale_segment(const RescaleArgs<R>& a, int64_t i, int b, doubl
   }
 }
 
-// KF = kFaces: polytope corridor (one y per face and sample, one matrix per rotated axis).
-// Trajectory-major grid (x = trajectory, y = chunk of 128 of its segments); the workgroups of
-// trajectories whose rho did not change leave at once.
+// KF = kFaces: polytope corridor (one y per face and sample, one matrix per rotated axis).  Over the
+// trajectories whose rho changed at this check (y = chunk of 128 of a trajectory's segments).
 template <typename R, int P, int S, bool BOX, bool VEL, int KF = 0>
 __global__ void __launch_bounds__(128) rescale_kernel(RescaleArgs<R> a) {
-  const int b = blockIdx.x;
-  const double r = a.ratio[b];
-  if (r == 1.0) return;
-  const int64_t i = a.off[b] + (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-  if (i < a.off[b + 1]) rescale_segment<R, P, S, BOX, VEL, KF>(a, i, b, r);
+  const int n = *a.count;
+  for (int q = blockIdx.x; q < n; q += gridDim.x) {
+    const int b = a.list[q];
+    const int64_t i = a.off[b] + (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+    if (i < a.off[b + 1]) rescale_segment<R, P, S, BOX, VEL, KF>(a, i, b, a.ratio[b]);
+  }
 }
 
 template <typename R>
 hipError_t launch_rescale(const Variant& v, const RescaleArgs<R>& a, hipStream_t st) {
   const int bs = 128;
-  const dim3 grid((unsigned)a.B, (unsigned)((a.max_len + bs - 1) / bs)), block(bs);
+  const dim3 grid((unsigned)std::min(a.B, kListBlocks), (unsigned)((a.max_len + bs - 1) / bs)), block(bs);
   if (v.faces != 0) {
     if (v.faces != kFaces || v.box || a.lam == nullptr) return hipErrorInvalidValue;
 #define TOP_RESCALE_POLY(P_, S_, V_)                                                        \

@@ -509,6 +509,7 @@ struct top_problem {
   uint8_t *done_dev = nullptr, *fresh = nullptr;
   int32_t *swept = nullptr, *stop_at = nullptr;
   double *rho_traj = nullptr, *ratio = nullptr;
+  int32_t *check_lists = nullptr, *check_counts = nullptr;  // [2][B] and [2]: per-check work lists
   // launch sequences replayed as graphs, keyed by (sweeps, start buffer, sweep index mod check_every)
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
   std::set<std::tuple<int, int, int>> graph_seen;  // sequences launched once directly
@@ -807,10 +808,14 @@ struct top_problem {
     ca.stop_at = stop_at;
     ca.rho = rho_traj;
     ca.ratio = ratio;
+    ca.lists = check_lists;
+    ca.counts = check_counts;
+    if ((e = top::launch_reset_counts(check_counts, st)) != hipSuccess)
+      return fail(TOP_E_HIP, "check reset failed: %s", hipGetErrorString(e));
     if ((e = top::launch_check(ca, st)) != hipSuccess)
       return fail(TOP_E_HIP, "check launch failed: %s", hipGetErrorString(e));
-    if ((e = top::launch_freeze_copy(state[c], state[c ^ 1], fresh, off_dev, B, max_len, nf, ld, rsz, st)) !=
-        hipSuccess)
+    if ((e = top::launch_freeze_copy(state[c], state[c ^ 1], check_lists, check_counts, off_dev, B, max_len, nf,
+                                     ld, rsz, st)) != hipSuccess)
       return fail(TOP_E_HIP, "freeze copy failed: %s", hipGetErrorString(e));
     if (!opt.adapt_rho) return TOP_OK;
     e = v.prec == 0 ? rescale_t<float>(c, st) : rescale_t<double>(c, st);
@@ -836,6 +841,8 @@ struct top_problem {
     ra.off = off_dev;
     ra.B = B;
     ra.max_len = max_len;
+    ra.list = check_lists + B;
+    ra.count = check_counts + 1;
     return top::launch_rescale<R>(v, ra, st);
   }
 
@@ -1080,6 +1087,8 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     if ((st = h->alloc(&h->swept, (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
     if ((st = h->alloc(&h->stop_at, (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
     if ((st = h->alloc(&h->ratio, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->check_lists, 2 * (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->check_counts, 2 * sizeof(int32_t))) != TOP_OK) return bail(st);
     hipError_t e = hipMemsetAsync(h->done_dev, 0, (size_t)n_traj, stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->swept, 0, (size_t)n_traj * sizeof(int32_t), stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->stop_at, 0xff, (size_t)n_traj * sizeof(int32_t), stream);

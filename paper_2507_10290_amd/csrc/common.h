@@ -250,14 +250,19 @@ struct CheckArgs {
   int32_t* stop_at;       // [B] sweeps applied when it stopped
   double* rho;            // [B] current penalty
   double* ratio;          // [B] rho_old / rho_new at this check, 1 when unchanged
+  int32_t* lists;         // [2][B] the trajectories that stopped / whose rho changed at this check
+  int32_t* counts;        // [2] their numbers (zeroed before the check)
 };
 hipError_t launch_check(const CheckArgs& a, hipStream_t st);
+// Zero the two list lengths of a check (a one-lane kernel, so that a captured graph holds no memset).
+hipError_t launch_reset_counts(int32_t* counts, hipStream_t st);
 // Copy the state of the trajectories that just stopped into the other ping-pong buffer (nf fields of
 // rsz bytes per segment), so that later sweeps can leave them alone.
-// off [B + 1] are the segment offsets; the grid is trajectory-major (x = trajectory, y = chunk of
-// 256 of its segments, max_len = the longest trajectory's segment count).
-hipError_t launch_freeze_copy(const void* cur, void* other, const uint8_t* fresh, const int64_t* off, int B,
-                              int64_t max_len, int nf, int64_t ld, size_t rsz, hipStream_t st);
+// list / count: the trajectories that stopped at this check (check_kernel's first list); off [B + 1]
+// the segment offsets, max_len the longest trajectory's segment count.
+hipError_t launch_freeze_copy(const void* cur, void* other, const int32_t* list, const int32_t* count,
+                              const int64_t* off, int B, int64_t max_len, int nf, int64_t ld, size_t rsz,
+                              hipStream_t st);
 
 template <typename R>
 struct RescaleArgs {
@@ -275,6 +280,8 @@ struct RescaleArgs {
   const int64_t* off;     // [B + 1] segment offsets (trajectory-major grid)
   int B;
   int64_t max_len;        // segments of the longest trajectory
+  const int32_t* list;    // the trajectories whose rho changed at this check
+  const int32_t* count;   // their number
 };
 template <typename R>
 hipError_t launch_rescale(const Variant& v, const RescaleArgs<R>& a, hipStream_t st);
