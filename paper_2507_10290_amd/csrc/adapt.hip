@@ -43,6 +43,7 @@ __global__ void check_kernel(CheckArgs a) {
         a.lists[a.B + atomicAdd(&a.counts[1], 1)] = b;
       }
     }
+    if (a.done[b] == 0) a.lists[2 * a.B + atomicAdd(&a.counts[2], 1)] = b;
   }
   a.ratio[b] = ratio;
 }
@@ -53,7 +54,18 @@ hipError_t launch_check(const CheckArgs& a, hipStream_t st) {
 }
 
 __global__ void reset_counts_kernel(int32_t* counts) {
-  if (threadIdx.x < 2) counts[threadIdx.x] = 0;
+  if (threadIdx.x < 3) counts[threadIdx.x] = 0;
+}
+
+__global__ void all_running_kernel(int32_t* lists, int32_t* counts, int B) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) lists[2 * B + b] = b;
+  if (b == 0) counts[2] = B;
+}
+
+hipError_t launch_all_running(int32_t* lists, int32_t* counts, int B, hipStream_t st) {
+  hipLaunchKernelGGL(all_running_kernel, dim3((B + 255) / 256), dim3(256), 0, st, lists, counts, B);
+  return hipGetLastError();
 }
 
 hipError_t launch_reset_counts(int32_t* counts, hipStream_t st) {

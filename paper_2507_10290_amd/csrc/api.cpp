@@ -482,6 +482,7 @@ struct top_problem {
     a.n_chunks = n_chunks;
     a.chunk_sum = chunk_sum;
     a.out = out;
+    a.done = opt.check_every > 0 ? done_dev : nullptr;
     return a;
   }
   std::shared_ptr<PlanEntry> pe;
@@ -509,7 +510,7 @@ struct top_problem {
   uint8_t *done_dev = nullptr, *fresh = nullptr;
   int32_t *swept = nullptr, *stop_at = nullptr;
   double *rho_traj = nullptr, *ratio = nullptr;
-  int32_t *check_lists = nullptr, *check_counts = nullptr;  // [2][B] and [2]: per-check work lists
+  int32_t *check_lists = nullptr, *check_counts = nullptr;  // [3][B] and [3]: per-check work lists
   // launch sequences replayed as graphs, keyed by (sweeps, start buffer, sweep index mod check_every)
   std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
   std::set<std::tuple<int, int, int>> graph_seen;  // sequences launched once directly
@@ -613,6 +614,8 @@ struct top_problem {
     a.off = off_dev;
     a.B = B;
     a.max_len = max_len;
+    a.live = check_lists != nullptr ? check_lists + 2 * B : nullptr;
+    a.live_count = check_counts != nullptr ? check_counts + 2 : nullptr;
     hipError_t e = top::launch_finalize<R>(v, a, st);
     if (e != hipSuccess) return fail(TOP_E_HIP, "finalize launch failed: %s", hipGetErrorString(e));
     return TOP_OK;
@@ -1087,11 +1090,12 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     if ((st = h->alloc(&h->swept, (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
     if ((st = h->alloc(&h->stop_at, (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
     if ((st = h->alloc(&h->ratio, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->check_lists, 2 * (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->check_counts, 2 * sizeof(int32_t))) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->check_lists, 3 * (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
+    if ((st = h->alloc(&h->check_counts, 3 * sizeof(int32_t))) != TOP_OK) return bail(st);
     hipError_t e = hipMemsetAsync(h->done_dev, 0, (size_t)n_traj, stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->swept, 0, (size_t)n_traj * sizeof(int32_t), stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->stop_at, 0xff, (size_t)n_traj * sizeof(int32_t), stream);
+    if (e == hipSuccess) e = top::launch_all_running(h->check_lists, h->check_counts, n_traj, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "check state reset failed: %s", hipGetErrorString(e)));
   }
   {

@@ -206,6 +206,8 @@ struct FinalArgs {
   const int64_t* off;   // [B + 1] segment offsets (used with done: a trajectory-major grid)
   int B;
   int64_t max_len;      // segments of the longest trajectory
+  const int32_t* live;        // with done: the trajectories still running (the last check's list)
+  const int32_t* live_count;  // and their number
 };
 
 template <typename R>
@@ -231,6 +233,7 @@ struct ReduceArgs {
   int n_chunks;
   double* chunk_sum;         // [3][n_chunks] scratch
   double* out;               // [3][B]
+  const uint8_t* done;       // [B] or null: stopped trajectories keep their sums (skipped)
 };
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t st);
 
@@ -250,12 +253,15 @@ struct CheckArgs {
   int32_t* stop_at;       // [B] sweeps applied when it stopped
   double* rho;            // [B] current penalty
   double* ratio;          // [B] rho_old / rho_new at this check, 1 when unchanged
-  int32_t* lists;         // [2][B] the trajectories that stopped / whose rho changed at this check
-  int32_t* counts;        // [2] their numbers (zeroed before the check)
+  int32_t* lists;         // [3][B] the trajectories that stopped / whose rho changed at this check /
+                          // that still run after it
+  int32_t* counts;        // [3] their numbers (zeroed before the check)
 };
 hipError_t launch_check(const CheckArgs& a, hipStream_t st);
-// Zero the two list lengths of a check (a one-lane kernel, so that a captured graph holds no memset).
+// Zero the three list lengths of a check (a one-lane kernel, so that a captured graph holds no memset).
 hipError_t launch_reset_counts(int32_t* counts, hipStream_t st);
+// The list of running trajectories before the first check: every trajectory.
+hipError_t launch_all_running(int32_t* lists, int32_t* counts, int B, hipStream_t st);
 // Copy the state of the trajectories that just stopped into the other ping-pong buffer (nf fields of
 // rsz bytes per segment), so that later sweeps can leave them alone.
 // list / count: the trajectories that stopped at this check (check_kernel's first list); off [B + 1]

@@ -82,16 +82,18 @@ __device__ void finalize_segment(const FinalArgs<R>& a, int64_t i) {
   }
 }
 
-// With a stop flag per trajectory (residual checks) the grid is trajectory-major: x = trajectory,
-// y = 256-segment chunk of it, and the workgroups of stopped trajectories leave at once (their
-// partials are final); otherwise one lane per segment.
+// With residual checks the workgroups walk the list of running trajectories (x, grid-stride; y =
+// 256-segment chunk of a trajectory): stopped ones keep their final partials.  Otherwise one lane
+// per segment.
 template <typename R, int P, int S>
 __global__ void __launch_bounds__(256) finalize_kernel(FinalArgs<R> a) {
   if (a.done != nullptr) {
-    const int b = blockIdx.x;
-    if (a.done[b] != 0) return;
-    const int64_t i = a.off[b] + (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
-    if (i < a.off[b + 1]) finalize_segment<R, P, S>(a, i);
+    const int n = *a.live_count;
+    for (int q = blockIdx.x; q < n; q += gridDim.x) {
+      const int b = a.live[q];
+      const int64_t i = a.off[b] + (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+      if (i < a.off[b + 1]) finalize_segment<R, P, S>(a, i);
+    }
     return;
   }
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -139,7 +141,7 @@ template hipError_t launch_coeffs<double>(int, const double*, const double*, int
 template <typename R>
 hipError_t launch_finalize(const Variant& v, const FinalArgs<R>& a, hipStream_t st) {
   const int bs = 256;
-  const dim3 grid = a.done != nullptr ? dim3((unsigned)a.B, (unsigned)((a.max_len + bs - 1) / bs))
+  const dim3 grid = a.done != nullptr ? dim3((unsigned)std::min(a.B, 1024), (unsigned)((a.max_len + bs - 1) / bs))
                                       : dim3((unsigned)((a.S + bs - 1) / bs));
   const dim3 block(bs);
   if (v.p == 3 && v.s == 3) hipLaunchKernelGGL((finalize_kernel<R, 3, 3>), grid, block, 0, st, a);
@@ -163,6 +165,7 @@ __global__ void __launch_bounds__(256) reduce_chunks_kernel(ReduceArgs a) {
   const int c = blockIdx.x;
   if (c >= a.n_chunks) return;
   const int b = a.chunk_traj[c];
+  if (a.done != nullptr && a.done[b] != 0) return;  // stopped: its sums are final
   const int64_t s0 = a.off[b] + (int64_t)(c - a.chunk_off[b]) * kReduceChunk;
   const int64_t s1 = s0 + kReduceChunk < a.off[b + 1] ? s0 + kReduceChunk : a.off[b + 1];
   const int t = threadIdx.x;
@@ -193,6 +196,7 @@ __global__ void __launch_bounds__(256) reduce_chunks_kernel(ReduceArgs a) {
 __global__ void reduce_traj_kernel(ReduceArgs a) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= a.B) return;
+  if (a.done != nullptr && a.done[b] != 0) return;
   for (int q = 0; q < 3; ++q) {
     double acc = 0.0;
     for (int c = a.chunk_off[b]; c < a.chunk_off[b + 1]; ++c) acc += a.chunk_sum[(int64_t)q * a.n_chunks + c];
