@@ -437,6 +437,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter scale)")
     ap.add_argument("--counters-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the markdown summary of two rocprofv3 counter runs and exit (no GPU)")
+    ap.add_argument("--solve-config", type=int, nargs="+", metavar="I",
+                    help="solve each listed benchmark workload once (fp32, default plan) and exit; "
+                         "a short program to run under a profiler")
     a = ap.parse_args()
     if a.counters_summary:
         print(counters_summary(*a.counters_summary))
@@ -451,6 +454,16 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
     from paper_2507_10290_amd.workloads import config_summary, make_config
+
+    if a.solve_config:
+        for i in a.solve_config:
+            wi = make_config(i)
+            prob = _problem(wi, _dev_inputs(wi, "cuda:0"), precision="fp32")
+            prob.iterate(wi.iters)
+            torch.cuda.synchronize()
+            print(f"config {i}: {config_summary(wi)['workload']}, plan {prob.plan()}", flush=True)
+            prob.close()
+        return
 
     dev = torch.device("cuda:0")
     w = make_config(3)
