@@ -230,6 +230,25 @@ def fwd_bwd(w, d, K, m, reps=3):
             "fwd_plus_bwd_segment_updates_per_s": round(w.n_seg * K / (f + b), 1)}
 
 
+def septic_leg(w2, d2):
+    """The 65,536-segment septic trajectory: tuned plan, whole solves, and the sweep launches alone."""
+    pt = _problem(w2, d2, precision="fp32")
+    pt.tune(32)
+    pt.close()
+    sec2 = time_steps(lambda: solve_step(w2, d2, w2.iters), 2, 1)
+    ph2 = phase_ms(w2, d2, w2.iters)
+    kms2, l2, plan2 = sweep_kernel_ms(w2, d2, w2.iters)
+    return {
+        "segment_updates_per_s": round(w2.n_seg * w2.iters / sec2, 1),
+        "sweep_only_segment_updates_per_s": round(w2.n_seg * w2.iters / (kms2 * 1e-3), 1),
+        "ms_per_solve": round(sec2 * 1e3, 3), "phases_ms": ph2, "tile_lanes": plan2["tile_lanes"],
+        "halo": plan2["halo"], "launches": l2,
+        "alu_frac": round(flops_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters / (kms2 * 1e-3)
+                          / PEAK_FP32_NONPACKED, 4),
+        "hbm_yardstick_frac": round(bytes_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters
+                                    / (kms2 * 1e-3) / HBM_PEAK, 3)}
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -437,6 +456,9 @@ def main():
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter scale)")
     ap.add_argument("--counters-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the markdown summary of two rocprofv3 counter runs and exit (no GPU)")
+    ap.add_argument("--leg", choices=["fwd_bwd", "septic"],
+                    help="run one extra leg alone (the differentiation workload's forward and backward, or "
+                         "the 65,536-segment septic solve), print its figures and exit; for profilers")
     ap.add_argument("--solve-config", type=int, nargs="+", metavar="I",
                     help="solve each listed benchmark workload once (fp32, default plan) and exit; "
                          "a short program to run under a profiler")
@@ -466,6 +488,14 @@ def main():
         return
 
     dev = torch.device("cuda:0")
+    if a.leg == "fwd_bwd":
+        w4 = make_config(4)
+        print(json.dumps({"fwd_bwd": fwd_bwd(w4, _dev_inputs(w4, dev), w4.iters, 10)}), flush=True)
+        return
+    if a.leg == "septic":
+        w2 = make_config(2)
+        print(json.dumps({"septic_65536": septic_leg(w2, _dev_inputs(w2, dev))}), flush=True)
+        return
     w = make_config(3)
     K = w.iters
     d = _dev_inputs(w, dev)
@@ -517,23 +547,7 @@ def main():
         extra["plain_sample"] = f"first {nplain} trajectories, one handle each, no graph"
         extra["batched_over_plain"] = round(value / pr, 1)
         w2 = make_config(2)
-        d2 = _dev_inputs(w2, dev)
-        pt = _problem(w2, d2, precision="fp32")
-        pt.tune(32)
-        pt.close()
-        sec2 = time_steps(lambda: solve_step(w2, d2, w2.iters), 2, 1)
-        ph2 = phase_ms(w2, d2, w2.iters)
-        kms2, l2, plan2 = sweep_kernel_ms(w2, d2, w2.iters)
-        extra["septic_65536"] = {
-            "segment_updates_per_s": round(w2.n_seg * w2.iters / sec2, 1),
-            "sweep_only_segment_updates_per_s": round(w2.n_seg * w2.iters / (kms2 * 1e-3), 1),
-            "ms_per_solve": round(sec2 * 1e3, 3), "phases_ms": ph2, "tile_lanes": plan2["tile_lanes"],
-            "halo": plan2["halo"],
-            "alu_frac": round(flops_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters / (kms2 * 1e-3)
-                              / PEAK_FP32_NONPACKED, 4),
-            "hbm_yardstick_frac": round(bytes_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters
-                                        / (kms2 * 1e-3) / HBM_PEAK, 3)}
-        del d2
+        extra["septic_65536"] = septic_leg(w2, _dev_inputs(w2, dev))
         w4 = make_config(4)
         extra["fwd_bwd"] = fwd_bwd(w4, _dev_inputs(w4, dev), w4.iters, 10)
         extra["adaptive_rho"] = adaptive_leg(w, d, K, sec)

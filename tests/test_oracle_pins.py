@@ -414,3 +414,176 @@ def test_workloads_shapes_and_determinism():
     P = w1.waypoints
     assert np.all(w1.box_lo <= np.minimum(P[:-1], P[1:]) - 0.3 + 1e-12)
     assert np.all(w1.box_hi >= np.maximum(P[:-1], P[1:]) + 0.3 - 1e-12)
+
+
+# --------------------------------------------------------------------------- dual residual, by numpy
+
+def _np_boundary_rows(T, d, left_orders, right_orders):
+    """Rows of the boundary map built from numpy polynomial derivatives of the unit monomials:
+    the left knot's orders at t = 0, then the right knot's at t = T."""
+    n = d + 1
+    rows = []
+    for t, orders in ((0.0, left_orders), (T, right_orders)):
+        for o in orders:
+            r = np.zeros(n)
+            for j in range(n):
+                e = np.zeros(n)
+                e[j] = 1.0
+                r[j] = nppoly.polyval(t, nppoly.polyder(e, o)) if o else nppoly.polyval(t, e)
+            rows.append(r)
+    return np.array(rows)
+
+
+@pytest.mark.parametrize("n_cont", [3, 4])
+def test_dual_residual_by_numpy(n_cont):
+    """||r_d||^2 of Sec. III-D.3 (eq. splitting_dual_residual, read per segment): for every segment,
+    rho times the transposed boundary map applied to the change of its knot pair, summed in squares
+    per trajectory.  Recomputed here from the oracle's knots z^k, z^{k+1} with boundary rows built by
+    numpy differentiation; three trajectories with rho 0.5, 1 and 2, so a dropped rho fails, and the
+    boundary map is not symmetric, so M in place of M^T fails too."""
+    w = random_walk_batch("rd", [4, 3, 5], [11, 12, 13], order=3, n_cont=n_cont, rho=[0.5, 1.0, 2.0],
+                          precision="fp64")
+    pr = cadmm.problem_from_workload(w)
+    mats, chol = cadmm.setup(pr)
+    st = cadmm.init_state(pr, mats)
+    for _ in range(6):
+        st, _, _ = cadmm.iterate(pr, mats, chol, st)
+    st2, _, rd2 = cadmm.iterate(pr, mats, chol, st)
+    z0, z1 = st.z.numpy(), st2.z.numpy()            # [S+B, 3, s]
+    T = w.durations
+    p, s, d = pr.p, pr.s, pr.d
+    want = np.zeros(pr.B)
+    wrong_norho = np.zeros(pr.B)
+    wrong_M = np.zeros(pr.B)
+    for b in range(pr.B):
+        s0, s1 = int(w.seg_offsets[b]), int(w.seg_offsets[b + 1])
+        for i in range(s0, s1):
+            kl, kr = i + b, i + b + 1                # knot rows of this segment's two ends
+            left = range(p) if i == s0 else range(s)
+            right = range(p) if i == s1 - 1 else range(s)
+            Mi = _np_boundary_rows(T[i], d, left, right)
+            for a in range(3):
+                dz = np.concatenate([z1[kl, a, list(left)] - z0[kl, a, list(left)],
+                                     z1[kr, a, list(right)] - z0[kr, a, list(right)]])
+                r = w.rho[b] * (Mi.T @ dz)
+                want[b] += r @ r
+                wrong_norho[b] += (Mi.T @ dz) @ (Mi.T @ dz)
+                if Mi.shape[0] == Mi.shape[1]:
+                    q = w.rho[b] * (Mi @ dz)
+                    wrong_M[b] += q @ q
+    got = rd2.numpy()
+    assert np.all(want > 0)
+    assert np.allclose(got, want, rtol=1e-10, atol=0), (got, want)
+    # the workload tells the readings apart
+    assert np.max(np.abs(wrong_norho - want) / want) > 0.5
+    if n_cont == 3:
+        assert np.max(np.abs(wrong_M - want) / want) > 0.1
+
+
+# --------------------------------------------------------------------------- non-rest end states
+
+def _np_gram(T, p, d):
+    """int_0^T of the p-th derivatives of the monomials, by numpy polynomial integration."""
+    n = d + 1
+    Q = np.zeros((n, n))
+    for j in range(n):
+        for k in range(n):
+            ej = np.zeros(n); ej[j] = 1.0
+            ek = np.zeros(n); ek[k] = 1.0
+            prod = nppoly.polymul(nppoly.polyder(ej, p), nppoly.polyder(ek, p))
+            Q[j, k] = nppoly.polyval(T, nppoly.polyint(prod))
+    return Q
+
+
+def _np_spline_through(P, T, bc, p, s):
+    """Minimum-effort piecewise polynomial of degree 2p-1 per axis: end states from the array bc
+    [2, p, 3] (orders 0..p-1 at the first and last knot), interior positions pinned to P, orders
+    1..s-1 continuous; the KKT system of that equality-constrained QP, assembled from numpy
+    polynomial derivatives and integrals and solved densely."""
+    d = 2 * p - 1
+    n = d + 1
+    N = len(T)
+    out = np.zeros((N, 3, n))
+    for a in range(3):
+        rows, rhs = [], []
+
+        def put(entries, val):
+            r = np.zeros(N * n)
+            for seg, vec in entries:
+                r[seg * n:(seg + 1) * n] += vec
+            rows.append(r)
+            rhs.append(val)
+
+        for o in range(p):
+            put([(0, _np_boundary_rows(T[0], d, [o], [])[0])], bc[0, o, a])
+            put([(N - 1, _np_boundary_rows(T[N - 1], d, [], [o])[0])], bc[1, o, a])
+        for k in range(N - 1):
+            put([(k, _np_boundary_rows(T[k], d, [], [0])[0])], P[k + 1, a])
+            put([(k + 1, _np_boundary_rows(T[k + 1], d, [0], [])[0])], P[k + 1, a])
+            for o in range(1, s):
+                put([(k, _np_boundary_rows(T[k], d, [], [o])[0]),
+                     (k + 1, -_np_boundary_rows(T[k + 1], d, [o], [])[0])], 0.0)
+        E, e = np.array(rows), np.array(rhs)
+        H = np.zeros((N * n, N * n))
+        for k in range(N):
+            H[k * n:(k + 1) * n, k * n:(k + 1) * n] = 2.0 * _np_gram(T[k], p, d)
+        m = E.shape[0]
+        K = np.block([[H, E.T], [E, np.zeros((m, m))]])
+        sol = np.linalg.solve(K, np.concatenate([np.zeros(N * n), e]))
+        out[:, a, :] = sol[:N * n].reshape(N, n)
+    return out
+
+
+def _bc_workload(lengths, seeds, p, rng_seed):
+    w = random_walk_batch("bc", lengths, seeds, order=p, box=False, vmax=None, rho=1.0, precision="fp64")
+    rng = np.random.default_rng(rng_seed)
+    B = len(lengths)
+    bc = rng.uniform(-2.0, 2.0, (B, 2, p, 3))
+    for b in range(B):                       # positions are the end waypoints (pinned)
+        bc[b, 0, 0] = w.waypoints[int(w.seg_offsets[b]) + b]
+        bc[b, 1, 0] = w.waypoints[int(w.seg_offsets[b + 1]) + b]
+    w.bc = bc
+    return w
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_single_segment_nonrest_ends_are_the_hermite_interpolant(p):
+    """One segment with given end states (eq. start_points_constraints, orders 0..p-1 at both ends):
+    2p conditions on 2p coefficients fix the polynomial, the Hermite interpolant.  Solved here with
+    numpy from the bc array; two trajectories with different states, so a slip in the [B][2][p][3]
+    layout (trajectory, side, order, axis) shows."""
+    w = _bc_workload([1, 1], [21, 22], p, 5 + p)
+    w.rho = np.full(2, 5e3 if p == 3 else 1e6)     # the end knots are fixed: a large rho converges fast
+    pr = cadmm.problem_from_workload(w)
+    res = cadmm.run(pr, 300)
+    c = cadmm.coeffs_by_axis(pr, res.c).numpy()
+    d = 2 * p - 1
+    for b in range(2):
+        Mi = _np_boundary_rows(w.durations[b], d, range(p), range(p))
+        for a in range(3):
+            want = np.linalg.solve(Mi, np.concatenate([w.bc[b, 0, :, a], w.bc[b, 1, :, a]]))
+            assert np.allclose(c[b, a], want, rtol=1e-9, atol=1e-9 * np.abs(want).max()), (b, a)
+    kk, _ = references.kkt_reference(pr)
+    want_all = np.stack([_np_spline_through(w.waypoints[b:b + 2], w.durations[b:b + 1], w.bc[b], p, p)[0]
+                         for b in range(2)])
+    assert np.allclose(kk, want_all, rtol=1e-10, atol=1e-10 * np.abs(want_all).max())
+
+
+@pytest.mark.parametrize("p", [3, 4])
+def test_nonrest_ends_multi_segment_match_numpy_kkt(p):
+    """Several segments with non-rest end states: the oracle's KKT reference, and for p = 3 the
+    iteration's fixed point, equal the minimum-effort spline that a numpy KKT solve builds from the
+    bc array directly (the septic iteration needs many thousand sweeps to get there; its end-state
+    path is pinned by the one-segment test)."""
+    w = _bc_workload([3, 2], [31, 32], p, 17 + p)
+    w.rho = np.array([60.0, 60.0])
+    pr = cadmm.problem_from_workload(w)
+    c = cadmm.coeffs_by_axis(pr, cadmm.run(pr, 3000).c).numpy() if p == 3 else None
+    kk, _ = references.kkt_reference(pr)
+    for b in range(2):
+        s0, s1 = int(w.seg_offsets[b]), int(w.seg_offsets[b + 1])
+        want = _np_spline_through(w.waypoints[s0 + b:s1 + b + 1], w.durations[s0:s1], w.bc[b], p, p)
+        sc = np.abs(want).max()
+        assert np.allclose(kk[s0:s1], want, rtol=1e-9, atol=1e-9 * sc), b
+        if c is not None:
+            assert np.allclose(c[s0:s1], want, rtol=1e-9, atol=1e-9 * sc), (b, np.abs(c[s0:s1] - want).max())
