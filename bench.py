@@ -250,6 +250,15 @@ def septic_leg(w2, d2):
 
 
 def _cpu_model() -> str:
+    """The host CPU's model name as lscpu reports it (falling back to /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.strip().lower().startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
     try:
         with open("/proc/cpuinfo") as f:
             for ln in f:
@@ -258,6 +267,19 @@ def _cpu_model() -> str:
     except OSError:
         pass
     return "unknown"
+
+
+def _host_threads() -> dict:
+    """Threads the CPU baseline runs on: every core this process may use (its affinity set), capped
+    by OMP_NUM_THREADS when the host sets it (the share of a shared host that belongs to this job)."""
+    visible = os.cpu_count() or 1
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = visible
+    cap = os.environ.get("OMP_NUM_THREADS", "")
+    use = min(allowed, int(cap)) if cap.isdigit() and int(cap) > 0 else allowed
+    return {"use": use, "os_cpu_count": visible, "affinity": allowed, "omp_num_threads": cap or None}
 
 
 def _first_trajectories(w, n_seg_wanted):
@@ -292,7 +314,10 @@ def cpu_baseline(w, K, run_s=4.0):
         cadmm.run(pr, K)
         return sub.n_seg, time.perf_counter() - t0
 
-    threads = torch.get_num_threads()
+    host = _host_threads()
+    prev_threads = torch.get_num_threads()
+    threads = host["use"]
+    torch.set_num_threads(threads)
     nb = _first_trajectories(w, rate_probe() * run_s / K)
     # the short probe under-states the rate of larger samples: resize once from a full-K run
     n0, dt0 = timed(nb)
@@ -306,9 +331,10 @@ def cpu_baseline(w, K, run_s=4.0):
         nb1 = _first_trajectories(w, rate_probe() * run_s / K)
         n1, dt1 = timed(nb1)
     finally:
-        torch.set_num_threads(threads)
+        torch.set_num_threads(prev_threads)
     return {"value": n_seg * K / dts[1], "unit": "segment-updates/s", "cores": threads,
-            "kind": "oracle", "cpu_model": _cpu_model(),
+            "kind": "oracle", "cpu_model": _cpu_model(), "os_cpu_count": host["os_cpu_count"],
+            "affinity_cpus": host["affinity"], "omp_num_threads": host["omp_num_threads"],
             "sample": f"first {nb} trajectories ({n_seg} segments) x {K} sweeps, float64 torch-CPU, "
                       f"median of 3 runs ({', '.join(f'{dt:.1f}' for dt in dts)} s)",
             "single_thread": {"value": n1 * K / dt1, "cores": 1,

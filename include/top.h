@@ -21,10 +21,25 @@
  *   - Arrays marked [dev] are device pointers, valid on the stream passed to
  *     top_create; arrays marked [host] are host pointers.  All [dev] inputs
  *     are float64 whatever the iterate precision.
- *   - Inputs are read during top_create only; the library keeps its own
- *     copies (in the iterate precision, or float64 where noted) and owns all
- *     device memory it allocates, which top_destroy releases.  The caller owns
- *     every output buffer.
+ *   - Inputs are read only by work that top_create queues on its stream; the
+ *     library keeps its own copies (in the iterate precision, or float64 where
+ *     noted).  The inputs must stay allocated and unchanged until the stream
+ *     has run that work (work queued on the same stream afterwards is ordered
+ *     after it).  The caller owns every output buffer.
+ *   - Device memory.  The per-problem state (Algorithm 1's iterates, the
+ *     per-segment factors, the tape) lives in one workspace that the caller
+ *     allocates (top_workspace_bytes gives its size) and passes to
+ *     top_create; such a handle makes no device allocation of its own.  The
+ *     caller keeps the workspace allocated, and uses it for nothing else,
+ *     until the handle has been destroyed and the handle's stream has run the
+ *     work queued before that (an allocation made on that stream by a
+ *     stream-ordered allocator, such as PyTorch's, satisfies this when it is
+ *     released after top_destroy).  Read-only tables that depend only on the
+ *     trajectory lengths (device copies of the offsets, the reduction chunk
+ *     table, the tile lane map) are built once per shape and device and kept
+ *     in a library cache shared by every handle of that shape.  A NULL
+ *     workspace makes the library take the state from its own pool instead
+ *     (hipMalloc; blocks are kept for reuse by later handles).
  *   - Every call that launches work is asynchronous on the handle's stream:
  *     outputs are ready once that stream has been synchronised.
  *   - A handle is not thread-safe; use one handle per host thread.  It belongs
@@ -52,6 +67,7 @@ typedef struct top_problem top_problem;
 typedef enum top_status {
   TOP_OK = 0,
   TOP_E_INVALID = -1,      /* an argument is null, out of range or not finite          */
+  TOP_E_WORKSPACE = -2,    /* the workspace given to top_create is too small            */
   TOP_E_HIP = -3,          /* a HIP runtime call failed                                 */
   TOP_E_STATE = -4,        /* the call is not valid in the handle's current state       */
   TOP_E_NONFINITE = -5,    /* an iterate became NaN or infinite                         */
@@ -115,6 +131,21 @@ typedef struct top_options {
    tau_incr = tau_decr = 1.1 for when checks are switched on. */
 void top_default_options(top_options* opt);
 
+/* Bytes of workspace a problem of n_traj trajectories and n_seg_total segments needs, for
+ * top_create with these options (NULL: the defaults) when a corridor, a velocity bound and end
+ * states are all given (less is needed without them; top_create checks the exact amount).  The
+ * workspace holds everything Algorithm 1 keeps per problem: the per-segment factors of eq.
+ * QpSubProblem, the iterate (c, z, u and the slack/dual pairs of Sec. III-C) in two buffers, the
+ * residual and cost partials of Sec. III-D.3, and with checkpoint_every > 0 the tape and the
+ * reverse pass's buffers.  Host-only: no device call.  Returns 0 for invalid arguments
+ * (top_last_error says why). */
+size_t top_workspace_bytes(int32_t n_traj, int64_t n_seg_total, const top_options* opt);
+
+/* The same for top_create_polytope with n_faces faces per segment (the faces and the per-axis
+ * factors of the rotated solve take the place of the box). */
+size_t top_workspace_bytes_polytope(int32_t n_traj, int64_t n_seg_total, int32_t n_faces,
+                                    const top_options* opt);
+
 /* Create a problem and run Init (Algorithm 1) on `stream`.
  *   n_traj       B >= 1
  *   seg_offsets  [host] int64 [B+1], seg_offsets[0] = 0, strictly increasing (every trajectory
@@ -129,13 +160,18 @@ void top_default_options(top_options* opt);
  *   vmax         [dev] [B] velocity-norm bound per trajectory (Sec. III-C.2), > 0, or NULL
  *   rho          [dev] [B] penalty per trajectory, > 0
  *   opt          [host] options, NULL for the defaults
+ *   workspace    [dev] caller-owned device memory for the problem's state, workspace_bytes long
+ *                (any alignment; at most top_workspace_bytes(...) is used), or NULL with
+ *                workspace_bytes = 0 for the library's own pool.  TOP_E_WORKSPACE, before any
+ *                device work, when workspace_bytes is below what this problem needs.
  *   stream       HIP stream all work of this handle is queued on (0 = the null stream)
  *   out          receives the handle; set to NULL on failure
  * Blocks once, to validate the device inputs. */
 top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
                       const double* durations, const double* bc, const double* box_lo,
                       const double* box_hi, const double* vmax, const double* rho,
-                      const top_options* opt, hipStream_t stream, top_problem** out);
+                      const top_options* opt, void* workspace, size_t workspace_bytes,
+                      hipStream_t stream, top_problem** out);
 
 /* top_create with a general convex polytope corridor per segment instead of a box: the
  * H-representation P_i^H = {x : a_k . x <= b_k} of Sec. III-D.1, imposed at the M samples
@@ -148,7 +184,8 @@ top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* 
 top_status top_create_polytope(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
                                const double* durations, const double* bc, int32_t n_faces, const double* faces,
                                const double* vmax, const double* rho, const top_options* opt,
-                               hipStream_t stream, top_problem** out);
+                               void* workspace, size_t workspace_bytes, hipStream_t stream,
+                               top_problem** out);
 
 /* Queue k >= 0 more sweeps (Algorithm 1 loop body: ClosedFormSolve, UpdateConsensus,
  * UpdateResidual, ProjectNonNeg, UpdateDual, and UpdateRho at the checks when check_every > 0).
@@ -237,11 +274,18 @@ typedef struct top_plan_info {
 
 top_status top_get_plan(const top_problem* h, top_plan_info* info);
 
-/* Release the handle; NULL is a no-op.  Its device buffers return to the library's pool without
- * waiting for the work still queued on the handle's stream: a later handle on the same stream reuses
- * them in stream order, one on another stream first waits (on the device) for that work.  Handles
- * that captured graphs wait for their stream first. */
+/* Release the handle; NULL is a no-op.  Handles that captured graphs wait for their stream first;
+ * others return at once.  A handle on a caller's workspace leaves the workspace
+ * to the caller (see the device-memory convention above).  A handle on the library's pool returns
+ * its buffers there without waiting for the work still queued on its stream: a later handle on the
+ * same stream reuses them in stream order, one on another stream first waits (on the device) for
+ * that work. */
 void top_destroy(top_problem* h);
+
+/* Free the device memory the library keeps for reuse: pool blocks no handle holds, and cached shape
+ * tables and lane maps no handle uses.  Blocks until the device has finished the work that last
+ * used them.  Handles stay valid. */
+void top_trim(void);
 
 /* Thread-local text of the last error reported by this library on the calling thread. */
 const char* top_last_error(void);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libtop.so")
 
 TOP_OK = 0
 TOP_E_INVALID = -1
+TOP_E_WORKSPACE = -2
 TOP_E_HIP = -3
 TOP_E_STATE = -4
 TOP_E_NONFINITE = -5
@@ -25,14 +26,14 @@ TOP_E_NOMEM = -7
 TOP_FP32 = 0
 TOP_FP64 = 1
 
-STATUS_NAMES = {0: "TOP_OK", -1: "TOP_E_INVALID", -3: "TOP_E_HIP", -4: "TOP_E_STATE",
+STATUS_NAMES = {0: "TOP_OK", -1: "TOP_E_INVALID", -2: "TOP_E_WORKSPACE", -3: "TOP_E_HIP", -4: "TOP_E_STATE",
                 -5: "TOP_E_NONFINITE", -6: "TOP_E_UNSUPPORTED", -7: "TOP_E_NOMEM"}
 
 # Every entry point declared in include/top.h.
-EXPORTED = ["top_default_options", "top_create", "top_create_polytope", "top_iterate", "top_time_sweeps", "top_residuals", "top_cost",
+EXPORTED = ["top_default_options", "top_workspace_bytes", "top_workspace_bytes_polytope", "top_create",
+            "top_create_polytope", "top_iterate", "top_time_sweeps", "top_residuals", "top_cost",
             "top_coeffs", "top_backward", "top_tune", "top_convergence", "top_get_state", "top_set_state",
-            "top_sync_status", "top_get_plan",
-            "top_destroy", "top_last_error"]
+            "top_sync_status", "top_get_plan", "top_destroy", "top_trim", "top_last_error"]
 
 
 class TopOptions(ctypes.Structure):
@@ -72,11 +73,15 @@ def lib() -> ctypes.CDLL:
     vp, i32, i64p, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p
     L.top_default_options.argtypes = [ctypes.POINTER(TopOptions)]
     L.top_default_options.restype = None
+    L.top_workspace_bytes.argtypes = [i32, ctypes.c_int64, ctypes.POINTER(TopOptions)]
+    L.top_workspace_bytes.restype = ctypes.c_size_t
+    L.top_workspace_bytes_polytope.argtypes = [i32, ctypes.c_int64, i32, ctypes.POINTER(TopOptions)]
+    L.top_workspace_bytes_polytope.restype = ctypes.c_size_t
     L.top_create.argtypes = [i32, i64p, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(TopOptions), vp,
-                             ctypes.POINTER(vp)]
+                             ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.top_create.restype = ctypes.c_int
     L.top_create_polytope.argtypes = [i32, i64p, dp, dp, dp, i32, dp, dp, dp, ctypes.POINTER(TopOptions), vp,
-                                      ctypes.POINTER(vp)]
+                                      ctypes.c_size_t, vp, ctypes.POINTER(vp)]
     L.top_create_polytope.restype = ctypes.c_int
     L.top_iterate.argtypes = [vp, i32]
     L.top_iterate.restype = ctypes.c_int
@@ -104,6 +109,8 @@ def lib() -> ctypes.CDLL:
     L.top_get_plan.restype = ctypes.c_int
     L.top_destroy.argtypes = [vp]
     L.top_destroy.restype = None
+    L.top_trim.argtypes = []
+    L.top_trim.restype = None
     L.top_last_error.argtypes = []
     L.top_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -139,28 +146,60 @@ def default_options() -> TopOptions:
 # Thin functions with the C names (handles are integers).
 # ---------------------------------------------------------------------------
 
+def top_workspace_bytes(n_traj: int, n_seg_total: int, options: Optional[TopOptions] = None) -> int:
+    """Workspace bytes top_create needs for this size (host-only; no device call)."""
+    n = lib().top_workspace_bytes(int(n_traj), int(n_seg_total), None if options is None else ctypes.byref(options))
+    if n == 0:
+        raise TopError(TOP_E_INVALID, lib().top_last_error().decode(errors="replace"))
+    return int(n)
+
+
+def top_workspace_bytes_polytope(n_traj: int, n_seg_total: int, n_faces: int,
+                                 options: Optional[TopOptions] = None) -> int:
+    n = lib().top_workspace_bytes_polytope(int(n_traj), int(n_seg_total), int(n_faces),
+                                           None if options is None else ctypes.byref(options))
+    if n == 0:
+        raise TopError(TOP_E_INVALID, lib().top_last_error().decode(errors="replace"))
+    return int(n)
+
+
+def _ws_args(workspace, workspace_bytes):
+    """(pointer, bytes) of a workspace given as a device tensor or a raw pointer, or (None, 0)."""
+    if workspace is None:
+        return None, 0
+    if isinstance(workspace, int):
+        return ctypes.c_void_p(workspace), int(workspace_bytes)
+    nbytes = workspace.numel() * workspace.element_size()
+    return ctypes.c_void_p(workspace.data_ptr()), int(workspace_bytes if workspace_bytes else nbytes)
+
+
 def top_create(seg_offsets: Sequence[int], waypoints, durations, rho, *, bc=None, box_lo=None,
-               box_hi=None, vmax=None, options: Optional[TopOptions] = None, stream: int = 0) -> int:
-    """Device tensors (float64) in, handle out.  seg_offsets is a host int64 sequence."""
+               box_hi=None, vmax=None, options: Optional[TopOptions] = None, workspace=None,
+               workspace_bytes: int = 0, stream: int = 0) -> int:
+    """Device tensors (float64) in, handle out.  seg_offsets is a host int64 sequence; workspace is a
+    device tensor (or pointer) of at least top_workspace_bytes bytes, or None for the library's pool."""
     offs = np.ascontiguousarray(np.asarray(seg_offsets, dtype=np.int64))
     h = ctypes.c_void_p()
+    wp, wb = _ws_args(workspace, workspace_bytes)
     st = lib().top_create(int(offs.shape[0] - 1), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                           _ptr(waypoints), _ptr(durations), _ptr(bc), _ptr(box_lo), _ptr(box_hi),
                           _ptr(vmax), _ptr(rho), None if options is None else ctypes.byref(options),
-                          ctypes.c_void_p(stream), ctypes.byref(h))
+                          wp, wb, ctypes.c_void_p(stream), ctypes.byref(h))
     _check(st)
     return h.value
 
 
 def top_create_polytope(seg_offsets: Sequence[int], waypoints, durations, rho, faces, *, bc=None, vmax=None,
-                        options: Optional[TopOptions] = None, stream: int = 0) -> int:
+                        options: Optional[TopOptions] = None, workspace=None, workspace_bytes: int = 0,
+                        stream: int = 0) -> int:
     """Like top_create with a polytope corridor: faces is a float64 device tensor [S, K, 4] (a, b)."""
     offs = np.ascontiguousarray(np.asarray(seg_offsets, dtype=np.int64))
     h = ctypes.c_void_p()
+    wp, wb = _ws_args(workspace, workspace_bytes)
     st = lib().top_create_polytope(int(offs.shape[0] - 1), offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                    _ptr(waypoints), _ptr(durations), _ptr(bc), int(faces.shape[1]), _ptr(faces),
                                    _ptr(vmax), _ptr(rho), None if options is None else ctypes.byref(options),
-                                   ctypes.c_void_p(stream), ctypes.byref(h))
+                                   wp, wb, ctypes.c_void_p(stream), ctypes.byref(h))
     _check(st)
     return h.value
 
@@ -221,6 +260,10 @@ def top_destroy(h: int) -> None:
     lib().top_destroy(ctypes.c_void_p(h))
 
 
+def top_trim() -> None:
+    lib().top_trim()
+
+
 # ---------------------------------------------------------------------------
 # Convenience wrapper.
 # ---------------------------------------------------------------------------
@@ -234,7 +277,9 @@ class TopProblem:
                  tile_lanes: int = 0, halo: int = 0, use_graph: bool = True, check_every: int = 0,
                  adapt_rho: bool = False, tol: float = 0.05, mu: float = 10.0, tau_incr: float = 1.1,
                  tau_decr: float = 1.1, numeric: bool = False, lbfgs_iters: int = 10, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, library_pool: bool = False):
+        """Create the handle.  By default its state lives in a workspace allocated by torch on the
+        handle's stream (released with the handle); library_pool=True uses the library's pool."""
         import torch
         self.device = torch.device(device)
         self.seg_offsets = np.asarray(seg_offsets, dtype=np.int64)
@@ -258,16 +303,30 @@ class TopProblem:
         o.local_solve = 1 if numeric else 0
         o.lbfgs_iters = int(lbfgs_iters)
         self.options = o
+        self.h = None
+        self.workspace = None
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        args = [_dev(x, self.device) for x in (waypoints, durations, rho, bc, box_lo, box_hi, vmax, faces)]
-        if faces is not None:
-            if box_lo is not None or box_hi is not None:
-                raise ValueError("give a box corridor or polytope faces, not both")
-            self.h = top_create_polytope(self.seg_offsets, args[0], args[1], args[2], args[7], bc=args[3],
-                                         vmax=args[6], options=o, stream=self.stream.cuda_stream)
-        else:
-            self.h = top_create(self.seg_offsets, args[0], args[1], args[2], bc=args[3], box_lo=args[4],
-                                box_hi=args[5], vmax=args[6], options=o, stream=self.stream.cuda_stream)
+        if faces is not None and (box_lo is not None or box_hi is not None):
+            raise ValueError("give a box corridor or polytope faces, not both")
+        cur = torch.cuda.current_stream(self.device)
+        if self.stream != cur:
+            self.stream.wait_stream(cur)  # inputs produced on the current stream
+        # Staging copies and the workspace are allocated on the handle's stream, so the caching
+        # allocator reuses their memory only after the work queued there (which reads them).
+        with torch.cuda.stream(self.stream):
+            args = [_dev(x, self.device) for x in (waypoints, durations, rho, bc, box_lo, box_hi, vmax, faces)]
+            if not library_pool:
+                nb = (top_workspace_bytes_polytope(self.B, self.S, int(args[7].shape[1]), o) if faces is not None
+                      else top_workspace_bytes(self.B, self.S, o))
+                self.workspace = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            if faces is not None:
+                self.h = top_create_polytope(self.seg_offsets, args[0], args[1], args[2], args[7], bc=args[3],
+                                             vmax=args[6], options=o, workspace=self.workspace,
+                                             stream=self.stream.cuda_stream)
+            else:
+                self.h = top_create(self.seg_offsets, args[0], args[1], args[2], bc=args[3], box_lo=args[4],
+                                    box_hi=args[5], vmax=args[6], options=o, workspace=self.workspace,
+                                    stream=self.stream.cuda_stream)
 
     @classmethod
     def from_workload(cls, w, **kw):
@@ -350,6 +409,9 @@ class TopProblem:
         if getattr(self, "h", None):
             top_destroy(self.h)
             self.h = None
+        # The workspace was allocated on the handle's stream: the caching allocator hands it out
+        # again only in that stream's order, after the work queued there.
+        self.workspace = None
 
     def __del__(self):
         try:
@@ -385,8 +447,9 @@ def _autograd_function():
 
         @staticmethod
         def backward(ctx, gJ):
+            # The handle stays open until ctx is released, so a graph kept with retain_graph=True
+            # can be differentiated again (the reverse pass replays the blocks it needs).
             dP, dT = ctx.prob.backward(gJ.detach().to(torch.float64).contiguous())
-            ctx.prob.close()
             return dP, dT, None, None, None, None, None, None, None, None, None
 
     return TopCost

@@ -20,11 +20,14 @@
 #include <vector>
 
 #include "adjoint_impl.h"
+#include "api_internal.h"
 #include "common.h"
 
 namespace {
 
 thread_local std::string g_err = "";
+
+constexpr size_t kWsAlign = 256;  // alignment of every buffer carved from a caller's workspace
 
 top_status fail(top_status s, const char* fmt, ...) {
   char buf[512];
@@ -335,6 +338,18 @@ struct ShapeEntry {
   }
 };
 
+// Reduction chunk tables of a CSR shape: first chunk of each trajectory, trajectory of each chunk.
+void chunk_tables(const std::vector<int64_t>& off, std::vector<int32_t>* c_off, std::vector<int32_t>* c_traj) {
+  const int B = (int)off.size() - 1;
+  c_off->assign((size_t)B + 1, 0);
+  c_traj->clear();
+  for (int b = 0; b < B; ++b) {
+    const int64_t nc = (off[b + 1] - off[b] + top::kReduceChunk - 1) / top::kReduceChunk;
+    (*c_off)[b + 1] = (*c_off)[b] + (int32_t)nc;
+    for (int64_t j = 0; j < nc; ++j) c_traj->push_back(b);
+  }
+}
+
 std::mutex g_shape_mu;
 std::map<uint64_t, std::shared_ptr<ShapeEntry>>& g_shapes = *new std::map<uint64_t, std::shared_ptr<ShapeEntry>>();
 
@@ -353,14 +368,8 @@ top_status get_shape(const std::vector<int64_t>& off, std::shared_ptr<ShapeEntry
   auto e = std::make_shared<ShapeEntry>();
   e->off = off;
   e->device = dev;
-  const int B = (int)off.size() - 1;
-  std::vector<int32_t> c_off((size_t)B + 1), c_traj;
-  c_off[0] = 0;
-  for (int b = 0; b < B; ++b) {
-    const int64_t nc = (off[b + 1] - off[b] + top::kReduceChunk - 1) / top::kReduceChunk;
-    c_off[b + 1] = c_off[b] + (int32_t)nc;
-    for (int64_t j = 0; j < nc; ++j) c_traj.push_back(b);
-  }
+  std::vector<int32_t> c_off, c_traj;
+  chunk_tables(off, &c_off, &c_traj);
   e->n_chunks = (int)c_traj.size();
   hipError_t he = hipMalloc((void**)&e->off_dev, off.size() * sizeof(int64_t));
   if (he == hipSuccess) he = hipMalloc((void**)&e->chunk_off, c_off.size() * sizeof(int32_t));
@@ -452,13 +461,18 @@ struct top_problem {
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;
   struct Block { void* p; size_t bytes; int dev; };
-  std::vector<Block> allocs;
+  std::vector<Block> allocs;           // pool blocks (handles without a caller workspace)
+  // Caller workspace: buffers are carved from it in order, kWsAlign-aligned.  `sizing` only counts
+  // the bytes (top_workspace_bytes), handing out placeholder pointers that are never dereferenced.
+  char* ws = nullptr;
+  size_t ws_cap = 0, ws_used = 0;
+  bool sizing = false;
   // device buffers
   void *Hr = nullptr, *iT = nullptr, *lo = nullptr, *hi = nullptr, *vmax = nullptr, *bcL = nullptr;
   void *Urot = nullptr, *fa = nullptr;  // polytope corridor: rotation and faces
   double* lam = nullptr;                // polytope corridor: eigenvalues of sum_k a_k a_k^T
   void* state[2] = {nullptr, nullptr};
-  void *cbuf = nullptr, *zold = nullptr, *scratch = nullptr;
+  void *cbuf = nullptr, *zold = nullptr;
   uint8_t* flags = nullptr;
   int32_t* traj = nullptr;
   double *Tdev = nullptr, *rho_seg = nullptr, *part = nullptr, *out = nullptr;
@@ -486,9 +500,23 @@ struct top_problem {
     return a;
   }
   std::shared_ptr<PlanEntry> pe;
-  Plan empty_plan;
-  const Plan& plan_ref() const { return pe ? pe->plan : empty_plan; }
-  const int32_t* lanes() const { return pe ? pe->dev : nullptr; }
+  // A handle on the static scratch keeps its shape tables and lane map in its own workspace: the
+  // host copies they are uploaded from, and the plan.
+  bool own_tables = false;
+  Plan own_plan;
+  int32_t* own_lanes = nullptr;
+  std::vector<int32_t> own_chunk_off, own_chunk_traj;
+  const Plan& plan_ref() const { return pe ? pe->plan : own_plan; }
+  const int32_t* lanes() const { return pe ? pe->dev : own_lanes; }
+
+  // The shape tables and the lane map in the handle's workspace (own_tables), after its buffers.
+  top_status allocate_tables(int64_t n_chunks, size_t n_lanes) {
+    top_status st;
+    if ((st = alloc(&off_dev, (size_t)(B + 1) * sizeof(int64_t))) != TOP_OK) return st;
+    if ((st = alloc(&chunk_off, (size_t)(B + 1) * sizeof(int32_t))) != TOP_OK) return st;
+    if ((st = alloc(&chunk_traj, (size_t)std::max<int64_t>(n_chunks, 1) * sizeof(int32_t))) != TOP_OK) return st;
+    return alloc(&own_lanes, n_lanes * sizeof(int32_t));
+  }
   int cur = 0;
   int iters_done = 0;
   bool have_sweep = false;
@@ -520,6 +548,20 @@ struct top_problem {
   top_status alloc(T** p, size_t bytes) {
     void* q = nullptr;
     if (bytes == 0) bytes = 256;
+    if (sizing || ws != nullptr) {
+      const size_t need = (bytes + kWsAlign - 1) / kWsAlign * kWsAlign;
+      if (sizing) {
+        ws_used += need;
+        *p = reinterpret_cast<T*>(uintptr_t(kWsAlign));
+        return TOP_OK;
+      }
+      if (ws_used + need > ws_cap)
+        return fail(TOP_E_WORKSPACE, "workspace of %zu bytes exhausted (%zu more needed)", ws_cap,
+                    ws_used + need - ws_cap);
+      *p = reinterpret_cast<T*>(ws + ws_used);
+      ws_used += need;
+      return TOP_OK;
+    }
     int dev = 0;
     hipError_t e = pool_get(bytes, stream, &q, &dev);
     if (e != hipSuccess) return fail(TOP_E_NOMEM, "device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
@@ -586,10 +628,79 @@ struct top_problem {
                        : launch_one<double>(pl, lane_map, in, outp, n, fin, st, store_frozen, rec);
   }
 
-  // Block buffers of the reverse pass (two blocks of checkpoint_every states), allocated on first use.
+  // Elements of the reverse pass's zero-initialised allocation: the adjoint of the state after the
+  // last sweep (adjb[0]) and the per-segment accumulators (1/T, rho Htilde^-1, start knot).
+  int64_t adjoint_zero_elems() const { return (int64_t)nf * ld + (2 + 3 * (int64_t)v.s) * ld; }
+
+  // Every device buffer of the handle, in one fixed order (the workspace layout).  has_* say which
+  // optional inputs were given; n_chunks is the number of reduction chunks of the shape.
+  top_status allocate_buffers(bool has_box, bool has_vmax, bool has_bc, int64_t n_chunks) {
+    top::Layout L{v.p, v.s, v.box, v.vel, v.faces, v.num};
+    const size_t R = rsz, l = (size_t)ld, s = (size_t)v.s;
+    top_status st;
+#define TOP_ALLOC(ptr, bytes) \
+  if ((st = alloc(&(ptr), (bytes))) != TOP_OK) return st
+    TOP_ALLOC(Hr, L.nhr() * l * R);
+    if (v.faces) {
+      TOP_ALLOC(Urot, 9 * l * R);
+      TOP_ALLOC(fa, 4 * (size_t)top::kFaces * l * R);
+      TOP_ALLOC(lam, 3 * l * sizeof(double));
+    }
+    TOP_ALLOC(iT, l * R);
+    TOP_ALLOC(lo, 3 * l * R);
+    TOP_ALLOC(hi, 3 * l * R);
+    TOP_ALLOC(vmax, l * R);
+    TOP_ALLOC(bcL, (size_t)B * 3 * s * R);
+    for (int q = 0; q < 2; ++q) TOP_ALLOC(state[q], (size_t)nf * l * R);  // setup zeroes the padding
+    TOP_ALLOC(cbuf, 3 * (size_t)L.n() * l * R);
+    TOP_ALLOC(zold, 3 * s * l * R);
+    TOP_ALLOC(flags, l);
+    TOP_ALLOC(traj, l * sizeof(int32_t));
+    TOP_ALLOC(Tdev, l * sizeof(double));
+    TOP_ALLOC(rho_seg, l * sizeof(double));
+    TOP_ALLOC(part, 3 * (size_t)S * sizeof(double));
+    TOP_ALLOC(out, 3 * (size_t)B * sizeof(double));
+    TOP_ALLOC(flag_dev, 2 * sizeof(int));
+    TOP_ALLOC(rho_traj, (size_t)B * sizeof(double));
+    TOP_ALLOC(chunk_sum, 3 * (size_t)std::max<int64_t>(n_chunks, 1) * sizeof(double));
+    if (opt.check_every > 0) {
+      TOP_ALLOC(done_dev, (size_t)B);
+      TOP_ALLOC(fresh, (size_t)B);
+      TOP_ALLOC(swept, (size_t)B * sizeof(int32_t));
+      TOP_ALLOC(stop_at, (size_t)B * sizeof(int32_t));
+      TOP_ALLOC(ratio, (size_t)B * sizeof(double));
+      TOP_ALLOC(check_lists, 3 * (size_t)B * sizeof(int32_t));
+      TOP_ALLOC(check_counts, 3 * sizeof(int32_t));
+    }
+    if (opt.checkpoint_every > 0) {
+      tape_slots = opt.max_taped_iters / opt.checkpoint_every + 1;
+      TOP_ALLOC(tape, (size_t)tape_slots * nf * l * R);
+      TOP_ALLOC(Hd, L.nh() * l * R);
+      TOP_ALLOC(wp64, (size_t)(S + B) * 3 * sizeof(double));
+      if (has_box) {
+        TOP_ALLOC(lo64, (size_t)S * 3 * sizeof(double));
+        TOP_ALLOC(hi64, (size_t)S * 3 * sizeof(double));
+      }
+      if (has_vmax) TOP_ALLOC(vmax64, (size_t)B * sizeof(double));
+      if (has_bc) TOP_ALLOC(bc64, (size_t)B * 2 * v.p * 3 * sizeof(double));
+      // reverse pass: two block buffers of checkpoint_every states, the zero-initialised adjoint
+      // and accumulators, the second adjoint buffer, and the float64 per-segment waypoint terms
+      TOP_ALLOC(blk, 2 * (size_t)opt.checkpoint_every * nf * l * R);
+      TOP_ALLOC(adjb[0], (size_t)adjoint_zero_elems() * R);
+      TOP_ALLOC(adjb[1], (size_t)nf * l * R);
+      acc_iT = (char*)adjb[0] + (size_t)nf * l * R;
+      acc_hd = (char*)acc_iT + l * R;
+      acc_z0 = (char*)acc_hd + l * R;
+      for (double** p : {&dPL, &dPR, &dK, &dK0}) TOP_ALLOC(*p, (size_t)S * 3 * sizeof(double));
+    }
+#undef TOP_ALLOC
+    return TOP_OK;
+  }
+
+  // Block buffers of the reverse pass; allocated with the handle when it records a tape.
   top_status ensure_blk() {
     if (blk != nullptr) return TOP_OK;
-    return alloc(&blk, 2 * (size_t)opt.checkpoint_every * nf * ld * rsz);
+    return fail(TOP_E_STATE, "the handle has no reverse-pass buffers");
   }
 
   template <typename R>
@@ -632,19 +743,7 @@ struct top_problem {
     const size_t sl = (size_t)nf * ld;
     top::Layout L{v.p, v.s, v.box, v.vel, v.faces, v.num};
     top_status s;
-    if ((s = ensure_blk()) != TOP_OK) return s;
-    // Everything that starts at zero sits in one allocation, cleared by one launch: the adjoint of
-    // the state after the last sweep (adjb[0]) and the per-segment accumulators.
-    const int64_t nzero = (int64_t)sl + (2 + 3 * (int64_t)v.s) * ld;
-    if (adjb[0] == nullptr) {
-      if ((s = alloc(&adjb[0], (size_t)nzero * sizeof(R))) != TOP_OK) return s;
-      if ((s = alloc(&adjb[1], sl * sizeof(R))) != TOP_OK) return s;
-      acc_iT = (R*)adjb[0] + sl;
-      acc_hd = (R*)acc_iT + ld;
-      acc_z0 = (R*)acc_hd + ld;
-      for (double** p : {&dPL, &dPR, &dK, &dK0})
-        if ((s = alloc(p, (size_t)S * 3 * sizeof(double))) != TOP_OK) return s;
-    }
+    const int64_t nzero = adjoint_zero_elems();
     auto chk = [](hipError_t e) -> top_status {
       return e == hipSuccess ? TOP_OK : fail(TOP_E_HIP, "backward launch failed: %s", hipGetErrorString(e));
     };
@@ -942,12 +1041,13 @@ const char* top_last_error(void) { return g_err.c_str(); }
 
 void top_destroy(top_problem* h) {
   if (h == nullptr) return;
-  // Handles with graphs or a reverse-pass stream wait for their work; a plain handle releases its
-  // buffers behind an event recorded on its stream and returns at once.
+  // Handles with graphs wait for their work; a handle on the pool releases its buffers behind an
+  // event recorded on its stream and returns at once; a handle on a caller's workspace leaves
+  // the workspace's stream order to the caller.
   std::shared_ptr<ReleaseEvent> done;
   if (!h->graphs.empty() || h->cap_stream != nullptr) {
     (void)hipStreamSynchronize(h->stream);
-  } else {
+  } else if (!h->allocs.empty()) {
     done = std::make_shared<ReleaseEvent>();
     if (hipEventCreateWithFlags(&done->ev, hipEventDisableTiming) != hipSuccess ||
         hipEventRecord(done->ev, h->stream) != hipSuccess) {
@@ -962,30 +1062,55 @@ void top_destroy(top_problem* h) {
     (void)hipEventDestroy(h->ev_valid);
   }
   pin_put(h->pin);
-  for (auto& b : h->allocs) pool_put(b.p, b.bytes, b.dev, h->stream, done);
+  for (auto& b : h->allocs) pool_put(b.p, b.bytes, b.dev, h->stream, done);  // none on a caller workspace
   delete h;
 }
 
-static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
-                              const double* durations, const double* bc, const double* box_lo,
-                              const double* box_hi, int32_t n_faces, const double* faces, const double* vmax,
-                              const double* rho, const top_options* opt_in, hipStream_t stream,
-                              top_problem** out) {
-  if (out == nullptr) return fail(TOP_E_INVALID, "out is NULL");
-  *out = nullptr;
+void top_trim(void) {
+  int dev0 = 0;
+  const bool have_dev = hipGetDevice(&dev0) == hipSuccess;
+  std::vector<std::pair<int, void*>> blocks;
+  {
+    std::lock_guard<std::mutex> lk(g_pool.mu);
+    for (auto& kv : g_pool.blocks) blocks.push_back({kv.first.first, kv.second.p});
+    g_pool.blocks.clear();
+    g_pool.cached = 0;
+  }
+  for (auto& b : blocks) {
+    (void)hipSetDevice(b.first);
+    (void)hipFree(b.second);  // waits for the device's queued work
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (auto it = g_plans.begin(); it != g_plans.end();) {
+      if (it->second.use_count() == 1) {
+        (void)hipSetDevice(it->second->device);
+        it = g_plans.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    for (auto it = g_shapes.begin(); it != g_shapes.end();) {
+      if (it->second.use_count() == 1) {
+        (void)hipSetDevice(it->second->device);
+        it = g_shapes.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  if (have_dev) (void)hipSetDevice(dev0);
+}
+
+// Options after defaults, checked as far as they can be without the trajectory lengths, and the
+// kernel variant they select.  box/vel/polytope say which corridor and bound are given.
+static top_status resolve_options(const top_options* opt_in, bool box, bool vel, bool polytope, top_options* opt_out,
+                                  top::Variant* v_out) {
   top_options opt;
   if (opt_in != nullptr) opt = *opt_in; else top_default_options(&opt);
-  if (n_traj < 1) return fail(TOP_E_INVALID, "n_traj must be >= 1 (got %d)", n_traj);
-  if (seg_offsets == nullptr) return fail(TOP_E_INVALID, "seg_offsets is NULL");
-  if (waypoints == nullptr || durations == nullptr || rho == nullptr)
-    return fail(TOP_E_INVALID, "waypoints, durations and rho are required");
-  if ((box_lo == nullptr) != (box_hi == nullptr)) return fail(TOP_E_INVALID, "give both box_lo and box_hi, or neither");
-  if (seg_offsets[0] != 0) return fail(TOP_E_INVALID, "seg_offsets[0] must be 0");
-  for (int b = 0; b < n_traj; ++b)
-    if (seg_offsets[b + 1] <= seg_offsets[b])
-      return fail(TOP_E_INVALID, "trajectory %d has no segment (seg_offsets must increase strictly)", b);
-  const int64_t S = seg_offsets[n_traj];
-  if (S + n_traj >= (int64_t)top::kHaloBit) return fail(TOP_E_UNSUPPORTED, "too many segments (%lld)", (long long)S);
   if (opt.order != 3 && opt.order != 4) return fail(TOP_E_UNSUPPORTED, "order must be 3 or 4 (got %d)", opt.order);
   const int s = opt.n_cont == 0 ? opt.order : opt.n_cont;
   if (s != opt.order && s != opt.order + 1 && s != 2 * opt.order - 1)
@@ -998,100 +1123,225 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   if (opt.fix_interior != 0 && opt.fix_interior != 1) return fail(TOP_E_INVALID, "fix_interior must be 0 or 1");
   if (opt.checkpoint_every < 0 || (opt.checkpoint_every > 0 && opt.max_taped_iters < 1))
     return fail(TOP_E_INVALID, "checkpoint_every >= 0, and max_taped_iters >= 1 when it is > 0");
-  top::Variant v{opt.precision == TOP_FP64 ? 1 : 0, opt.order, s, box_lo != nullptr, vmax != nullptr,
-                 faces != nullptr ? top::kFaces : 0, opt.local_solve == 1 ? 1 : 0};
   if (opt.local_solve != 0 && opt.local_solve != 1) return fail(TOP_E_INVALID, "local_solve must be 0 or 1");
+  top::Variant v{opt.precision == TOP_FP64 ? 1 : 0, opt.order, s, box, vel, polytope ? top::kFaces : 0,
+                 opt.local_solve == 1 ? 1 : 0};
   if (v.num) {
-    if (vmax == nullptr) return fail(TOP_E_UNSUPPORTED, "NumericSolve needs a velocity bound (vmax)");
-    if (faces != nullptr || s != opt.order || opt.checkpoint_every > 0 || opt.check_every > 0)
+    if (!vel) return fail(TOP_E_UNSUPPORTED, "NumericSolve needs a velocity bound (vmax)");
+    if (polytope || s != opt.order || opt.checkpoint_every > 0 || opt.check_every > 0)
       return fail(TOP_E_UNSUPPORTED, "NumericSolve takes s = p, a box or no corridor, no tape and no checks");
     if (opt.lbfgs_iters < 0) return fail(TOP_E_INVALID, "lbfgs_iters must be >= 0");
   }
   const bool taped = opt.checkpoint_every > 0;
-  if (faces != nullptr && taped) return fail(TOP_E_UNSUPPORTED, "a polytope corridor cannot be combined with a tape");
-  if (opt.tile_lanes != 0 &&
-      (opt.tile_lanes < 64 || opt.tile_lanes > max_tile(v, taped) || opt.tile_lanes % 64 != 0))
-    return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, %d] (got %d)", max_tile(v, taped),
-                opt.tile_lanes);
+  if (polytope && taped) return fail(TOP_E_UNSUPPORTED, "a polytope corridor cannot be combined with a tape");
   if (opt.halo < 0) return fail(TOP_E_INVALID, "halo must be >= 0");
   if (opt.check_every < 0) return fail(TOP_E_INVALID, "check_every must be >= 0 (got %d)", opt.check_every);
   if (opt.check_every > 0) {
     if (taped) return fail(TOP_E_UNSUPPORTED, "residual checks cannot be combined with a tape");
-    int64_t longest = 0;
-    for (int b = 0; b < n_traj; ++b) longest = std::max<int64_t>(longest, seg_offsets[b + 1] - seg_offsets[b]);
-    if (longest > 65535LL * 128)  // the check kernels' trajectory-major grids
-      return fail(TOP_E_UNSUPPORTED, "residual checks support trajectories of at most %lld segments",
-                  65535LL * 128);
     if (opt.adapt_rho != 0 && opt.adapt_rho != 1) return fail(TOP_E_INVALID, "adapt_rho must be 0 or 1");
     if (!std::isfinite(opt.tol)) return fail(TOP_E_INVALID, "tol must be finite");
     if (opt.adapt_rho && !(opt.mu > 1.0 && opt.tau_incr > 1.0 && opt.tau_decr > 1.0 && std::isfinite(opt.mu) &&
                            std::isfinite(opt.tau_incr) && std::isfinite(opt.tau_decr)))
       return fail(TOP_E_INVALID, "mu, tau_incr and tau_decr must be finite and > 1");
   }
+  opt.n_cont = s;
+  *opt_out = opt;
+  *v_out = v;
+  return TOP_OK;
+}
 
-  top_problem* h = new (std::nothrow) top_problem();
-  if (h == nullptr) return fail(TOP_E_NOMEM, "host allocation failed");
-  {
-    // Several kernels keep spill areas or local arrays in per-lane scratch (up to a few KiB; the
-    // build refuses any kernel above top::kScratchLimit).  A kernel whose scratch exceeded the
-    // runtime's per-lane stack limit was seen to compute wrong values, so raise the limit first.
-    size_t lim = 0;
-    if (hipDeviceGetLimit(&lim, hipLimitStackSize) == hipSuccess && lim < top::kScratchLimit)
-      (void)hipDeviceSetLimit(hipLimitStackSize, top::kScratchLimit);
-  }
+// Reduction chunks of a CSR shape (chunk j of trajectory b covers kReduceChunk segments from
+// off[b] + j * kReduceChunk).
+static int64_t count_chunks(const int64_t* off, int B) {
+  int64_t n = 0;
+  for (int b = 0; b < B; ++b) n += (off[b + 1] - off[b] + top::kReduceChunk - 1) / top::kReduceChunk;
+  return n;
+}
+
+// Fill the shape fields of a handle that has no buffers yet.
+static void shape_handle(top_problem* h, const top_options& opt, const top::Variant& v, int B, int64_t S) {
   h->opt = opt;
-  h->opt.n_cont = s;
   h->v = v;
-  h->B = n_traj;
+  h->B = B;
   h->S = S;
   h->ld = (S + 63) / 64 * 64;
   h->rsz = v.prec == 0 ? sizeof(float) : sizeof(double);
-  h->off.assign(seg_offsets, seg_offsets + n_traj + 1);
-  for (int b = 0; b < n_traj; ++b) h->max_len = std::max<int64_t>(h->max_len, seg_offsets[b + 1] - seg_offsets[b]);
-  h->stream = stream;
   top::Layout L{v.p, v.s, v.box, v.vel, v.faces, v.num};
   h->nf = L.nf();
+}
+
+// Workspace bytes of a problem (exact for the given presence flags and chunk count), or 0 with the
+// error set.
+static size_t workspace_need(int32_t n_traj, int64_t S, const top_options& opt, const top::Variant& v, bool has_box,
+                             bool has_vmax, bool has_bc, int64_t n_chunks) {
+  top_problem sz;
+  sz.sizing = true;
+  shape_handle(&sz, opt, v, n_traj, S);
+  if (sz.allocate_buffers(has_box, has_vmax, has_bc, n_chunks) != TOP_OK) return 0;
+  return sz.ws_used;
+}
+
+static size_t workspace_bytes_impl(int32_t n_traj, int64_t n_seg_total, int32_t n_faces, const top_options* opt_in) {
+  if (n_traj < 1) { fail(TOP_E_INVALID, "n_traj must be >= 1 (got %d)", n_traj); return 0; }
+  if (n_seg_total < n_traj) {
+    fail(TOP_E_INVALID, "n_seg_total must be >= n_traj (every trajectory has a segment; got %lld)",
+         (long long)n_seg_total);
+    return 0;
+  }
+  if (n_seg_total + n_traj >= (int64_t)top::kHaloBit) {
+    fail(TOP_E_UNSUPPORTED, "too many segments (%lld)", (long long)n_seg_total);
+    return 0;
+  }
+  top_options opt;
+  top::Variant v;
+  if (resolve_options(opt_in, n_faces == 0, true, n_faces > 0, &opt, &v) != TOP_OK) return 0;
+  // chunks: sum over trajectories of ceil(len / c) <= (S + B (c - 1)) / c
+  const int64_t c = top::kReduceChunk;
+  const int64_t chunks = (n_seg_total + (int64_t)n_traj * (c - 1)) / c;
+  const size_t need = workspace_need(n_traj, n_seg_total, opt, v, n_faces == 0, true, true, chunks);
+  return need == 0 ? 0 : need + kWsAlign;  // room to align an arbitrary base
+}
+
+static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
+                              const double* durations, const double* bc, const double* box_lo,
+                              const double* box_hi, int32_t n_faces, const double* faces, const double* vmax,
+                              const double* rho, const top_options* opt_in, void* workspace, size_t workspace_bytes,
+                              hipStream_t stream, top_problem** out, top::Mem mem = top::Mem::kCallerWs) {
+  using top::Mem;
+  if (out == nullptr) return fail(TOP_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n_traj < 1) return fail(TOP_E_INVALID, "n_traj must be >= 1 (got %d)", n_traj);
+  if (seg_offsets == nullptr) return fail(TOP_E_INVALID, "seg_offsets is NULL");
+  if (waypoints == nullptr || durations == nullptr || rho == nullptr)
+    return fail(TOP_E_INVALID, "waypoints, durations and rho are required");
+  if ((box_lo == nullptr) != (box_hi == nullptr)) return fail(TOP_E_INVALID, "give both box_lo and box_hi, or neither");
+  if ((workspace == nullptr) != (workspace_bytes == 0))
+    return fail(TOP_E_INVALID, "give a workspace with its size, or NULL and 0 for the library's pool");
+  if (seg_offsets[0] != 0) return fail(TOP_E_INVALID, "seg_offsets[0] must be 0");
+  for (int b = 0; b < n_traj; ++b)
+    if (seg_offsets[b + 1] <= seg_offsets[b])
+      return fail(TOP_E_INVALID, "trajectory %d has no segment (seg_offsets must increase strictly)", b);
+  const int64_t S = seg_offsets[n_traj];
+  if (S + n_traj >= (int64_t)top::kHaloBit) return fail(TOP_E_UNSUPPORTED, "too many segments (%lld)", (long long)S);
+  top_options opt;
+  top::Variant v;
+  top_status st = resolve_options(opt_in, box_lo != nullptr, vmax != nullptr, faces != nullptr, &opt, &v);
+  if (st != TOP_OK) return st;
+  const int s = opt.n_cont;
+  const bool taped = opt.checkpoint_every > 0;
+  if (opt.check_every > 0) {
+    int64_t longest = 0;
+    for (int b = 0; b < n_traj; ++b) longest = std::max<int64_t>(longest, seg_offsets[b + 1] - seg_offsets[b]);
+    if (longest > 65535LL * 128)  // the check kernels' trajectory-major grids
+      return fail(TOP_E_UNSUPPORTED, "residual checks support trajectories of at most %lld segments",
+                  65535LL * 128);
+  }
+  if (opt.tile_lanes != 0 &&
+      (opt.tile_lanes < 64 || opt.tile_lanes > max_tile(v, taped) || opt.tile_lanes % 64 != 0))
+    return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, %d] (got %d)", max_tile(v, taped),
+                opt.tile_lanes);
+  if (mem == Mem::kPool) workspace = nullptr, workspace_bytes = 0;
+  const std::vector<int64_t> off(seg_offsets, seg_offsets + n_traj + 1);
+  // execution plan: explicit, tuned for this shape class, or the default
+  int W = opt.tile_lanes, halo = opt.halo;
+  if (W == 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load();
+    auto it = g_tune.find(shape_key(v, off));
+    if (it != g_tune.end() && it->second.first <= max_tile(v, taped)) {
+      W = it->second.first;
+      if (halo == 0) halo = it->second.second;
+    }
+  }
+  if (W == 0) W = max_tile(v, taped);
+  if (halo == 0) halo = std::max(1, std::min(32, W / 8));
+  if (2 * halo >= W) return fail(TOP_E_INVALID, "halo %d too large for %d-lane tiles", halo, W);
+  if (taped && halo < 2) {
+    if (opt.halo != 0) return fail(TOP_E_INVALID, "a handle that records a tape needs halo >= 2 (got %d)", halo);
+    halo = 2;
+  }
+  Plan own_plan;
+  if (mem == Mem::kStatic) own_plan = make_plan(off, W, halo);
+  // The workspace must hold this problem's buffers (checked before any device work).
+  size_t ws_pad = 0;
+  const int64_t n_chunks = count_chunks(seg_offsets, n_traj);
+  if (workspace != nullptr) {
+    ws_pad = (kWsAlign - (uintptr_t)workspace % kWsAlign) % kWsAlign;
+    size_t need = workspace_need(n_traj, S, opt, v, box_lo != nullptr, vmax != nullptr, bc != nullptr, n_chunks);
+    if (need == 0) return fail(TOP_E_INVALID, "workspace sizing failed");
+    if (mem == Mem::kStatic) {
+      top_problem sz;
+      sz.sizing = true;
+      sz.B = n_traj;
+      (void)sz.allocate_tables(n_chunks, own_plan.lanes.size());
+      need += sz.ws_used;
+    }
+    if (workspace_bytes < ws_pad + need)
+      return fail(TOP_E_WORKSPACE, "workspace of %zu bytes is too small: this problem needs %zu (plus %zu to align it)",
+                  workspace_bytes, need, ws_pad);
+  }
+  {
+    // Several kernels keep spill areas or local arrays in per-lane scratch (the build refuses any
+    // kernel above top::kScratchLimit bytes).  A kernel whose scratch exceeded the runtime's per-lane
+    // stack limit was seen to compute wrong values, so the limit is raised first, and a device on
+    // which it cannot be raised is refused.
+    size_t lim = 0;
+    hipError_t e = hipDeviceGetLimit(&lim, hipLimitStackSize);
+    if (e == hipSuccess && lim < top::kScratchLimit) {
+      e = hipDeviceSetLimit(hipLimitStackSize, top::kScratchLimit);
+      if (e == hipSuccess) e = hipDeviceGetLimit(&lim, hipLimitStackSize);
+    }
+    if (e != hipSuccess) return fail(TOP_E_HIP, "per-lane stack limit: %s", hipGetErrorString(e));
+    if (lim < top::kScratchLimit)
+      return fail(TOP_E_HIP, "the per-lane stack limit stays at %zu bytes (kernels need %zu)", lim,
+                  (size_t)top::kScratchLimit);
+  }
+
+  top_problem* h = new (std::nothrow) top_problem();
+  if (h == nullptr) return fail(TOP_E_NOMEM, "host allocation failed");
+  shape_handle(h, opt, v, n_traj, S);
+  h->off = off;
+  h->explicit_tile = opt.tile_lanes != 0;
+  for (int b = 0; b < n_traj; ++b) h->max_len = std::max<int64_t>(h->max_len, seg_offsets[b + 1] - seg_offsets[b]);
+  h->stream = stream;
+  if (workspace != nullptr) {
+    h->ws = static_cast<char*>(workspace) + ws_pad;
+    h->ws_cap = workspace_bytes - ws_pad;
+  }
 
   auto bail = [&](top_status st) { top_destroy(h); return st; };
   const size_t R = h->rsz, ld = (size_t)h->ld;
-  top_status st;
-  if ((st = h->alloc(&h->Hr, L.nhr() * ld * R)) != TOP_OK) return bail(st);
-  if (v.faces) {
-    if ((st = h->alloc(&h->Urot, 9 * ld * R)) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->fa, 4 * (size_t)top::kFaces * ld * R)) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->lam, 3 * ld * sizeof(double))) != TOP_OK) return bail(st);
+  if (mem != Mem::kStatic) {
+    if ((st = get_shape(h->off, &h->shape)) != TOP_OK) return bail(st);
+    h->off_dev = h->shape->off_dev;
+    h->chunk_off = h->shape->chunk_off;
+    h->chunk_traj = h->shape->chunk_traj;
+    h->n_chunks = h->shape->n_chunks;
+  } else {
+    h->n_chunks = (int)n_chunks;
   }
-  if ((st = h->alloc(&h->iT, ld * R)) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->lo, 3 * ld * R)) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->hi, 3 * ld * R)) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->vmax, ld * R)) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->bcL, (size_t)n_traj * 3 * s * R)) != TOP_OK) return bail(st);
-  for (int q = 0; q < 2; ++q)  // the setup zeroes the padding columns S..ld-1 of both
-    if ((st = h->alloc(&h->state[q], (size_t)h->nf * ld * R)) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->cbuf, 3 * (size_t)L.n() * ld * R)) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->zold, 3 * (size_t)s * ld * R)) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->flags, ld)) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->traj, ld * sizeof(int32_t))) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->Tdev, ld * sizeof(double))) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->rho_seg, ld * sizeof(double))) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->part, 3 * (size_t)S * sizeof(double))) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->out, 3 * (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->flag_dev, 2 * sizeof(int))) != TOP_OK) return bail(st);
-  if ((st = h->alloc(&h->rho_traj, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
-  if ((st = get_shape(h->off, &h->shape)) != TOP_OK) return bail(st);
-  h->off_dev = h->shape->off_dev;
-  h->chunk_off = h->shape->chunk_off;
-  h->chunk_traj = h->shape->chunk_traj;
-  h->n_chunks = h->shape->n_chunks;
-  if ((st = h->alloc(&h->chunk_sum, 3 * std::max<size_t>(h->n_chunks, 1) * sizeof(double))) != TOP_OK) return bail(st);
+  if ((st = h->allocate_buffers(box_lo != nullptr, vmax != nullptr, bc != nullptr, h->n_chunks)) != TOP_OK)
+    return bail(st);
+  if (mem == Mem::kStatic) {
+    // shape tables and lane map into the workspace, from host copies the handle keeps
+    h->own_tables = true;
+    h->own_plan = std::move(own_plan);
+    chunk_tables(h->off, &h->own_chunk_off, &h->own_chunk_traj);
+    if ((st = h->allocate_tables(h->n_chunks, h->own_plan.lanes.size())) != TOP_OK) return bail(st);
+    hipError_t e = hipMemcpyAsync(const_cast<int64_t*>(h->off_dev), h->off.data(), h->off.size() * sizeof(int64_t),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(const_cast<int32_t*>(h->chunk_off), h->own_chunk_off.data(),
+                         h->own_chunk_off.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !h->own_chunk_traj.empty())
+      e = hipMemcpyAsync(const_cast<int32_t*>(h->chunk_traj), h->own_chunk_traj.data(),
+                         h->own_chunk_traj.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h->own_lanes, h->own_plan.lanes.data(), h->own_plan.lanes.size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return bail(fail(TOP_E_HIP, "table upload failed: %s", hipGetErrorString(e)));
+  }
   if (opt.check_every > 0) {
-    if ((st = h->alloc(&h->done_dev, (size_t)n_traj)) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->fresh, (size_t)n_traj)) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->swept, (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->stop_at, (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->ratio, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->check_lists, 3 * (size_t)n_traj * sizeof(int32_t))) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->check_counts, 3 * sizeof(int32_t))) != TOP_OK) return bail(st);
     hipError_t e = hipMemsetAsync(h->done_dev, 0, (size_t)n_traj, stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->swept, 0, (size_t)n_traj * sizeof(int32_t), stream);
     if (e == hipSuccess) e = hipMemsetAsync(h->stop_at, 0xff, (size_t)n_traj * sizeof(int32_t), stream);
@@ -1102,29 +1352,18 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     hipError_t e = hipMemcpyAsync(h->rho_traj, rho, (size_t)n_traj * sizeof(double), hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "rho copy failed: %s", hipGetErrorString(e)));
   }
-  if (opt.checkpoint_every > 0) {
-    h->tape_slots = opt.max_taped_iters / opt.checkpoint_every + 1;
-    if ((st = h->alloc(&h->tape, (size_t)h->tape_slots * h->nf * ld * R)) != TOP_OK) return bail(st);
-    if ((st = h->alloc(&h->Hd, L.nh() * ld * R)) != TOP_OK) return bail(st);
+  if (taped) {
     const size_t nwp = (size_t)(S + n_traj) * 3 * sizeof(double);
-    if ((st = h->alloc(&h->wp64, nwp)) != TOP_OK) return bail(st);
     hipError_t e = hipMemcpyAsync(h->wp64, waypoints, nwp, hipMemcpyDeviceToDevice, stream);
     if (e == hipSuccess && box_lo != nullptr) {
-      if ((st = h->alloc(&h->lo64, (size_t)S * 3 * sizeof(double))) != TOP_OK) return bail(st);
-      if ((st = h->alloc(&h->hi64, (size_t)S * 3 * sizeof(double))) != TOP_OK) return bail(st);
       e = hipMemcpyAsync(h->lo64, box_lo, (size_t)S * 3 * sizeof(double), hipMemcpyDeviceToDevice, stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(h->hi64, box_hi, (size_t)S * 3 * sizeof(double), hipMemcpyDeviceToDevice, stream);
     }
-    if (e == hipSuccess && vmax != nullptr) {
-      if ((st = h->alloc(&h->vmax64, (size_t)n_traj * sizeof(double))) != TOP_OK) return bail(st);
+    if (e == hipSuccess && vmax != nullptr)
       e = hipMemcpyAsync(h->vmax64, vmax, (size_t)n_traj * sizeof(double), hipMemcpyDeviceToDevice, stream);
-    }
-    if (e == hipSuccess && bc != nullptr) {
-      const size_t nbc = (size_t)n_traj * 2 * v.p * 3 * sizeof(double);
-      if ((st = h->alloc(&h->bc64, nbc)) != TOP_OK) return bail(st);
-      e = hipMemcpyAsync(h->bc64, bc, nbc, hipMemcpyDeviceToDevice, stream);
-    }
+    if (e == hipSuccess && bc != nullptr)
+      e = hipMemcpyAsync(h->bc64, bc, (size_t)n_traj * 2 * v.p * 3 * sizeof(double), hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "input copy failed: %s", hipGetErrorString(e)));
   }
   {
@@ -1140,7 +1379,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   {
     hipError_t e = top::launch_validate(sa, v.p, h->flag_dev, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "validation launch failed: %s", hipGetErrorString(e)));
-    h->pin = pin_get();
+    h->pin = mem == Mem::kStatic ? nullptr : pin_get();
     if (h->pin != nullptr) {
       e = hipMemcpyAsync(h->pin, h->flag_dev, 2 * sizeof(int), hipMemcpyDeviceToHost, stream);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&h->ev_valid, hipEventDisableTiming);
@@ -1169,26 +1408,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     hipError_t e = hipMemcpyAsync(h->tape, h->state[0], (size_t)h->nf * ld * R, hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "tape copy failed: %s", hipGetErrorString(e)));
   }
-  // execution plan: explicit, tuned for this shape class, or the default
-  int W = opt.tile_lanes, halo = opt.halo;
-  h->explicit_tile = W != 0;
-  if (W == 0) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    tune_cache_load();
-    auto it = g_tune.find(shape_key(v, h->off));
-    if (it != g_tune.end() && it->second.first <= max_tile(v, taped)) {
-      W = it->second.first;
-      if (halo == 0) halo = it->second.second;
-    }
-  }
-  if (W == 0) W = max_tile(v, taped);
-  if (halo == 0) halo = std::max(1, std::min(32, W / 8));
-  if (2 * halo >= W) return bail(fail(TOP_E_INVALID, "halo %d too large for %d-lane tiles", halo, W));
-  if (taped && halo < 2) {
-    if (opt.halo != 0) return bail(fail(TOP_E_INVALID, "a handle that records a tape needs halo >= 2 (got %d)", halo));
-    halo = 2;
-  }
-  if ((st = get_plan(h->off, W, halo, &h->pe)) != TOP_OK) return bail(st);
+  if (mem != Mem::kStatic && (st = get_plan(h->off, W, halo, &h->pe)) != TOP_OK) return bail(st);
   // the input check's verdict
   int bad = 0;
   {
@@ -1222,21 +1442,35 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
 top_status top_create(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
                       const double* durations, const double* bc, const double* box_lo,
                       const double* box_hi, const double* vmax, const double* rho,
-                      const top_options* opt, hipStream_t stream, top_problem** out) {
+                      const top_options* opt, void* workspace, size_t workspace_bytes, hipStream_t stream,
+                      top_problem** out) {
   return create_impl(n_traj, seg_offsets, waypoints, durations, bc, box_lo, box_hi, 0, nullptr, vmax, rho, opt,
-                     stream, out);
+                     workspace, workspace_bytes, stream, out);
+}
+
+
+size_t top_workspace_bytes(int32_t n_traj, int64_t n_seg_total, const top_options* opt) {
+  return workspace_bytes_impl(n_traj, n_seg_total, 0, opt);
+}
+
+size_t top_workspace_bytes_polytope(int32_t n_traj, int64_t n_seg_total, int32_t n_faces, const top_options* opt) {
+  if (n_faces < 1 || n_faces > top::kFaces) {
+    fail(TOP_E_UNSUPPORTED, "n_faces must be in [1, %d] (got %d)", top::kFaces, n_faces);
+    return 0;
+  }
+  return workspace_bytes_impl(n_traj, n_seg_total, n_faces, opt);
 }
 
 top_status top_create_polytope(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
                                const double* durations, const double* bc, int32_t n_faces, const double* faces,
                                const double* vmax, const double* rho, const top_options* opt,
-                               hipStream_t stream, top_problem** out) {
+                               void* workspace, size_t workspace_bytes, hipStream_t stream, top_problem** out) {
   if (out != nullptr) *out = nullptr;
   if (faces == nullptr) return fail(TOP_E_INVALID, "faces is NULL");
   if (n_faces < 1 || n_faces > top::kFaces)
     return fail(TOP_E_UNSUPPORTED, "n_faces must be in [1, %d] (got %d)", top::kFaces, n_faces);
   return create_impl(n_traj, seg_offsets, waypoints, durations, bc, nullptr, nullptr, n_faces, faces, vmax, rho, opt,
-                     stream, out);
+                     workspace, workspace_bytes, stream, out);
 }
 
 top_status top_iterate(top_problem* h, int32_t k) {
@@ -1396,10 +1630,9 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   if (h == nullptr) return fail(TOP_E_INVALID, "handle is NULL");
   if (k_probe < 1) return fail(TOP_E_INVALID, "k_probe must be >= 1");
   if (h->explicit_tile) return TOP_OK;
-  if (h->scratch == nullptr) {
-    top_status s = h->alloc(&h->scratch, (size_t)h->nf * h->ld * h->rsz);
-    if (s != TOP_OK) return s;
-  }
+  // The probe sweeps write the state buffer the next sweep will overwrite anyway.  Lanes of stopped
+  // trajectories store their unchanged state there (or nothing), so that buffer keeps holding it.
+  void* probe_out = h->state[h->cur ^ 1];
   int64_t mx = 0;
   for (int b = 0; b < h->B; ++b) mx = std::max(mx, h->off[b + 1] - h->off[b]);
   std::vector<std::pair<int, int>> cands;
@@ -1425,8 +1658,8 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
       int remaining = k_probe;
       while (remaining > 0) {
         const int n = pl.halo > 0 ? std::min(remaining, pl.halo) : remaining;
-        // probe sweeps read the live state and write scratch; the iterate is not advanced
-        s = h->sweep_launch(pl, cand->dev, h->state[h->cur], h->scratch, n, false, h->stream, true);
+        // probe sweeps read the live state; the iterate is not advanced
+        s = h->sweep_launch(pl, cand->dev, h->state[h->cur], probe_out, n, false, h->stream, true);
         if (s != TOP_OK) return s;
         remaining -= n;
       }
@@ -1455,4 +1688,17 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   return TOP_OK;
 }
 
+
 }  // extern "C"
+
+namespace top {
+top_status internal_create(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
+                           const double* durations, const double* bc, const double* box_lo, const double* box_hi,
+                           const double* vmax, const double* rho, const top_options* opt, void* workspace,
+                           size_t workspace_bytes, hipStream_t stream, top_problem** out, Mem mem) {
+  return create_impl(n_traj, seg_offsets, waypoints, durations, bc, box_lo, box_hi, 0, nullptr, vmax, rho, opt,
+                     workspace, workspace_bytes, stream, out, mem);
+}
+
+top_status internal_error(top_status s, const char* text) { return fail(s, "%s", text); }
+}  // namespace top

@@ -1,5 +1,6 @@
 // FP32 instantiations of the resident sweep kernel: quintic tiles of up to 512 lanes (two waves
-// per SIMD), septic tiles of up to 256 lanes (one wave per SIMD, room for its larger state).
+// per SIMD), septic tiles of up to 256 lanes (the box + velocity instance is compiled for two waves
+// per SIMD as well, sweep_min_waves; the other septic instances for one).
 #include "sweep_impl.h"
 
 namespace top {

@@ -37,13 +37,14 @@ def test_default_options_and_error_text():
     assert isinstance(binding.lib().top_last_error(), bytes)
 
 
-def _create(n_traj, offs, opts=None, with_ptrs=True):
+def _create(n_traj, offs, opts=None, with_ptrs=True, ws=None, ws_bytes=0, box=False, vmax=False):
     L = binding.lib()
     offs = np.asarray(offs, dtype=np.int64)
     h = ctypes.c_void_p()
     fake = 0x1000 if with_ptrs else None   # never dereferenced: host checks fail first
-    st = L.top_create(n_traj, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), fake, fake, None, None,
-                      None, None, fake, None if opts is None else ctypes.byref(opts), None, ctypes.byref(h))
+    st = L.top_create(n_traj, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), fake, fake, None,
+                      fake if box else None, fake if box else None, fake if vmax else None, fake,
+                      None if opts is None else ctypes.byref(opts), ws, ws_bytes, None, ctypes.byref(h))
     return st, h.value, L.top_last_error().decode()
 
 
@@ -107,3 +108,63 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "libtop.so"))
     with pytest.raises(ImportError, match="missing"):
         binding.lib()
+
+
+# ---------------------------------------------------------------------------
+# Caller-owned workspace: the size query and the too-small error are host-only.
+# ---------------------------------------------------------------------------
+
+def _ws(B, S, **kw):
+    o = binding.default_options()
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return binding.lib().top_workspace_bytes(B, S, ctypes.byref(o))
+
+
+def test_workspace_bytes_query():
+    S = 10_000
+    n32, n64 = _ws(4, S), _ws(4, S, precision=binding.TOP_FP64)
+    assert n32 > 0 and n64 > n32
+    # at least the two iterate buffers: 99 float fields per segment (quintic, box + velocity)
+    ld = (S + 63) // 64 * 64
+    assert n32 >= 2 * 99 * ld * 4
+    assert _ws(4, 2 * S) > n32                                   # grows with the segment count
+    assert _ws(4, S, order=4) > n32                              # septic: more fields, larger factors
+    taped = _ws(4, S, checkpoint_every=10, max_taped_iters=100)
+    assert taped - n32 >= 11 * 99 * ld * 4                       # the tape holds 100 / 10 + 1 states
+    assert _ws(4, S, check_every=10) > n32                       # per-trajectory check state
+    o = binding.default_options()
+    npoly = binding.lib().top_workspace_bytes_polytope(4, S, 8, ctypes.byref(o))
+    assert npoly > n32                                           # per-axis factors, rotation, faces
+    assert binding.top_workspace_bytes(4, S) == n32              # the Python wrapper
+
+
+def test_workspace_bytes_query_errors():
+    L = binding.lib()
+    assert L.top_workspace_bytes(0, 10, None) == 0 and "n_traj" in L.top_last_error().decode()
+    assert L.top_workspace_bytes(4, 3, None) == 0                # fewer segments than trajectories
+    o = binding.default_options()
+    o.order = 5
+    assert L.top_workspace_bytes(1, 10, ctypes.byref(o)) == 0 and "order" in L.top_last_error().decode()
+    assert L.top_workspace_bytes_polytope(1, 10, 9, None) == 0   # at most 8 faces
+    with pytest.raises(binding.TopError):
+        binding.top_workspace_bytes(0, 10)
+
+
+def test_workspace_too_small_is_rejected_before_device_work():
+    offs = [0, 300, 1000]
+    st, h, msg = _create(2, offs, ws=0x100000, ws_bytes=4096, box=True, vmax=True)
+    assert st == binding.TOP_E_WORKSPACE and h is None, msg
+    need = int(re.search(r"needs (\d+)", msg).group(1))
+    assert 0 < need <= _ws(2, 1000)                             # the query is an upper bound
+    # one byte short (256-aligned base: no alignment padding) is still refused
+    st, h, msg = _create(2, offs, ws=0x100000, ws_bytes=need - 1, box=True, vmax=True)
+    assert st == binding.TOP_E_WORKSPACE and h is None
+    # an unaligned base needs the padding on top
+    st, h, msg = _create(2, offs, ws=0x100010, ws_bytes=need, box=True, vmax=True)
+    assert st == binding.TOP_E_WORKSPACE and "align" in msg
+    # a pointer without a size, or a size without a pointer
+    st, h, msg = _create(2, offs, ws=0x100000, ws_bytes=0)
+    assert st == binding.TOP_E_INVALID and "workspace" in msg
+    st, h, msg = _create(2, offs, ws=None, ws_bytes=4096)
+    assert st == binding.TOP_E_INVALID and "workspace" in msg

@@ -219,20 +219,22 @@ def test_repeat_runs_bitwise_equal():
     assert np.array_equal(a, b)
 
 
-def test_buffers_reused_across_streams_after_destroy():
-    # top_destroy does not wait: a handle created right after on another stream reuses the pooled
-    # buffers only after the released handle's queued sweeps have finished
+@pytest.mark.parametrize("library_pool", [True, False])
+def test_buffers_reused_across_streams_after_destroy(library_pool):
+    # top_destroy does not wait: a handle created right after on another stream reuses the released
+    # memory only after the released handle's queued sweeps have finished (the library's pool orders
+    # that with an event; a torch workspace through the caching allocator's per-stream blocks)
     from paper_2507_10290_amd import TopProblem
     w = make_config(3, n_traj=128)
     ref = run_gpu(w, 40, "fp32")[0]
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
     for rep in range(3):
         with torch.cuda.stream(s1):
-            a = TopProblem.from_workload(w, precision="fp32", stream=s1, use_graph=False)
+            a = TopProblem.from_workload(w, precision="fp32", stream=s1, use_graph=False, library_pool=library_pool)
             a.iterate(400)
             a.close()
         with torch.cuda.stream(s2):
-            b = TopProblem.from_workload(w, precision="fp32", stream=s2, use_graph=False)
+            b = TopProblem.from_workload(w, precision="fp32", stream=s2, use_graph=False, library_pool=library_pool)
             b.iterate(40)
             c = b.coeffs()
             b.close()
