@@ -287,6 +287,31 @@ void top_destroy(top_problem* h);
  * used them.  Handles stay valid. */
 void top_trim(void);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): one whole solve -- top_create, top_iterate(k), then
+ * top_residuals, top_cost and top_coeffs into the given buffers -- whose device memory (the problem's
+ * state, its shape tables and tile lane map) is a fixed array of TOP_STATIC_SCRATCH_BYTES compiled into
+ * the library, one copy per device, held until the process ends.  The call makes no hipMalloc or
+ * other device allocation, no pinned host allocation and no graph.
+ *   arguments    as top_create (box corridor or none; no workspace) and top_iterate; k >= 0
+ *   coeffs       [dev] float64 [S][3][2p], or NULL
+ *   cost         [dev] float64 [B], or NULL
+ *   r_primal/r_dual  [dev] float64 [B], or NULL (both NULL when k = 0: TOP_E_STATE otherwise)
+ * Options: a tape (checkpoint_every > 0) is TOP_E_UNSUPPORTED; use_graph is ignored.  A problem
+ * whose buffers exceed the scratch returns TOP_E_WORKSPACE before any device work (about 2.0 KB per
+ * segment in float64, 1.05 KB in float32, for quintic box + velocity: some 8,000 or 15,000 segments).
+ * Blocks until the outputs are written and returns TOP_E_NONFINITE like top_sync_status.  Every
+ * call on a device shares that device's copy of the array (one per process), which keeps what the
+ * last call left; a call writes everything it reads first.  Calls that overlapped on one device
+ * would race on the array: the library serialises them with a per-device lock, and each call waits
+ * for its own work before it returns. */
+#define TOP_STATIC_SCRATCH_BYTES (16u << 20)
+top_status top_solve_static(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
+                            const double* durations, const double* bc, const double* box_lo,
+                            const double* box_hi, const double* vmax, const double* rho,
+                            const top_options* opt, int32_t k, double* coeffs, double* cost,
+                            double* r_primal, double* r_dual, hipStream_t stream);
+
 /* Thread-local text of the last error reported by this library on the calling thread. */
 const char* top_last_error(void);
 

@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "TOP_OK", -1: "TOP_E_INVALID", -2: "TOP_E_WORKSPACE", -3: "TO
 EXPORTED = ["top_default_options", "top_workspace_bytes", "top_workspace_bytes_polytope", "top_create",
             "top_create_polytope", "top_iterate", "top_time_sweeps", "top_residuals", "top_cost",
             "top_coeffs", "top_backward", "top_tune", "top_convergence", "top_get_state", "top_set_state",
-            "top_sync_status", "top_get_plan", "top_destroy", "top_trim", "top_last_error"]
+            "top_sync_status", "top_get_plan", "top_destroy", "top_trim", "top_solve_static", "top_last_error"]
 
 
 class TopOptions(ctypes.Structure):
@@ -111,6 +111,9 @@ def lib() -> ctypes.CDLL:
     L.top_destroy.restype = None
     L.top_trim.argtypes = []
     L.top_trim.restype = None
+    L.top_solve_static.argtypes = [i32, i64p, dp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(TopOptions), i32,
+                                   dp, dp, dp, dp, vp]
+    L.top_solve_static.restype = ctypes.c_int
     L.top_last_error.argtypes = []
     L.top_last_error.restype = ctypes.c_char_p
     _lib = L

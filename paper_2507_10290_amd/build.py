@@ -20,7 +20,7 @@ LIB = os.path.join(PKG, "libtop.so")
 
 SOURCES = ["sweep_f32.hip", "sweep_f64.hip", "poly_f32.hip", "poly_f64.hip", "numeric_f32.hip", "numeric_f64.hip", "adjoint_f32.hip", "adjoint_f64.hip",
            "setup.hip",
-           "finalize.hip", "grad.hip", "adapt.hip", "api.cpp"]
+           "finalize.hip", "grad.hip", "adapt.hip", "api.cpp", "solve_static.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SCRATCH_LIMIT = 8192   # kScratchLimit of csrc/common.h
 # Packed FP32 VALU forms are kept out of the generated code.
