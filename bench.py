@@ -203,31 +203,42 @@ def plain_rate(w, d_all, K, n_traj):
     return segs * K / (time.perf_counter() - t0)
 
 
-def fwd_bwd(w, d, K, m, reps=3):
-    """Differentiation workload: forward with a tape (create + K sweeps + cost), then top_backward."""
+def fwd_bwd(w, d, K, m, reps=3, **kw):
+    """Differentiation workload: create with a tape, K sweeps + cost (the forward), then top_backward.
+
+    Two ratios: backward over the forward's sweeps and cost (create excluded: the comparison the
+    <= 4x budget is read against), and backward over create + forward (end to end)."""
     import torch
     dc = torch.ones(w.n_traj, dtype=torch.float64, device="cuda:0")
-    tf, tb = [], []
+    tc, tf, tb = [], [], []
+    plan = None
     for _ in range(reps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        prob = _problem(w, d, precision="fp32", checkpoint_every=m, max_taped_iters=K)
+        prob = _problem(w, d, precision="fp32", checkpoint_every=m, max_taped_iters=K, **kw)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
         prob.iterate(K)
         prob.cost()
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
+        t2 = time.perf_counter()
         prob.backward(dc)
         torch.cuda.synchronize()
-        t2 = time.perf_counter()
+        t3 = time.perf_counter()
+        plan = prob.plan()
         prob.close()
-        tf.append(t1 - t0)
-        tb.append(t2 - t1)
-    f, b = float(np.median(tf[1:])), float(np.median(tb[1:]))
-    return {"workload": "256 trajectories x 128 segments, fp32, K = 100, checkpoint every 10",
-            "forward_ms": round(f * 1e3, 3), "backward_ms": round(b * 1e3, 3),
+        tc.append(t1 - t0)
+        tf.append(t2 - t1)
+        tb.append(t3 - t2)
+    c, f, b = (float(np.median(x[1:])) for x in (tc, tf, tb))
+    return {"workload": f"{w.n_traj} trajectories x {w.n_seg // w.n_traj} segments, fp32, K = {K}, "
+                        f"checkpoint every {m}",
+            "tile_lanes": plan["tile_lanes"], "n_tiles": plan["n_tiles"],
+            "create_ms": round(c * 1e3, 3), "forward_ms": round(f * 1e3, 3), "backward_ms": round(b * 1e3, 3),
             "backward_over_forward": round(b / f, 2),
+            "backward_over_create_plus_forward": round(b / (c + f), 2),
             "forward_segment_updates_per_s": round(w.n_seg * K / f, 1),
-            "fwd_plus_bwd_segment_updates_per_s": round(w.n_seg * K / (f + b), 1)}
+            "fwd_plus_bwd_segment_updates_per_s": round(w.n_seg * K / (c + f + b), 1)}
 
 
 def septic_leg(w2, d2):
@@ -485,6 +496,8 @@ def main():
     ap.add_argument("--leg", choices=["fwd_bwd", "septic"],
                     help="run one extra leg alone (the differentiation workload's forward and backward, or "
                          "the 65,536-segment septic solve), print its figures and exit; for profilers")
+    ap.add_argument("--tile-lanes", type=int, default=0,
+                    help="with --leg: an explicit tile width for that leg's handles (0: the default plan)")
     ap.add_argument("--solve-config", type=int, nargs="+", metavar="I",
                     help="solve each listed benchmark workload once (fp32, default plan) and exit; "
                          "a short program to run under a profiler")
@@ -516,7 +529,8 @@ def main():
     dev = torch.device("cuda:0")
     if a.leg == "fwd_bwd":
         w4 = make_config(4)
-        print(json.dumps({"fwd_bwd": fwd_bwd(w4, _dev_inputs(w4, dev), w4.iters, 10)}), flush=True)
+        kw = {"tile_lanes": a.tile_lanes} if a.tile_lanes else {}
+        print(json.dumps({"fwd_bwd": fwd_bwd(w4, _dev_inputs(w4, dev), w4.iters, 10, **kw)}), flush=True)
         return
     if a.leg == "septic":
         w2 = make_config(2)

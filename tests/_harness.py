@@ -47,5 +47,14 @@ def per_traj_rel(w, a, b):
     return worst
 
 
+def worst_segment(a, b):
+    """(max over segments i of ||a_i - b_i|| / ||b_i||, that i) for coefficient arrays [S, 3, n]."""
+    num = np.linalg.norm((a - b).reshape(a.shape[0], -1), axis=1)
+    den = np.linalg.norm(b.reshape(b.shape[0], -1), axis=1)
+    r = num / den
+    i = int(np.argmax(r))
+    return float(r[i]), i
+
+
 def rel(a, b):
     return float(np.max(np.abs(a - b) / np.abs(b)))

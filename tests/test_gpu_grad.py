@@ -3,7 +3,7 @@
 Gradients of sum_b dcost_b J_b after K sweeps with respect to the waypoints and
 durations; corridor, vmax and rho are held constant.  float64 iterates are
 compared to the oracle's autograd at 1e-8 (norm-wise, relative); float32 ones to
-the float64 GPU gradient at 1e-3.
+the float64 GPU gradient and to the oracle's autograd at 1e-3.
 """
 import numpy as np
 import pytest
@@ -100,6 +100,35 @@ def test_fp32_backward_matches_fp64_config4_subset():
     _, dPg, dTg = gpu_grad(sub, 100, 10, "fp64", [dcost[0], dcost[7]])
     _, dPo, dTo = oracle_grad(sub, 100, [dcost[0], dcost[7]])
     assert nrel(dPg, dPo) < 1e-8 and nrel(dTg, dTo) < 1e-8
+
+
+def test_fp32_backward_matches_oracle_autograd():
+    # float32 iterates, gradients straight against the float64 oracle's autograd on two trajectories
+    # of the differentiation workload (K = 100, a checkpoint every 10 sweeps)
+    w = make_config(4, n_traj=8).subset([2, 5])
+    dcost = [1.0, 0.75]
+    _, dPg, dTg = gpu_grad(w, 100, 10, "fp32", dcost)
+    _, dPo, dTo = oracle_grad(w, 100, dcost)
+    print(f"[grad]   fp32 vs oracle: dP rel {nrel(dPg, dPo):.2e}  dT rel {nrel(dTg, dTo):.2e}", flush=True)
+    assert nrel(dPg, dPo) < 1e-3 and nrel(dTg, dTo) < 1e-3
+
+
+def test_fp32_backward_full_size_sampled():
+    # the full differentiation workload (256 x 128, fp32, K = 100, m = 10) as the bench runs it; the
+    # trajectories are independent, so the gradient rows of eight of them equal the oracle's
+    # autograd on those eight alone
+    w = make_config(4)
+    dcost = np.linspace(0.5, 1.5, w.n_traj)
+    print(f"[grad] fp32 full S={w.n_seg}", flush=True)
+    _, dPg, dTg = gpu_grad(w, 100, 10, "fp32", dcost)
+    picks = [0, 3, 64, 100, 129, 200, 250, 255]
+    sub = w.subset(picks)
+    _, dPo, dTo = oracle_grad(sub, 100, dcost[picks])
+    rows_p = np.concatenate([np.arange(w.seg_offsets[t] + t, w.seg_offsets[t + 1] + t + 1) for t in picks])
+    rows_t = np.concatenate([np.arange(w.seg_offsets[t], w.seg_offsets[t + 1]) for t in picks])
+    eP, eT = nrel(dPg[rows_p], dPo), nrel(dTg[rows_t], dTo)
+    print(f"[grad]   sampled rows: dP rel {eP:.2e}  dT rel {eT:.2e}", flush=True)
+    assert eP < 1e-3 and eT < 1e-3
 
 
 def test_central_differences_fp64():
