@@ -51,7 +51,7 @@ int max_tile(const top::Variant& v) {
   return (v.prec == 0 && v.p == 3 && v.s != 2 * v.p - 1) ? 512 : 256;
 }
 // Handles that keep a tape also run the adjoint kernel on the same tiles: it is built for tiles of up
-// to 256 lanes, and its per-lane LDS column (box and velocity pair adjoints) must fit the device's
+// to top::adjoint_max_tile segments (three lanes each), and its LDS must fit the device's
 // per-workgroup LDS.
 int max_tile(const top::Variant& v, bool taped) {
   if (!taped) return max_tile(v);
@@ -62,7 +62,7 @@ int max_tile(const top::Variant& v, bool taped) {
     if (hipDeviceGetAttribute(&q, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && q > 0) lds = q;
   }
   const size_t rsz = v.prec == 0 ? 4 : 8;
-  int W = std::min(256, max_tile(v));
+  int W = std::min(top::adjoint_max_tile(v.prec), max_tile(v));
   while (W > 64 && top::adjoint_lds_bytes(v, rsz, W) + top::kAdjointStaticLds > (size_t)lds) W -= 64;
   return W;
 }

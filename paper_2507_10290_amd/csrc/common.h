@@ -306,13 +306,19 @@ hipError_t launch_adjoint(const Variant& v, const AdjArgs<R>& a, int n_tiles, hi
 template <typename R>
 hipError_t launch_fill(R* p, int64_t n, R v, hipStream_t st);
 
-// Dynamic LDS of the adjoint kernel: the box and velocity pair adjoints of every lane.
+// The adjoint kernel runs a tile of W segments as 3 W lanes (one per segment and axis), so an axis
+// has at most kMaxAxisWaves waves.  Its largest tile: 128 segments in float32 (384 lanes, two waves
+// per SIMD), 64 in float64 (192 lanes, one wave per SIMD).
+constexpr int kMaxAxisWaves = 4;
+inline int adjoint_max_tile(int prec) { return prec == 0 ? 128 : 64; }
+// Dynamic LDS of the adjoint kernel: the per-axis partial adjoints of the velocity factors (double
+// buffered), then the per-axis parameter adjoints summed at the end.
 inline size_t adjoint_lds_bytes(const Variant& v, size_t rsz, int W) {
-  const int nyg = (v.box ? 6 * kSamples : 0) + (v.vel ? 3 * kSamples : 0);
-  return (size_t)(nyg > 0 ? nyg : 1) * rsz * (size_t)W;
+  const int nf = 2 * 3 * (v.vel ? kSamples : 1) + 6;
+  return (size_t)nf * rsz * (size_t)W;
 }
 // Static LDS of the adjoint kernel (wave-boundary exchange buffers), an upper bound.
-constexpr size_t kAdjointStaticLds = 2 * kMaxWaves * 12 * 5 * sizeof(double);
+constexpr size_t kAdjointStaticLds = 2 * 3 * kMaxAxisWaves * 4 * 5 * sizeof(double);
 
 template <typename R>
 struct InitAdjArgs {
