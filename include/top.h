@@ -187,8 +187,9 @@ top_status top_create_polytope(int32_t n_traj, const int64_t* seg_offsets, const
                                void* workspace, size_t workspace_bytes, hipStream_t stream,
                                top_problem** out);
 
-/* Queue k >= 0 more sweeps (Algorithm 1 loop body: ClosedFormSolve, UpdateConsensus,
- * UpdateResidual, ProjectNonNeg, UpdateDual, and UpdateRho at the checks when check_every > 0).
+/* Queue k >= 0 more sweeps, each one ADMM iteration of Sec. III-D.1 (eqs. QpSubProblem,
+ * DynamicProject, UpdateCloseW, UpdateZ, NonNegativeProject, UpdateV, UpdateU), with the residuals of
+ * Sec. III-D.3 and eq. UpdateRho at the checks when check_every > 0.
  * Trajectories that passed the stopping test are left unchanged.  Asynchronous. */
 top_status top_iterate(top_problem* h, int32_t k);
 

@@ -14,8 +14,13 @@ Sources (Sec. III of the paper):
   ``QpSubProblem``, ``UpdateZ``, ``UpdateU``, ``NonNegativeProject``,
   ``UpdateV``, ``DynamicProject``, ``UpdateCloseW``;
 * stopping residuals: Sec. III-D.3, eqs. ``splitting_primal_residual`` and
-  ``splitting_dual_residual``;
-* the order of the steps inside one iteration: Algorithm 1.
+  ``splitting_dual_residual``.
+
+One iteration is the scaled-form ADMM pass those equations define: minimise
+each segment's augmented Lagrangian over c (with the velocity split's
+projection and dual step right after it, since they need only the new c),
+then the knot averages, the residuals of the new iterate, the corridor slacks,
+and the dual steps that use the new c, z and slacks.
 
 Readings taken where the paper is silent or inconsistent (each is listed with
 its justification in the design notes of the repository):
@@ -188,7 +193,7 @@ def project_ball(x: torch.Tensor, vmax: torch.Tensor) -> torch.Tensor:
 
 
 # ---------------------------------------------------------------------------
-# State and the steps of Algorithm 1.
+# State and the update equations of Sec. III-D.1.
 # ---------------------------------------------------------------------------
 
 @dataclass
@@ -240,7 +245,7 @@ def knot_pair(pr: Problem, z: torch.Tensor) -> torch.Tensor:
 
 
 def init_state(pr: Problem, mats: dict) -> State:
-    """Init of Algorithm 1 (the paper leaves it open; reading stated in the module docstring)."""
+    """The starting iterate (the paper leaves it open; reading stated in the module docstring)."""
     S, n, p = pr.S, pr.n, pr.p
     sc = torch.tensor([float(x) for x in smoothstep_coeffs(p)], dtype=DT)   # [n]
     P0 = pr.P[pr.knot_l]                                   # [S, 3]
@@ -262,22 +267,25 @@ def init_state(pr: Problem, mats: dict) -> State:
     return State(c=c, z=z, u=u, s=s_, v=v, phi=phi, w=w)
 
 
-def closed_form_solve(pr: Problem, mats: dict, chol: torch.Tensor, st: State):
-    """ClosedFormSolve of Algorithm 1: eq. QpSubProblem, then DynamicProject and UpdateCloseW."""
+def qp_subproblem(pr: Problem, chol: torch.Tensor, mats: dict, st: State) -> torch.Tensor:
+    """Eq. QpSubProblem: the minimiser of each segment's augmented Lagrangian over its coefficients,
+    (2Q~ + rho M~^T M~ + rho A^oT A^o + rho sum A^vT A^v) c = rho [M~^T (z~ - u) + A^oT (b - s - v)
+    + sum A^vT (phi - w)], solved with the Cholesky factor of the left-hand matrix."""
     rho = pr.rho[pr.traj][:, None]
     rhs = (mats["Mt"].transpose(1, 2) @ (knot_pair(pr, st.z) - st.u)[:, :, None])[..., 0]
     if st.s is not None:
         rhs = rhs + (mats["Ao"].transpose(1, 2) @ (mats["b"] - st.s - st.v)[:, :, None])[..., 0]
     if st.phi is not None:
         rhs = rhs + torch.einsum("smai,sma->si", mats["Av"], st.phi - st.w)
-    c = torch.cholesky_solve((rho * rhs)[:, :, None], chol)[..., 0]
-    phi = w = None
-    if st.phi is not None:
-        vel = (mats["Av"] @ c[:, None, :, None])[..., 0]
-        x = vel + st.w
-        phi = project_ball(x, pr.vmax[pr.traj][:, None, None])
-        w = st.w + vel - phi
-    return c, phi, w
+    return torch.cholesky_solve((rho * rhs)[:, :, None], chol)[..., 0]
+
+
+def velocity_split(pr: Problem, mats: dict, c: torch.Tensor, w: torch.Tensor):
+    """Eqs. DynamicProject and UpdateCloseW: phi = Proj(A^v c + w) onto the ball |x| <= vmax, then
+    w += A^v c - phi."""
+    vel = (mats["Av"] @ c[:, None, :, None])[..., 0]
+    phi = project_ball(vel + w, pr.vmax[pr.traj][:, None, None])
+    return phi, w + vel - phi
 
 
 def end_derivatives(pr: Problem, c: torch.Tensor):
@@ -295,8 +303,9 @@ def interior(pr: Problem) -> torch.Tensor:
     return torch.nonzero(~pr.last)[:, 0]
 
 
-def update_consensus(pr: Problem, c: torch.Tensor, z: torch.Tensor) -> torch.Tensor:
-    """UpdateConsensus (eq. UpdateZ): z_i = (beta~(T_i) c_i + beta~(0) c_{i+1}) / 2 at interior knots."""
+def knot_average(pr: Problem, c: torch.Tensor, z: torch.Tensor) -> torch.Tensor:
+    """Eq. UpdateZ: z_i = (beta~(T_i) c_i + beta~(0) c_{i+1}) / 2 at interior knots (pinned orders keep
+    their values)."""
     xl, xr = end_derivatives(pr, c)
     i = interior(pr)
     avg = 0.5 * (xr[i] + xl[i + 1])                       # [I, 3, s]
@@ -308,7 +317,7 @@ def update_consensus(pr: Problem, c: torch.Tensor, z: torch.Tensor) -> torch.Ten
 
 
 def residuals(pr: Problem, c: torch.Tensor, z_new: torch.Tensor, z_old: torch.Tensor):
-    """UpdateResidual: squared norms of eqs. splitting_primal_residual / splitting_dual_residual, per trajectory.
+    """Squared norms of eqs. splitting_primal_residual / splitting_dual_residual, per trajectory.
 
     The dual residual is read per segment, rho M~(T_i)^T (z~_i^{k+1} - z~_i^k),
     stacked over segments.
@@ -325,14 +334,14 @@ def residuals(pr: Problem, c: torch.Tensor, z_new: torch.Tensor, z_old: torch.Te
     return rp2, rd2
 
 
-def project_nonneg(mats: dict, c: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
-    """ProjectNonNeg (eq. NonNegativeProject): s = max(0, -(A^o c - b + v))."""
+def slack_projection(mats: dict, c: torch.Tensor, v: torch.Tensor) -> torch.Tensor:
+    """Eq. NonNegativeProject: s = max(0, -(A^o c - b + v))."""
     Ac = (mats["Ao"] @ c[:, :, None])[..., 0]
     return torch.clamp(-(Ac - mats["b"] + v), min=0.0)
 
 
-def update_dual(pr: Problem, mats: dict, c, z_new, u, s_new, v):
-    """UpdateDual: eq. UpdateU  u += M~ c - z~  and eq. UpdateV  v += A^o c + s - b."""
+def scaled_dual_steps(pr: Problem, mats: dict, c, z_new, u, s_new, v):
+    """Eq. UpdateU  u += M~ c - z~  and eq. UpdateV  v += A^o c + s - b."""
     u_new = u + (mats["Mt"] @ c[:, :, None])[..., 0] - knot_pair(pr, z_new)
     v_new = None
     if v is not None:
@@ -358,12 +367,18 @@ class Result:
 
 
 def iterate(pr: Problem, mats: dict, chol: torch.Tensor, st: State):
-    """One pass of Algorithm 1's loop body with fixed rho; returns (new state, rp2, rd2)."""
-    c, phi, w = closed_form_solve(pr, mats, chol, st)
-    z = update_consensus(pr, c, st.z)
+    """One ADMM iteration with fixed rho (Sec. III-D.1); returns (new state, rp2, rd2).
+
+    The coefficient minimisation comes first; everything after it depends on the new c: the
+    velocity split (its projection and dual step), the knot averages, the residuals of the new
+    iterate against the previous knots, the corridor slacks, and the consensus and corridor dual
+    steps, which also use the new knots and slacks."""
+    c = qp_subproblem(pr, chol, mats, st)
+    phi, w = velocity_split(pr, mats, c, st.w) if st.phi is not None else (None, None)
+    z = knot_average(pr, c, st.z)
     rp2, rd2 = residuals(pr, c, z, st.z)
-    s_new = project_nonneg(mats, c, st.v) if st.s is not None else None
-    u, v = update_dual(pr, mats, c, z, st.u, s_new, st.v)
+    s_new = slack_projection(mats, c, st.v) if st.s is not None else None
+    u, v = scaled_dual_steps(pr, mats, c, z, st.u, s_new, st.v)
     return State(c=c, z=z, u=u, s=s_new, v=v, phi=phi, w=w), rp2, rd2
 
 
@@ -375,7 +390,8 @@ def setup(pr: Problem):
 
 
 def run(pr: Problem, K: int, state: Optional[State] = None, setup_out=None) -> Result:
-    """K iterations of Algorithm 1 from Init (or from ``state``)."""
+    """K iterations from the starting iterate (or from ``state``): the iteration of Algorithm 1 with
+    fixed rho and no stopping test."""
     mats, chol = setup_out if setup_out is not None else setup(pr)
     st = state if state is not None else init_state(pr, mats)
     rp2 = rd2 = torch.full((pr.B,), float("nan"), dtype=DT)

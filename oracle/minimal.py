@@ -45,7 +45,7 @@ def iterate(pr: Problem, mats: dict, chol: torch.Tensor, st: MinState) -> MinSta
         pg = project_ball(st.g, pr.vmax[pr.traj][:, None, None])
         rhs = rhs + torch.einsum("smai,sma->si", mats["Av"], 2.0 * pg - st.g)
     c = torch.cholesky_solve((rho * rhs)[:, :, None], chol)[..., 0]
-    z = cadmm.update_consensus(pr, c, st.z)
+    z = cadmm.knot_average(pr, c, st.z)
     u = st.u + (mats["Mt"] @ c[:, :, None])[..., 0] - cadmm.knot_pair(pr, z)
     y = g = None
     if st.y is not None:

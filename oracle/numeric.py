@@ -12,7 +12,8 @@ NumericSolve branch:
   c^{k+1} = argmin_c  c^T Q~ c + rho/2 |M~ c - z~ + u|^2 + rho/2 |A^o c - b + s + v|^2
                       + rho/2 sum_j (g_j(c) + w_j)^2
   w_j^{k+1} = w_j + g_j(c^{k+1})          (like the scaled consensus dual, eq. Consensus_dual_update)
-  then UpdateConsensus, UpdateResidual, ProjectNonNeg and UpdateDual as in ``cadmm``.
+  then the knot averages, residuals, slacks and dual steps as in ``cadmm`` (eqs. UpdateZ,
+  splitting_*_residual, NonNegativeProject, UpdateU, UpdateV).
 
 Readings (the paper names L-BFGS and nothing more):
 * each local minimisation runs exactly ``inner`` L-BFGS iterations from the
@@ -152,7 +153,7 @@ def init_state(pr, mats) -> NumState:
 
 
 def iterate(pr, mats, st: NumState, inner: int):
-    """One pass of Alg. 1's loop body with NumericSolve."""
+    """One iteration with the NumericSolve local minimisation in place of eq. QpSubProblem."""
     c = lbfgs(pr, mats, st, st.base.c, inner)
     w = None
     if st.w is not None:
@@ -160,16 +161,16 @@ def iterate(pr, mats, st: NumState, inner: int):
         vmax = pr.vmax[pr.traj][:, None]
         hp = torch.clamp((vel * vel).sum(2) - vmax * vmax, min=0.0)
         w = st.w + hp * hp
-    z = cadmm.update_consensus(pr, c, st.base.z)
+    z = cadmm.knot_average(pr, c, st.base.z)
     rp2, rd2 = cadmm.residuals(pr, c, z, st.base.z)
-    s_new = cadmm.project_nonneg(mats, c, st.base.v) if st.base.s is not None else None
-    u, v = cadmm.update_dual(pr, mats, c, z, st.base.u, s_new, st.base.v)
+    s_new = cadmm.slack_projection(mats, c, st.base.v) if st.base.s is not None else None
+    u, v = cadmm.scaled_dual_steps(pr, mats, c, z, st.base.u, s_new, st.base.v)
     base = cadmm.State(c=c, z=z, u=u, s=s_new, v=v, phi=None, w=None)
     return NumState(base=base, w=w), rp2, rd2
 
 
 def run(pr, K: int, inner: int = 10) -> cadmm.Result:
-    """K iterations of Alg. 1 with NumericSolve from Init."""
+    """K iterations with NumericSolve from the starting iterate."""
     mats = cadmm.segment_matrices(pr)
     st = init_state(pr, mats)
     rp2 = rd2 = torch.full((pr.B,), float("nan"), dtype=DT)

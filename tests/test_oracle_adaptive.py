@@ -80,7 +80,7 @@ def _unscaled_run(q, rhos):
         vel = (Av @ c[:, None, :, None])[..., 0]
         phi = cadmm.project_ball(vel + om / rho, vmax)
         om = om + rho * (vel - phi)
-        z = cadmm.update_consensus(q, c, z)
+        z = cadmm.knot_average(q, c, z)
         Ac = (Ao @ c[:, :, None])[..., 0]
         s = torch.clamp(-(Ac - bb + nu / rho), min=0.0)
         nu = nu + rho * (Ac + s - bb)

@@ -124,7 +124,7 @@ def test_local_solve_is_stationary_and_matches_lstsq(rho):
     pr = cadmm.problem_from_workload(w)
     mats, chol = cadmm.setup(pr)
     st = _random_state(pr, mats, 3)
-    c, _, _ = cadmm.closed_form_solve(pr, mats, chol, st)
+    c = cadmm.qp_subproblem(pr, chol, mats, st)
     cc = c.clone().requires_grad_(True)
     gL, = torch.autograd.grad(_aug_lagrangian(pr, mats, st, cc), cc)
     c0 = torch.zeros_like(c).requires_grad_(True)
