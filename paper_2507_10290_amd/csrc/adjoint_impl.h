@@ -70,10 +70,12 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
   __shared__ R sh_r[2][3][kMaxAxisWaves][2 * S];   // E1, to the right neighbour: lz, luR
   __shared__ R sh_l[2][3][kMaxAxisWaves][S];       // E1, to the left neighbour: luL
   __shared__ R sh_c[2][3][kMaxAxisWaves][S];       // E2, to the left neighbour: cL
-  // per-axis partial adjoints of the velocity factors [2][3][MV][W], and after them the per-axis
-  // parameter adjoints [3][2][W] of the end
+  // Dynamic LDS: the segment's rho Htilde^-1 and its T-derivative [2][NH][W] (read by the three
+  // lanes of the segment), the per-axis partial adjoints of the velocity factors [2][3][MV][W], and
+  // the per-axis parameter adjoints [3][2][W] of the end.
   extern __shared__ double adj_lds_raw[];
-  R* sh_f = reinterpret_cast<R*>(adj_lds_raw);
+  R* sh_H = reinterpret_cast<R*>(adj_lds_raw);
+  R* sh_f = sh_H + 2 * NH * A.W;
 
   const int W = A.W;
   const int a = threadIdx.x / W;      // axis of this lane
@@ -105,12 +107,15 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
     return;
   }
 
-  R H[NH], Hd[NH];
+  // the matrices go to LDS once (axis 0 lanes: rho Htilde^-1, axis 1 lanes: its T-derivative); the
+  // first step's barrier orders these stores before any read
+  const R* Hsrc = a == 0 ? A.k.Hr : A.Hd;
+  if (a < 2) {
 #pragma unroll
-  for (int h = 0; h < NH; ++h) {
-    H[h] = active ? A.k.Hr[h * ld + seg] : R(0);
-    Hd[h] = active ? A.Hd[h * ld + seg] : R(0);
+    for (int h = 0; h < NH; ++h) sh_H[(a * NH + h) * W + lane] = active ? Hsrc[h * ld + seg] : R(0);
   }
+  auto H = [&](int h) -> R { return sh_H[h * W + lane]; };
+  auto Hd = [&](int h) -> R { return sh_H[(NH + h) * W + lane]; };
   const R iT = active ? A.k.iT[seg] : R(1);
   const R vm = (VEL && active) ? A.k.vmax[seg] : R(1);
   const R lo = (BOX && active) ? A.k.lo[a * ld + seg] : R(0);
@@ -251,7 +256,7 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
     R c[N];
     static_for<0, N>([&](auto i) {
       R acc = R(0);
-      static_for<0, N>([&](auto j) { acc += H[tri(N, i, j)] * r[j]; });
+      static_for<0, N>([&](auto j) { acc += H(tri(N, i, j)) * r[j]; });
       c[i] = acc;
     });
 
@@ -334,8 +339,8 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
     static_for<0, N>([&](auto i) {
       R acc = R(0), hr = R(0);
       static_for<0, N>([&](auto j) {
-        acc += H[tri(N, i, j)] * lc[j];
-        hr += Hd[tri(N, i, j)] * r[j];
+        acc += H(tri(N, i, j)) * lc[j];
+        hr += Hd(tri(N, i, j)) * r[j];
       });
       lr[i] = acc;
       ahd += lc[i] * hr;

@@ -311,10 +311,12 @@ hipError_t launch_fill(R* p, int64_t n, R v, hipStream_t st);
 // per SIMD), 64 in float64 (192 lanes, one wave per SIMD).
 constexpr int kMaxAxisWaves = 4;
 inline int adjoint_max_tile(int prec) { return prec == 0 ? 128 : 64; }
-// Dynamic LDS of the adjoint kernel: the per-axis partial adjoints of the velocity factors (double
-// buffered), then the per-axis parameter adjoints summed at the end.
+// Dynamic LDS of the adjoint kernel: each segment's rho Htilde^-1 and its T-derivative, the per-axis
+// partial adjoints of the velocity factors (double buffered), then the per-axis parameter adjoints
+// summed at the end.
 inline size_t adjoint_lds_bytes(const Variant& v, size_t rsz, int W) {
-  const int nf = 2 * 3 * (v.vel ? kSamples : 1) + 6;
+  const int n = 2 * v.p, nh = n * (n + 1) / 2;
+  const int nf = 2 * nh + 2 * 3 * (v.vel ? kSamples : 1) + 6;
   return (size_t)nf * rsz * (size_t)W;
 }
 // Static LDS of the adjoint kernel (wave-boundary exchange buffers), an upper bound.
