@@ -124,11 +124,16 @@ typedef struct top_options {
      and takes no tape and no residual checks.                                                     */
   int32_t local_solve;
   int32_t lbfgs_iters;       /* L-BFGS iterations per local solve (>= 0; default 10)                 */
+  int32_t vel_norm;          /* the speed bound at the samples: 2 (or 0): the Euclidean ball |v| <= vmax
+                                (Sec. III-C.2); 4: the l4 ball (v_x^4 + v_y^4 + v_z^4)^(1/4) <= vmax, a
+                                convex bound with no closed-form projection, NumericSolve only
+                                (TOP_E_UNSUPPORTED otherwise), as h = ||v||_4 - vmax in g = max{0,h}^2 */
 } top_options;
 
 /* Fill *opt with the defaults: p = 3, s = p, pinned interior, M = 8, FP32, no tape, graph on,
    no checks (check_every = 0), and the paper's rule constants tol = 0.05, mu = 10,
-   tau_incr = tau_decr = 1.1 for when checks are switched on. */
+   tau_incr = tau_decr = 1.1 for when checks are switched on; closed-form local update, Euclidean
+   speed bound. */
 void top_default_options(top_options* opt);
 
 /* Bytes of workspace a problem of n_traj trajectories and n_seg_total segments needs, for

@@ -3,10 +3,13 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The velocity bound is treated as a general convex inequality: with
-h_j(c) = ||A^v(T_ij) c||^2 - vmax^2 and g_j = max{0, h_j}^2 (eq. ``componentwise
+h_j(c) <= 0 a function of the velocity A^v(T_ij) c and g_j = max{0, h_j}^2 (eq. ``componentwise
 maximum``) it becomes the equality g_j(c) = 0, kept in the segment's augmented
 Lagrangian (eq. ``general_constraint_aug``) in scaled form; the box rows keep
-their slack/dual pairs as in the closed form.  One iteration of Alg. 1's
+their slack/dual pairs as in the closed form.  q = 2 is the Euclidean speed
+ball of Sec. III-C.2 with h_j = |v_j|^2 - vmax^2 (which also has the closed-form
+projection); q = 4 is the l4 ball ||v_j||_4 <= vmax with h_j = ||v_j||_4 - vmax,
+a convex bound with no closed-form projection, which only this update handles.  One iteration of Alg. 1's
 NumericSolve branch:
 
   c^{k+1} = argmin_c  c^T Q~ c + rho/2 |M~ c - z~ + u|^2 + rho/2 |A^o c - b + s + v|^2
@@ -47,6 +50,23 @@ class NumState:
     w: Optional[torch.Tensor]       # [S, M] scaled multipliers of g_j = 0
 
 
+def velocity_excess(vel: torch.Tensor, vmax: torch.Tensor, norm: int = 2):
+    """h_j at every sample (vel [S, M, 3]) and dh_j/dv_j.
+
+    q = 2: h = |v|^2 - vmax^2 (the quadratic form of Sec. III-C.2).  q = 4: h = ||v||_4 - vmax, the
+    norm itself (convex, smooth away from v = 0, where h < 0); its fourth power would make the squared
+    hinge an eighth-degree polynomial in c, too steep for the line search from a far start."""
+    if norm == 2:
+        return (vel * vel).sum(2) - vmax * vmax, 2.0 * vel
+    if norm == 4:
+        v2 = vel * vel
+        n4 = torch.sqrt(torch.sqrt((v2 * v2).sum(2)))                    # ||v||_4
+        safe = torch.where(n4 > 0, n4, torch.ones_like(n4))
+        dh = torch.where((n4 > 0)[..., None], vel * v2 / (safe * safe * safe)[..., None], torch.zeros_like(vel))
+        return n4 - vmax, dh
+    raise ValueError("norm must be 2 or 4")
+
+
 def _parts(pr, mats, st: NumState):
     """The fixed data of one local problem per segment."""
     rho = pr.rho[pr.traj][:, None]
@@ -57,8 +77,8 @@ def _parts(pr, mats, st: NumState):
     return rho, zt, bt
 
 
-def objective(pr, mats, st: NumState, c: torch.Tensor):
-    """L_i(c) per segment and its gradient, c [S, 3n]."""
+def objective(pr, mats, st: NumState, c: torch.Tensor, norm: int = 2):
+    """L_i(c) per segment and its gradient, c [S, 3n]; norm q of the velocity bound."""
     rho, zt, bt = _parts(pr, mats, st)
     Qc = (mats["Qt"] @ c[:, :, None])[..., 0]
     rM = (mats["Mt"] @ c[:, :, None])[..., 0] - zt
@@ -71,22 +91,22 @@ def objective(pr, mats, st: NumState, c: torch.Tensor):
     if st.w is not None:
         vel = (mats["Av"] @ c[:, None, :, None])[..., 0]              # [S, M, 3]
         vmax = pr.vmax[pr.traj][:, None]
-        h = (vel * vel).sum(2) - vmax * vmax                          # [S, M]
+        h, dh = velocity_excess(vel, vmax, norm)                      # [S, M], [S, M, 3]
         hp = torch.clamp(h, min=0.0)
         g = hp * hp
         e = g + st.w
         L = L + 0.5 * rho[:, 0] * (e * e).sum(1)
-        # d/dc of rho/2 (g + w)^2 = rho (g + w) 2 max(0, h) 2 A^v^T A^v c
-        coef = rho * e * 4.0 * hp                                     # [S, M]
-        G = G + torch.einsum("sm,smai,sma->si", coef, mats["Av"], vel)
+        # d/dc of rho/2 (g + w)^2 = rho (g + w) 2 max(0, h) A^v^T dh/dv
+        coef = rho * e * 2.0 * hp                                     # [S, M]
+        G = G + torch.einsum("sm,smai,sma->si", coef, mats["Av"], dh)
     return L, G
 
 
-def lbfgs(pr, mats, st: NumState, c0: torch.Tensor, inner: int, mem: int = 5, trials: int = 20):
+def lbfgs(pr, mats, st: NumState, c0: torch.Tensor, inner: int, mem: int = 5, trials: int = 20, norm: int = 2):
     """``inner`` L-BFGS iterations on every segment's L_i from c0 (readings in the module docstring)."""
     S, n3 = c0.shape
     c = c0.clone()
-    L, G = objective(pr, mats, st, c)
+    L, G = objective(pr, mats, st, c, norm)
     Sh = torch.zeros(S, mem, n3, dtype=DT)
     Yh = torch.zeros(S, mem, n3, dtype=DT)
     Rh = torch.zeros(S, mem, dtype=DT)        # 1 / (s^T y); 0 marks an empty slot
@@ -119,14 +139,14 @@ def lbfgs(pr, mats, st: NumState, c0: torch.Tensor, inner: int, mem: int = 5, tr
         done = torch.zeros(S, dtype=torch.bool)
         a = torch.ones(S, dtype=DT)
         for _t in range(trials):
-            Lt, _ = objective(pr, mats, st, c + a[:, None] * d)
+            Lt, _ = objective(pr, mats, st, c + a[:, None] * d, norm)
             ok = (~done) & (Lt <= L + C1 * a * slope)
             step = torch.where(ok, a, step)
             done = done | ok
             a = a * 0.5
         moved = step > 0
         c_new = c + step[:, None] * d
-        L_new, G_new = objective(pr, mats, st, c_new)
+        L_new, G_new = objective(pr, mats, st, c_new, norm)
         s_vec = c_new - c
         y_vec = G_new - G
         sy = (s_vec * y_vec).sum(1)
@@ -152,14 +172,14 @@ def init_state(pr, mats) -> NumState:
     return NumState(base=base, w=w)
 
 
-def iterate(pr, mats, st: NumState, inner: int):
+def iterate(pr, mats, st: NumState, inner: int, norm: int = 2):
     """One iteration with the NumericSolve local minimisation in place of eq. QpSubProblem."""
-    c = lbfgs(pr, mats, st, st.base.c, inner)
+    c = lbfgs(pr, mats, st, st.base.c, inner, norm=norm)
     w = None
     if st.w is not None:
         vel = (mats["Av"] @ c[:, None, :, None])[..., 0]
         vmax = pr.vmax[pr.traj][:, None]
-        hp = torch.clamp((vel * vel).sum(2) - vmax * vmax, min=0.0)
+        hp = torch.clamp(velocity_excess(vel, vmax, norm)[0], min=0.0)
         w = st.w + hp * hp
     z = cadmm.knot_average(pr, c, st.base.z)
     rp2, rd2 = cadmm.residuals(pr, c, z, st.base.z)
@@ -169,12 +189,12 @@ def iterate(pr, mats, st: NumState, inner: int):
     return NumState(base=base, w=w), rp2, rd2
 
 
-def run(pr, K: int, inner: int = 10) -> cadmm.Result:
-    """K iterations with NumericSolve from the starting iterate."""
+def run(pr, K: int, inner: int = 10, norm: int = 2) -> cadmm.Result:
+    """K iterations with NumericSolve from the starting iterate; norm q of the velocity bound."""
     mats = cadmm.segment_matrices(pr)
     st = init_state(pr, mats)
     rp2 = rd2 = torch.full((pr.B,), float("nan"), dtype=DT)
     for _ in range(K):
-        st, rp2, rd2 = iterate(pr, mats, st, inner)
+        st, rp2, rd2 = iterate(pr, mats, st, inner, norm)
     return cadmm.Result(c=st.base.c, J=cadmm.cost(pr, st.base.c), rp=torch.sqrt(rp2), rd=torch.sqrt(rd2),
                         state=st.base, iters=K)

@@ -109,9 +109,9 @@ def optimality_reference(pr: Problem):
     return out, _cost(pr, out)
 
 
-def constrained_reference(pr: Problem, tol: float = 1e-15, maxiter: int = 2000):
+def constrained_reference(pr: Problem, tol: float = 1e-15, maxiter: int = 2000, vel_norm: int = 2):
     """Corridor- (box or polytope) and velocity-constrained optimum of one trajectory by scipy's SLSQP
-    (tiny N only)."""
+    (tiny N only); the speed bound is ||v||_q <= vmax at the samples, q = vel_norm (2 or 4)."""
     assert pr.B == 1
     n, d, S = pr.n, pr.d, pr.S
     Q = _np(cost_gram(pr.T, pr.p, pr.d))
@@ -171,20 +171,23 @@ def constrained_reference(pr: Problem, tol: float = 1e-15, maxiter: int = 2000):
             for j in range(pr.n_samples):
                 D.append((i, _row(1, ts[i, j], d)))
 
+        q = vel_norm
+
         def vfun(x):
             c = unpack(x)
-            return np.array([float(((c[i] @ r) ** 2).sum()) for i, r in D])
+            return np.array([float((np.abs(c[i] @ r) ** q).sum()) for i, r in D])
 
         def vjac(x):
             c = unpack(x)
             J = np.zeros((len(D), nv))
             for k, (i, r) in enumerate(D):
+                v = c[i] @ r
                 g = np.zeros((S, 3, n))
-                g[i] = 2.0 * (c[i] @ r)[:, None] * r[None, :]
+                g[i] = (q * np.abs(v) ** (q - 1) * np.sign(v))[:, None] * r[None, :]
                 J[k] = g.reshape(-1)
             return J
 
-        cons.append(scipy.optimize.NonlinearConstraint(vfun, -np.inf, vm * vm, jac=vjac))
+        cons.append(scipy.optimize.NonlinearConstraint(vfun, -np.inf, vm ** q, jac=vjac))
     # Feasible-ish start: the unconstrained optimum.
     x0, _ = kkt_reference(pr)
     res = scipy.optimize.minimize(f, x0.reshape(-1), jac=grad, method="SLSQP", constraints=cons,

@@ -43,7 +43,7 @@ class TopOptions(ctypes.Structure):
                 ("tile_lanes", ctypes.c_int32), ("halo", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("check_every", ctypes.c_int32), ("adapt_rho", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("mu", ctypes.c_double), ("tau_incr", ctypes.c_double), ("tau_decr", ctypes.c_double),
-                ("local_solve", ctypes.c_int32), ("lbfgs_iters", ctypes.c_int32)]
+                ("local_solve", ctypes.c_int32), ("lbfgs_iters", ctypes.c_int32), ("vel_norm", ctypes.c_int32)]
 
 
 class TopPlanInfo(ctypes.Structure):
@@ -279,8 +279,8 @@ class TopProblem:
                  fix_interior: bool = True, checkpoint_every: int = 0, max_taped_iters: int = 0,
                  tile_lanes: int = 0, halo: int = 0, use_graph: bool = True, check_every: int = 0,
                  adapt_rho: bool = False, tol: float = 0.05, mu: float = 10.0, tau_incr: float = 1.1,
-                 tau_decr: float = 1.1, numeric: bool = False, lbfgs_iters: int = 10, device: str = "cuda:0",
-                 stream=None, library_pool: bool = False):
+                 tau_decr: float = 1.1, numeric: bool = False, lbfgs_iters: int = 10, vel_norm: int = 2,
+                 device: str = "cuda:0", stream=None, library_pool: bool = False):
         """Create the handle.  By default its state lives in a workspace allocated by torch on the
         handle's stream (released with the handle); library_pool=True uses the library's pool."""
         import torch
@@ -305,6 +305,7 @@ class TopProblem:
         o.tol, o.mu, o.tau_incr, o.tau_decr = float(tol), float(mu), float(tau_incr), float(tau_decr)
         o.local_solve = 1 if numeric else 0
         o.lbfgs_iters = int(lbfgs_iters)
+        o.vel_norm = int(vel_norm)
         self.options = o
         self.h = None
         self.workspace = None

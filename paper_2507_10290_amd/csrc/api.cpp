@@ -1035,6 +1035,7 @@ void top_default_options(top_options* opt) {
   opt->tau_decr = 1.1;
   opt->local_solve = 0;
   opt->lbfgs_iters = 10;
+  opt->vel_norm = 2;
 }
 
 const char* top_last_error(void) { return g_err.c_str(); }
@@ -1124,8 +1125,12 @@ static top_status resolve_options(const top_options* opt_in, bool box, bool vel,
   if (opt.checkpoint_every < 0 || (opt.checkpoint_every > 0 && opt.max_taped_iters < 1))
     return fail(TOP_E_INVALID, "checkpoint_every >= 0, and max_taped_iters >= 1 when it is > 0");
   if (opt.local_solve != 0 && opt.local_solve != 1) return fail(TOP_E_INVALID, "local_solve must be 0 or 1");
+  if (opt.vel_norm == 0) opt.vel_norm = 2;
+  if (opt.vel_norm != 2 && opt.vel_norm != 4) return fail(TOP_E_INVALID, "vel_norm must be 2 or 4 (got %d)", opt.vel_norm);
+  if (opt.vel_norm == 4 && opt.local_solve != 1)
+    return fail(TOP_E_UNSUPPORTED, "the l4 speed bound needs NumericSolve (local_solve = 1)");
   top::Variant v{opt.precision == TOP_FP64 ? 1 : 0, opt.order, s, box, vel, polytope ? top::kFaces : 0,
-                 opt.local_solve == 1 ? 1 : 0};
+                 opt.local_solve == 1 ? 1 : 0, opt.vel_norm};
   if (v.num) {
     if (!vel) return fail(TOP_E_UNSUPPORTED, "NumericSolve needs a velocity bound (vmax)");
     if (polytope || s != opt.order || opt.checkpoint_every > 0 || opt.check_every > 0)

@@ -139,6 +139,7 @@ struct Variant {
   int p, s, box, vel;
   int faces = 0;  // kFaces: general polytope corridor (box is then 0)
   int num = 0;    // 1: NumericSolve local update (L-BFGS) instead of the closed form
+  int vn = 2;     // norm of the velocity bound: 2 (Euclidean ball) or 4 (l4 ball, NumericSolve only)
 };
 
 template <typename R>

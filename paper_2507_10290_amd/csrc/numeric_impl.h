@@ -2,9 +2,10 @@
 // Algorithm 1), resident form: same tiles, launch protocol and knot exchange as the closed-form
 // kernel of sweep_impl.h.
 //
-// The velocity bound is a general convex inequality h_s(c) = |v_s|^2 - vmax^2 <= 0 turned into the
-// equality g_s = max{0, h_s}^2 = 0 (eq. componentwise maximum) with a scaled multiplier w_s; the box
-// rows keep their folded slack/dual pairs.  The local update minimises the segment's augmented
+// The velocity bound is a general convex inequality h_s(c) <= 0 turned into the equality
+// g_s = max{0, h_s}^2 = 0 (eq. componentwise maximum) with a scaled multiplier w_s, where h_s is
+// |v_s|^2 - vmax^2 (VN = 2, the Euclidean ball of Sec. III-C.2) or ||v_s||_4 - vmax (VN = 4, the l4
+// ball, which has no closed-form projection); the box rows keep their folded slack/dual pairs.  The local update minimises the segment's augmented
 // Lagrangian (eq. general_constraint_aug, scaled form)
 //   L(c) = c^T Q~ c + rho/2 |M~ c - z~ + u|^2 + rho/2 |A^o c - (b - |y|)|^2 + rho/2 sum_s (g_s + w_s)^2
 // by `inner` L-BFGS iterations (two-loop recursion, memory kLbfgsMem, H0 = gamma I with gamma =
@@ -36,8 +37,28 @@ struct NumLane {
   bool first, last, has_left, has_right, fixpos;
 };
 
+// h of the velocity bound at one sample and dh/dv.
+template <int VN, typename R>
+__device__ __forceinline__ R vel_excess(const R (&v)[3], R vm, R (&dh)[3]) {
+  if constexpr (VN == 2) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dh[a] = R(2) * v[a];
+    return v[0] * v[0] + v[1] * v[1] + v[2] * v[2] - vm * vm;
+  } else {
+    static_assert(VN == 4, "the velocity bound is the 2- or the 4-norm");
+    R v2[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v2[a] = v[a] * v[a];
+    const R n4 = sqrt(sqrt(v2[0] * v2[0] + v2[1] * v2[1] + v2[2] * v2[2]));
+    const R i3 = n4 > R(0) ? R(1) / (n4 * n4 * n4) : R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) dh[a] = v[a] * v2[a] * i3;
+    return n4 - vm;
+  }
+}
+
 // L at the monomial coefficients x (and dL/dx when GRAD).
-template <bool GRAD, typename R, int P, int S, bool BOX>
+template <bool GRAD, int VN, typename R, int P, int S, bool BOX>
 __device__ __forceinline__ R num_objective(const NumLane<R, P, S, BOX>& L, const R (&x)[3][2 * P],
                                            R (&gx)[3][2 * P]) {
   constexpr int N = 2 * P;
@@ -95,24 +116,24 @@ __device__ __forceinline__ R num_objective(const NumLane<R, P, S, BOX>& L, const
       });
     }
   }
-  // velocity: rho/2 (g_s + w_s)^2, g_s = max{0, |v_s|^2 - vmax^2}^2
+  // velocity: rho/2 (g_s + w_s)^2, g_s = max{0, h_s}^2
   static_for<0, M>([&](auto s) {
-    R v[3];
+    R v[3], dh[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       R acc = R(0);
       static_for<1, N>([&](auto j) { acc += R(cvel(s, j)) * ct[a][j]; });
       v[a] = acc * L.iT;
     }
-    const R h = v[0] * v[0] + v[1] * v[1] + v[2] * v[2] - L.vm * L.vm;
+    const R h = vel_excess<VN>(v, L.vm, dh);
     const R hp = h > R(0) ? h : R(0);
     const R e = hp * hp + L.w[s];
     val += hr * e * e;
     if constexpr (GRAD) {
-      const R t = L.rho * e * R(4) * hp * L.iT;
+      const R t = L.rho * e * R(2) * hp * L.iT;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        const R ta = t * v[a];
+        const R ta = t * dh[a];
         static_for<1, N>([&](auto j) { gt[a][j] += ta * R(cvel(s, j)); });
       }
     }
@@ -138,7 +159,7 @@ __device__ __forceinline__ R dot3(const R (&a)[3][N], const R (&b)[3][N]) {
 
 // Local update: `inner` L-BFGS iterations on L from the lane's previous c; returns c~ in ct.
 // hist: this lane's LDS column, element (k) at hist[k * W + lane].
-template <typename R, int P, int S, bool BOX>
+template <int VN, typename R, int P, int S, bool BOX>
 __device__ __forceinline__ void num_local_solve(const NumLane<R, P, S, BOX>& L, int inner, R* hist, int W, int lane,
                                                 R (&ct)[3][2 * P]) {
   constexpr int N = 2 * P;
@@ -153,7 +174,7 @@ __device__ __forceinline__ void num_local_solve(const NumLane<R, P, S, BOX>& L, 
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int j = 0; j < N; ++j) x[a][j] = L.cw[a][j] * L.iTp[j];
-  R f = num_objective<true>(L, x, g);
+  R f = num_objective<true, VN>(L, x, g);
   int head = m - 1, count = 0;
   R gamma = R(1);
   for (int it = 0; it < inner; ++it) {
@@ -217,7 +238,7 @@ __device__ __forceinline__ void num_local_solve(const NumLane<R, P, S, BOX>& L, 
         for (int a = 0; a < 3; ++a)
 #pragma unroll
           for (int j = 0; j < N; ++j) xt[a][j] = x[a][j] + al * d[a][j];
-        const R ft = num_objective<false>(L, xt, dummy);
+        const R ft = num_objective<false, VN>(L, xt, dummy);
         if (ft <= f + R(1e-4) * al * slope) {
           step = al;
           acc = true;
@@ -232,7 +253,7 @@ __device__ __forceinline__ void num_local_solve(const NumLane<R, P, S, BOX>& L, 
       for (int a = 0; a < 3; ++a)
 #pragma unroll
         for (int j = 0; j < N; ++j) xn[a][j] = x[a][j] + step * d[a][j];
-      const R fn = num_objective<true>(L, xn, gn);
+      const R fn = num_objective<true, VN>(L, xn, gn);
       R sy = R(0), yy = R(0);
 #pragma unroll
       for (int a = 0; a < 3; ++a)
@@ -271,24 +292,24 @@ __device__ __forceinline__ void num_local_solve(const NumLane<R, P, S, BOX>& L, 
     for (int j = 0; j < N; ++j) ct[a][j] = x[a][j] * L.Tp[j];
 }
 
-template <bool FINAL, typename R, int P, int S, bool BOX>
+template <bool FINAL, int VN, typename R, int P, int S, bool BOX>
 __device__ __forceinline__ void num_sweep_once(NumLane<R, P, S, BOX>& L, int inner, R* hist, int W, int lane,
                                                R (*xr_sh)[3 * S], R (*xl_sh)[3 * S], int wl, int wid, int nw,
                                                R (&cfin)[3][2 * P], R (&zfin)[3][S]) {
   constexpr int N = 2 * P;
   constexpr int M = kSamples;
   R c[3][N];
-  num_local_solve(L, inner, hist, W, lane, c);
+  num_local_solve<VN>(L, inner, hist, W, lane, c);
   // multipliers of g_s = 0
   static_for<0, M>([&](auto s) {
-    R v[3];
+    R v[3], dh[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       R acc = R(0);
       static_for<1, N>([&](auto j) { acc += R(cvel(s, j)) * c[a][j]; });
       v[a] = acc * L.iT;
     }
-    const R h = v[0] * v[0] + v[1] * v[1] + v[2] * v[2] - L.vm * L.vm;
+    const R h = vel_excess<VN>(v, L.vm, dh);
     const R hp = h > R(0) ? h : R(0);
     L.w[s] += hp * hp;
   });
@@ -324,7 +345,7 @@ inline size_t numeric_lds_bytes(int p, size_t rsz, int W) {
   return (size_t)(2 * kLbfgsMem * 3 * 2 * p + kLbfgsMem) * rsz * (size_t)W;
 }
 
-template <typename R, int P, int S, bool BOX, int LB>
+template <typename R, int P, int S, bool BOX, int VN, int LB>
 __global__ __launch_bounds__(LB) void numeric_sweep_kernel(SweepArgs<R> A) {
   using LT = NumLane<R, P, S, BOX>;
   constexpr int N = LT::N;
@@ -418,9 +439,9 @@ __global__ __launch_bounds__(LB) void numeric_sweep_kernel(SweepArgs<R> A) {
   const int n_plain = A.final_out ? A.iters - 1 : A.iters;
   int it = 0;
   for (; it < n_plain; ++it)
-    num_sweep_once<false>(L, A.inner, hist, W, lane, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
+    num_sweep_once<false, VN>(L, A.inner, hist, W, lane, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
   if (A.final_out && A.iters > 0) {
-    num_sweep_once<true>(L, A.inner, hist, W, lane, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
+    num_sweep_once<true, VN>(L, A.inner, hist, W, lane, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
     if (core) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -464,16 +485,18 @@ hipError_t dispatch_numeric_sweep(const Variant& v, const SweepArgs<R>& a, int n
   if (a.W <= 0 || a.W > 64 || (a.W & 63) != 0 || n_tiles <= 0) return hipErrorInvalidValue;
   dim3 grid(n_tiles), block(a.W);
   const size_t lds = numeric_lds_bytes(v.p, sizeof(R), a.W);
-#define TOP_NUM_CASE(P_, B_)                                                                  \
-  if (v.p == P_ && (v.box != 0) == B_) {                                                    \
-    auto k_ = numeric_sweep_kernel<R, P_, P_, B_, 64>;                                      \
+#define TOP_NUM_CASE(P_, B_, VN_)                                                             \
+  if (v.p == P_ && (v.box != 0) == B_ && v.vn == VN_) {                                     \
+    auto k_ = numeric_sweep_kernel<R, P_, P_, B_, VN_, 64>;                                 \
     hipError_t e_ = hipFuncSetAttribute((const void*)k_, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
     if (e_ != hipSuccess) return e_;                                                        \
     hipLaunchKernelGGL(k_, grid, block, lds, st, a);                                        \
     return hipGetLastError();                                                               \
   }
-  TOP_NUM_CASE(3, true) TOP_NUM_CASE(3, false)
-  TOP_NUM_CASE(4, true) TOP_NUM_CASE(4, false)
+  TOP_NUM_CASE(3, true, 2) TOP_NUM_CASE(3, false, 2)
+  TOP_NUM_CASE(4, true, 2) TOP_NUM_CASE(4, false, 2)
+  TOP_NUM_CASE(3, true, 4) TOP_NUM_CASE(3, false, 4)
+  TOP_NUM_CASE(4, true, 4) TOP_NUM_CASE(4, false, 4)
 #undef TOP_NUM_CASE
   return hipErrorInvalidValue;
 }

@@ -57,14 +57,14 @@ def _oracle_state(pr, mats, st_gpu, box):
     return numeric.NumState(base=base, w=wv)
 
 
-def _jitter_step(pr, mats, ost, inner, rel, seed=7):
+def _jitter_step(pr, mats, ost, inner, rel, seed=7, norm=2):
     """The oracle step from ost and from ost with every state value scaled by 1 + U(-rel, rel)."""
     g = torch.Generator().manual_seed(seed)
     jit = lambda t: None if t is None else t * (1.0 + rel * (2.0 * torch.rand(t.shape, generator=g, dtype=DT) - 1.0))
     b = ost.base
     pst = numeric.NumState(base=replace(b, c=jit(b.c), z=jit(b.z), u=jit(b.u), s=jit(b.s), v=jit(b.v)), w=jit(ost.w))
-    a_, _, _ = numeric.iterate(pr, mats, ost, inner)
-    p_, _, _ = numeric.iterate(pr, mats, pst, inner)
+    a_, _, _ = numeric.iterate(pr, mats, ost, inner, norm)
+    p_, _, _ = numeric.iterate(pr, mats, pst, inner, norm)
     return a_, cadmm.coeffs_by_axis(pr, p_.base.c).numpy()
 
 
@@ -72,10 +72,10 @@ def _rel_per_seg(a, b):
     return max(np.linalg.norm(a[i] - b[i]) / np.linalg.norm(b[i]) for i in range(len(b)))
 
 
-def _check_steps(w, inner, Ks, floor, rel, box, **kw):
+def _check_steps(w, inner, Ks, floor, rel, box, norm=2, **kw):
     pr = cadmm.problem_from_workload(w)
     mats = cadmm.segment_matrices(pr)
-    prob = _problem(w, inner, **kw)
+    prob = _problem(w, inner, vel_norm=norm, **kw)
     done = 0
     worst = 0.0
     for K in Ks:
@@ -84,7 +84,7 @@ def _check_steps(w, inner, Ks, floor, rel, box, **kw):
             done = K
         st = prob.get_state()[:, :pr.S].cpu().numpy().astype(np.float64)
         ost = _oracle_state(pr, mats, st, box)
-        nxt, cj = _jitter_step(pr, mats, ost, inner, rel)
+        nxt, cj = _jitter_step(pr, mats, ost, inner, rel, norm=norm)
         prob.iterate(1)
         done += 1
         c = prob.coeffs().cpu().numpy()
@@ -104,6 +104,37 @@ def test_fp64_numeric_steps_match_oracle(order, box, vmax, inner):
     w = random_walk_batch("num", [4, 6, 3], [21, 22, 23], order=order, box=box, vmax=vmax, rho=[1.0, 2.0, 0.5],
                           precision="fp64")
     _check_steps(w, inner, [0, 3, 8, 14], 1e-10, 1e-14, box)
+
+
+@pytest.mark.parametrize("order,box,vmax,inner", [(3, True, 1.2, 10), (4, False, 1.0, 8)])
+def test_fp64_numeric_l4_bound_steps_match_oracle(order, box, vmax, inner):
+    # the l4 speed bound (no closed-form projection): h = ||v||_4 - vmax in the squared hinge
+    w = random_walk_batch("numl4", [4, 6, 3], [31, 32, 33], order=order, box=box, vmax=vmax, rho=[1.0, 2.0, 0.5],
+                          precision="fp64")
+    _check_steps(w, inner, [0, 3, 8, 14], 1e-10, 1e-14, box, norm=4)
+
+
+def test_fp64_numeric_l4_first_sweeps_match_oracle_runs():
+    w = random_walk_batch("numl4", [4, 6, 3], [31, 32, 33], order=3, vmax=1.2, rho=[1.0, 2.0, 0.5], precision="fp64")
+    pr = cadmm.problem_from_workload(w)
+    mats = cadmm.segment_matrices(pr)
+    for K in (1, 2):
+        prob = _problem(w, 10, vel_norm=4)
+        prob.iterate(K)
+        c = prob.coeffs().cpu().numpy()
+        prob.close()
+        res = numeric.run(pr, K, inner=10, norm=4)
+        co = cadmm.coeffs_by_axis(pr, res.c).numpy()
+        print(f"[numeric] l4 run K={K}: coeff rel {_rel_per_seg(c, co):.2e}", flush=True)
+        assert _rel_per_seg(c, co) <= 1e-8
+    # the bound is active in these sweeps (else this would only repeat the closed-form tests)
+    vel = (mats["Av"] @ res.c[:, None, :, None])[..., 0]
+    assert (numeric.velocity_excess(vel, pr.vmax[pr.traj][:, None], 4)[0] > 0).any()
+
+
+def test_fp32_numeric_l4_steps_close_to_oracle():
+    w = random_walk_batch("numl432", [5, 7], [35, 36], order=3, vmax=1.2, rho=1.0, precision="fp32")
+    _check_steps(w, 10, [0, 3], 1e-4, 1e-6, True, norm=4)
 
 
 def test_fp64_numeric_first_sweeps_match_oracle_runs():
@@ -155,3 +186,5 @@ def test_numeric_option_errors():
         TopProblem.from_workload(w, numeric=True, checkpoint_every=5, max_taped_iters=10)
     with pytest.raises(TopError, match="no checks"):
         TopProblem.from_workload(w, numeric=True, check_every=5)
+    with pytest.raises(TopError, match="l4"):
+        TopProblem.from_workload(w, vel_norm=4)               # the closed form has no l4 projection

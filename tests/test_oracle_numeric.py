@@ -12,7 +12,13 @@
   the cost rises toward the optimum from below (the squared hinge has a zero
   gradient on the boundary, so this approach is slow, as the paper reports for
   the numeric update).
+
+The same local pins cover the l4 speed bound ||v||_4 <= vmax (a convex bound
+with no closed-form projection, h_j = ||v_j||_4 - vmax), plus its excess h_j
+checked against velocities evaluated with numpy polynomials at the sample
+instants.
 """
+import pytest
 import numpy as np
 import scipy.optimize
 import torch
@@ -35,19 +41,55 @@ def _mid_run_state(w, K=5, wscale=0.3, seed=3):
     return pr, mats, st
 
 
-def test_gradient_matches_central_differences():
-    w = random_walk_batch("numgrad", [3], [5], order=3, vmax=1.0, rho=1.5, precision="fp64")
+@pytest.mark.parametrize("norm,vmax,scale", [(2, 1.0, 0.1), (4, 0.7, 0.03)])
+def test_gradient_matches_central_differences(norm, vmax, scale):
+    # (the l4 case keeps the excess moderate: a large objective would drown the differences in rounding)
+    w = random_walk_batch("numgrad", [3], [5], order=3, vmax=vmax, rho=1.5, precision="fp64")
     pr, mats, st = _mid_run_state(w)
-    c = st.base.c + 0.1 * torch.randn(st.base.c.shape, generator=torch.Generator().manual_seed(1), dtype=DT)
-    _, G = numeric.objective(pr, mats, st, c)
+    c = st.base.c + scale * torch.randn(st.base.c.shape, generator=torch.Generator().manual_seed(1), dtype=DT)
+    vel = (mats["Av"] @ c[:, None, :, None])[..., 0]
+    assert (numeric.velocity_excess(vel, pr.vmax[0], norm)[0] > 0).sum() >= 3   # the bound term is active
+    _, G = numeric.objective(pr, mats, st, c, norm)
     h = 1e-6
     for k in [0, 3, 7, 11, 17]:
         e = torch.zeros_like(c)
         e[:, k] = h
-        Lp, _ = numeric.objective(pr, mats, st, c + e)
-        Lm, _ = numeric.objective(pr, mats, st, c - e)
+        Lp, _ = numeric.objective(pr, mats, st, c + e, norm)
+        Lm, _ = numeric.objective(pr, mats, st, c - e, norm)
         fd = (Lp - Lm) / (2 * h)
         assert torch.allclose(fd, G[:, k], rtol=1e-6, atol=1e-6), (k, fd, G[:, k])
+
+
+@pytest.mark.parametrize("norm", [2, 4])
+def test_velocity_excess_matches_numpy_polynomials(norm):
+    # h_j = |v(t_j)|^2 - vmax^2 (q = 2) or ||v(t_j)||_4 - vmax (q = 4), with v from numpy's polynomial
+    # derivative at t_j = j T / (M + 1) and the norm from numpy.linalg.norm
+    w = random_walk_batch("numexc", [3, 2], [21, 22], order=3, vmax=1.3, rho=1.0, precision="fp64")
+    pr = cadmm.problem_from_workload(w)
+    mats = cadmm.segment_matrices(pr)
+    c = torch.randn(pr.S, 3 * pr.n, generator=torch.Generator().manual_seed(4), dtype=DT)
+    vel = (mats["Av"] @ c[:, None, :, None])[..., 0]
+    h, dh = numeric.velocity_excess(vel, pr.vmax[pr.traj][:, None], norm)
+    T, vmax = w.durations, w.vmax
+    cc = c.numpy().reshape(pr.S, 3, pr.n)
+    traj = pr.traj.numpy()
+    for i in range(pr.S):
+        for j in range(pr.n_samples):
+            t = (j + 1) * T[i] / (pr.n_samples + 1)
+            v = np.array([np.polynomial.polynomial.polyval(t, np.polynomial.polynomial.polyder(cc[i, a]))
+                          for a in range(3)])
+            hf = (lambda x: np.linalg.norm(x) ** 2 - vmax[traj[i]] ** 2) if norm == 2 else \
+                 (lambda x: np.linalg.norm(x, ord=4) - vmax[traj[i]])
+            want = hf(v)
+            assert abs(h[i, j].item() - want) <= 1e-12 * (1 + abs(want)), (i, j)
+            # dh/dv by central differences of the same numpy expression
+            for a in range(3):
+                e = np.zeros(3)
+                e[a] = 1e-6
+                fd = (hf(v + e) - hf(v - e)) / 2e-6
+                # rounding of the differenced values: ~1e-16 of |h| over the 2e-6 step
+                tol = 1e-6 * (1 + abs(fd)) + 1e-9 * (1 + abs(want))
+                assert abs(dh[i, j, a].item() - fd) <= tol
 
 
 def test_box_only_local_problem_gives_the_closed_form_solve():
@@ -68,22 +110,23 @@ def test_box_only_runs_match_the_closed_form_iteration():
     assert (a.c - b.c).abs().max().item() < 2e-6 * (1 + b.c.abs().max().item())
 
 
-def test_active_bound_local_minimiser_matches_scipy_bfgs():
+@pytest.mark.parametrize("norm", [2, 4])
+def test_active_bound_local_minimiser_matches_scipy_bfgs(norm):
     w = random_walk_batch("numact", [2], [9], order=3, vmax=0.8, rho=2.0, precision="fp64")
     pr, mats, st = _mid_run_state(w)
-    c = numeric.lbfgs(pr, mats, st, st.base.c, inner=400)
+    c = numeric.lbfgs(pr, mats, st, st.base.c, inner=400, norm=norm)
     for i in range(pr.S):
         def f(x):
             cc = st.base.c.clone()
             cc[i] = torch.tensor(x, dtype=DT)
-            L, G = numeric.objective(pr, mats, st, cc)
+            L, G = numeric.objective(pr, mats, st, cc, norm)
             return L[i].item(), G[i].numpy()
         r = scipy.optimize.minimize(f, st.base.c[i].numpy(), jac=True, method="BFGS",
                                     options={"gtol": 1e-11, "maxiter": 5000})
         assert np.abs(c[i].numpy() - r.x).max() < 1e-6 * (1 + np.abs(r.x).max()), (i, r.message)
     # the velocity term is active at that minimiser (otherwise this pins nothing new)
     vel = (mats["Av"] @ c[:, None, :, None])[..., 0]
-    assert ((vel * vel).sum(2) > pr.vmax[0] ** 2).any()
+    assert (numeric.velocity_excess(vel, pr.vmax[0], norm)[0] > 0).any()
 
 
 def test_numeric_iteration_moves_toward_the_constrained_optimum():
