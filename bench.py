@@ -253,7 +253,7 @@ def septic_leg(w2, d2):
         "segment_updates_per_s": round(w2.n_seg * w2.iters / sec2, 1),
         "sweep_only_segment_updates_per_s": round(w2.n_seg * w2.iters / (kms2 * 1e-3), 1),
         "ms_per_solve": round(sec2 * 1e3, 3), "phases_ms": ph2, "tile_lanes": plan2["tile_lanes"],
-        "halo": plan2["halo"], "launches": l2,
+        "halo": plan2["halo"], "lanes_per_segment": plan2["lane_form"], "n_tiles": plan2["n_tiles"], "launches": l2,
         "alu_frac": round(flops_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters / (kms2 * 1e-3)
                           / PEAK_FP32_NONPACKED, 4),
         "hbm_yardstick_frac": round(bytes_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters

@@ -128,6 +128,12 @@ typedef struct top_options {
                                 (Sec. III-C.2); 4: the l4 ball (v_x^4 + v_y^4 + v_z^4)^(1/4) <= vmax, a
                                 convex bound with no closed-form projection, NumericSolve only
                                 (TOP_E_UNSUPPORTED otherwise), as h = ||v||_4 - vmax in g = max{0,h}^2 */
+  int32_t lane_form;         /* lanes per segment of the sweep: 1, or 3 (one per axis: three times the
+                                waves, for trajectories longer than a tile; tiles of at most 320
+                                segments; closed form with n_cont < 2p-1, no tape, no checks,
+                                TOP_E_UNSUPPORTED otherwise); 0 picks 3 where allowed and some
+                                trajectory is longer than the largest one-lane tile, else 1 (or the
+                                tuned form after top_tune)                                            */
 } top_options;
 
 /* Fill *opt with the defaults: p = 3, s = p, pinned interior, M = 8, FP32, no tape, graph on,
@@ -276,6 +282,7 @@ typedef struct top_plan_info {
   int32_t iters_done;        /* sweeps run since top_create                                 */
   int32_t n_fields;          /* rows of the iterate state (see top_get_state)               */
   int64_t ld;                /* elements per state row, n_seg rounded up to a multiple of 64 */
+  int32_t lane_form;         /* lanes per segment of the sweep launches: 1 or 3                */
 } top_plan_info;
 
 top_status top_get_plan(const top_problem* h, top_plan_info* info);

@@ -142,13 +142,16 @@ std::string shape_key(const top::Variant& v, const std::vector<int64_t>& off) {
   const int64_t S = off.back();
   auto lg = [](int64_t x) { int r = 0; while (x > 1) { x >>= 1; ++r; } return r; };
   char buf[128];
-  snprintf(buf, sizeof buf, "v1:prec%d:p%d:s%d:box%d:vel%d:logS%d:logmax%d", v.prec, v.p, v.s, v.box,
+  snprintf(buf, sizeof buf, "v2:prec%d:p%d:s%d:box%d:vel%d:logS%d:logmax%d", v.prec, v.p, v.s, v.box,
            v.vel, lg(S), lg(mx));
   return buf;
 }
 
+struct TuneChoice {
+  int W = 0, halo = 0, form = 1;   // tile width, halo, lanes per segment
+};
 std::mutex g_tune_mu;
-std::map<std::string, std::pair<int, int>> g_tune;  // shape -> (W, halo)
+std::map<std::string, TuneChoice> g_tune;  // shape class -> tuned plan
 bool g_tune_loaded = false;
 
 void tune_cache_load() {
@@ -159,8 +162,8 @@ void tune_cache_load() {
   FILE* f = std::fopen(path, "r");
   if (f == nullptr) return;
   char key[160];
-  int W, h;
-  while (std::fscanf(f, "%159s %d %d", key, &W, &h) == 3) g_tune[key] = {W, h};
+  int W, h, form;
+  while (std::fscanf(f, "%159s %d %d %d", key, &W, &h, &form) == 4) g_tune[key] = TuneChoice{W, h, form};
   std::fclose(f);
 }
 
@@ -169,7 +172,8 @@ void tune_cache_store() {
   if (path == nullptr) return;
   FILE* f = std::fopen(path, "w");
   if (f == nullptr) return;
-  for (auto& kv : g_tune) std::fprintf(f, "%s %d %d\n", kv.first.c_str(), kv.second.first, kv.second.second);
+  for (auto& kv : g_tune)
+    std::fprintf(f, "%s %d %d %d\n", kv.first.c_str(), kv.second.W, kv.second.halo, kv.second.form);
   std::fclose(f);
 }
 
@@ -522,6 +526,8 @@ struct top_problem {
   bool have_sweep = false;
   bool init_cost_ready = false;  // out[0] holds the Init guess's cost (computed on first request)
   bool explicit_tile = false;
+  bool axis = false;             // sweep launches run one lane per segment and axis
+  bool axis_ok = false;          // the variant and options allow that form
   // tape: slot j holds the state before sweep j * checkpoint_every
   void* tape = nullptr;
   int tape_slots = 0;
@@ -601,6 +607,12 @@ struct top_problem {
     return a;
   }
 
+  // The lane form of launches over plan pl: the handle's, for its own plan (tuning probes pass
+  // candidate plans and set probe_axis).
+  bool probe_axis = false;
+  const Plan* probe_plan = nullptr;
+  bool axis_of(const Plan& pl) const { return &pl == probe_plan ? probe_axis : axis; }
+
   template <typename R>
   top_status launch_one(const Plan& pl, const int32_t* lane_map, const void* in, void* outp, int n, bool fin,
                         hipStream_t st, bool store_frozen, void* rec) {
@@ -617,6 +629,7 @@ struct top_problem {
     }
     hipError_t e = v.num     ? top::launch_numeric_sweep<R>(v, a, pl.n_tiles, st)
                  : v.faces ? top::launch_poly_sweep<R>(v, a, pl.n_tiles, st)
+                 : (axis_of(pl) && rec == nullptr) ? top::launch_sweep_axis<R>(v, a, pl.n_tiles, st)
                            : top::launch_sweep<R>(v, a, pl.n_tiles, st);
     if (e != hipSuccess) return fail(TOP_E_HIP, "sweep launch failed: %s", hipGetErrorString(e));
     return TOP_OK;
@@ -1036,6 +1049,7 @@ void top_default_options(top_options* opt) {
   opt->local_solve = 0;
   opt->lbfgs_iters = 10;
   opt->vel_norm = 2;
+  opt->lane_form = 0;
 }
 
 const char* top_last_error(void) { return g_err.c_str(); }
@@ -1106,6 +1120,11 @@ void top_trim(void) {
   if (have_dev) (void)hipSetDevice(dev0);
 }
 
+// Whether the sweep of this variant and these options can run one lane per segment and axis.
+static bool axis_allowed(const top::Variant& v, const top_options& opt) {
+  return !v.num && !v.faces && v.s != 2 * v.p - 1 && opt.checkpoint_every == 0 && opt.check_every == 0;
+}
+
 // Options after defaults, checked as far as they can be without the trajectory lengths, and the
 // kernel variant they select.  box/vel/polytope say which corridor and bound are given.
 static top_status resolve_options(const top_options* opt_in, bool box, bool vel, bool polytope, top_options* opt_out,
@@ -1139,6 +1158,11 @@ static top_status resolve_options(const top_options* opt_in, bool box, bool vel,
   }
   const bool taped = opt.checkpoint_every > 0;
   if (polytope && taped) return fail(TOP_E_UNSUPPORTED, "a polytope corridor cannot be combined with a tape");
+  if (opt.lane_form != 0 && opt.lane_form != 1 && opt.lane_form != 3)
+    return fail(TOP_E_INVALID, "lane_form must be 0, 1 or 3 (got %d)", opt.lane_form);
+  if (opt.lane_form == 3 && !axis_allowed(v, opt))
+    return fail(TOP_E_UNSUPPORTED, "one lane per axis needs the closed form with n_cont < 2p-1, no polytope, "
+                                   "no tape and no residual checks");
   if (opt.halo < 0) return fail(TOP_E_INVALID, "halo must be >= 0");
   if (opt.check_every < 0) return fail(TOP_E_INVALID, "check_every must be >= 0 (got %d)", opt.check_every);
   if (opt.check_every > 0) {
@@ -1241,24 +1265,33 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
       return fail(TOP_E_UNSUPPORTED, "residual checks support trajectories of at most %lld segments",
                   65535LL * 128);
   }
-  if (opt.tile_lanes != 0 &&
-      (opt.tile_lanes < 64 || opt.tile_lanes > max_tile(v, taped) || opt.tile_lanes % 64 != 0))
-    return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, %d] (got %d)", max_tile(v, taped),
-                opt.tile_lanes);
   if (mem == Mem::kPool) workspace = nullptr, workspace_bytes = 0;
   const std::vector<int64_t> off(seg_offsets, seg_offsets + n_traj + 1);
-  // execution plan: explicit, tuned for this shape class, or the default
-  int W = opt.tile_lanes, halo = opt.halo;
-  if (W == 0) {
+  int64_t longest = 0;
+  for (int b = 0; b < n_traj; ++b) longest = std::max<int64_t>(longest, off[b + 1] - off[b]);
+  // execution plan: explicit, tuned for this shape class, or the default.  Lane form: one lane per
+  // segment and axis where allowed and some trajectory is longer than a one-lane tile.
+  const bool axis_ok = axis_allowed(v, opt);
+  int W = opt.tile_lanes, halo = opt.halo, form = opt.lane_form;
+  if (W == 0 && form == 0) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache_load();
     auto it = g_tune.find(shape_key(v, off));
-    if (it != g_tune.end() && it->second.first <= max_tile(v, taped)) {
-      W = it->second.first;
-      if (halo == 0) halo = it->second.second;
+    if (it != g_tune.end()) {
+      const TuneChoice& t = it->second;
+      const bool valid = t.form == 3 ? (axis_ok && t.W <= top::axis_max_tile(v.prec)) : t.W <= max_tile(v, taped);
+      if (valid) {
+        W = t.W;
+        form = t.form;
+        if (halo == 0) halo = t.halo;
+      }
     }
   }
-  if (W == 0) W = max_tile(v, taped);
+  if (form == 0) form = (axis_ok && longest > max_tile(v, taped)) ? 3 : 1;
+  const int wmax = form == 3 ? top::axis_max_tile(v.prec) : max_tile(v, taped);
+  if (opt.tile_lanes != 0 && (opt.tile_lanes < 64 || opt.tile_lanes > wmax || opt.tile_lanes % 64 != 0))
+    return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, %d] (got %d)", wmax, opt.tile_lanes);
+  if (W == 0) W = wmax;
   if (halo == 0) halo = std::max(1, std::min(32, W / 8));
   if (2 * halo >= W) return fail(TOP_E_INVALID, "halo %d too large for %d-lane tiles", halo, W);
   if (taped && halo < 2) {
@@ -1306,7 +1339,9 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   if (h == nullptr) return fail(TOP_E_NOMEM, "host allocation failed");
   shape_handle(h, opt, v, n_traj, S);
   h->off = off;
-  h->explicit_tile = opt.tile_lanes != 0;
+  h->explicit_tile = opt.tile_lanes != 0 || opt.lane_form != 0;
+  h->axis = form == 3;
+  h->axis_ok = axis_ok;
   for (int b = 0; b < n_traj; ++b) h->max_len = std::max<int64_t>(h->max_len, seg_offsets[b + 1] - seg_offsets[b]);
   h->stream = stream;
   if (workspace != nullptr) {
@@ -1613,6 +1648,7 @@ top_status top_get_plan(const top_problem* h, top_plan_info* info) {
   info->iters_done = h->iters_done;
   info->n_fields = h->nf;
   info->ld = h->ld;
+  info->lane_form = h->axis ? 3 : 1;
   return TOP_OK;
 }
 
@@ -1640,54 +1676,64 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   void* probe_out = h->state[h->cur ^ 1];
   int64_t mx = 0;
   for (int b = 0; b < h->B; ++b) mx = std::max(mx, h->off[b + 1] - h->off[b]);
-  std::vector<std::pair<int, int>> cands;
-  for (int W = 64; W <= max_tile(h->v, h->tape != nullptr); W *= 2) {
-    if (mx <= W) cands.push_back({W, 0});
+  std::vector<TuneChoice> cands;   // (W, halo or 0 when nothing is split, lane form)
+  auto add = [&](int W, int form) {
+    if (mx <= W) cands.push_back({W, 0, form});
     else
       for (int halo : {8, 16, 32})
-        if (4 * halo <= W) cands.push_back({W, halo});
-  }
+        if (4 * halo <= W) cands.push_back({W, halo, form});
+  };
+  for (int W = 64; W <= max_tile(h->v, h->tape != nullptr); W *= 2) add(W, 1);
+  if (h->axis_ok && mx > 64)   // one lane per axis: for tiles that hold parts of long trajectories
+    for (int W = 128; W <= top::axis_max_tile(h->v.prec); W += 64) add(W, 3);
   hipEvent_t e0, e1;
   TOP_HIP(hipEventCreate(&e0));
   TOP_HIP(hipEventCreate(&e1));
   float best = 1e30f;
-  std::pair<int, int> bestc = {h->plan_ref().W, h->plan_ref().halo};
-  for (auto c : cands) {
+  TuneChoice bestc{h->plan_ref().W, h->plan_ref().halo, h->axis ? 3 : 1};
+  top_status s = TOP_OK;
+  for (const TuneChoice& c : cands) {
     std::shared_ptr<PlanEntry> cand;
-    top_status s = get_plan(h->off, c.first, c.second > 0 ? c.second : 1, &cand);
-    if (s != TOP_OK) return s;
+    s = get_plan(h->off, c.W, c.halo > 0 ? c.halo : 1, &cand);
+    if (s != TOP_OK) break;
     const Plan& pl = cand->plan;
+    h->probe_plan = &pl;
+    h->probe_axis = c.form == 3;
     float tbest = 1e30f;
-    for (int rep = 0; rep < 3; ++rep) {
+    for (int rep = 0; rep < 3 && s == TOP_OK; ++rep) {
       TOP_HIP(hipEventRecord(e0, h->stream));
       int remaining = k_probe;
       while (remaining > 0) {
         const int n = pl.halo > 0 ? std::min(remaining, pl.halo) : remaining;
         // probe sweeps read the live state; the iterate is not advanced
         s = h->sweep_launch(pl, cand->dev, h->state[h->cur], probe_out, n, false, h->stream, true);
-        if (s != TOP_OK) return s;
+        if (s != TOP_OK) break;
         remaining -= n;
       }
+      if (s != TOP_OK) break;
       TOP_HIP(hipEventRecord(e1, h->stream));
       TOP_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
       TOP_HIP(hipEventElapsedTime(&ms, e0, e1));
       tbest = std::min(tbest, ms);
     }
+    h->probe_plan = nullptr;
+    if (s != TOP_OK) break;
     if (tbest < best) {
       best = tbest;
-      bestc = {c.first, pl.halo};
+      bestc = {c.W, pl.halo, c.form};
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  top_status s = get_plan(h->off, bestc.first,
-                          bestc.second > 0 ? bestc.second : std::max(1, std::min(32, bestc.first / 8)), &h->pe);
   if (s != TOP_OK) return s;
+  s = get_plan(h->off, bestc.W, bestc.halo > 0 ? bestc.halo : std::max(1, std::min(32, bestc.W / 8)), &h->pe);
+  if (s != TOP_OK) return s;
+  h->axis = bestc.form == 3;
   h->drop_graphs();
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[shape_key(h->v, h->off)] = {h->plan_ref().W, h->plan_ref().halo};
+    g_tune[shape_key(h->v, h->off)] = TuneChoice{h->plan_ref().W, h->plan_ref().halo, bestc.form};
     tune_cache_store();
   }
   return TOP_OK;

@@ -144,6 +144,14 @@ struct Variant {
 
 template <typename R>
 hipError_t launch_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
+// the same sweep with one lane per segment and axis (3 W threads per tile of W <= axis_max_tile
+// segments; closed form with s < 2p - 1, no recording, no stopped trajectories).  Float32 tiles go
+// to 320 segments (960 lanes at four waves per SIMD, 128 VGPRs); float64 ones to 128, so that the
+// doubled registers need no spills.
+constexpr int kAxisTileMax = 320;
+inline int axis_max_tile(int prec) { return prec == 0 ? kAxisTileMax : 128; }
+template <typename R>
+hipError_t launch_sweep_axis(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
 // the same launch for a general polytope corridor (v.faces = kFaces)
 template <typename R>
 hipError_t launch_poly_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);

@@ -59,6 +59,27 @@ struct Lane {
   bool first, last, has_left, has_right, fixpos;
 };
 
+// Consensus and dual update of one knot order of one axis (eqs. UpdateZ, UpdateU), given the
+// segment's own end states xl / xr and its neighbours' (xp: the left neighbour's end state, xn: the
+// right neighbour's start state; ignored without a neighbour).
+template <bool FINAL, int P, typename R>
+__device__ __forceinline__ void knot_update(int o, R xl, R xr, R xp, R xn, bool has_left, bool has_right,
+                                            bool first, bool last, bool fixpos, R& zL, R& zR, R& uL, R& uR,
+                                            R& zfin) {
+  xp = has_left ? xp : xl;
+  xn = has_right ? xn : xr;
+  if constexpr (FINAL) zfin = zR;
+  const bool free_o = (o > 0) || !fixpos;
+  const R zr_new = R(0.5) * (xr + xn);
+  const R zl_new = R(0.5) * (xp + xl);
+  zR = (!last && free_o) ? zr_new : zR;
+  zL = (!first && free_o) ? zl_new : zL;
+  const R du_l = xl - zL;
+  const R du_r = xr - zR;
+  uL += (o < P || !first) ? du_l : R(0);
+  uR += (o < P || !last) ? du_r : R(0);
+}
+
 // Knot consensus and the u update after the local solves (eqs. UpdateZ, UpdateU): neighbours
 // inside the wave by shuffles, across waves through LDS (one barrier).  LT is any lane type with
 // the knot state zL, zR, uL, uR [3][S] and the neighbour flags.
@@ -86,19 +107,108 @@ __device__ __forceinline__ void knot_exchange(LT& L, R (&xL)[3][S], R (&xR)[3][S
       R xn = __shfl_down(xL[a][o], 1);
       if (wl == 0 && wid > 0) xp = xr_sh[wid - 1][a * S + o];
       if (wl == 63 && wid < nw - 1) xn = xl_sh[wid + 1][a * S + o];
-      xp = L.has_left ? xp : xL[a][o];
-      xn = L.has_right ? xn : xR[a][o];
-      if constexpr (FINAL) zfin[a][o] = L.zR[a][o];
-      const bool free_o = (o > 0) || !L.fixpos;
-      const R zr_new = R(0.5) * (xR[a][o] + xn);
-      const R zl_new = R(0.5) * (xp + xL[a][o]);
-      L.zR[a][o] = (!L.last && free_o) ? zr_new : L.zR[a][o];
-      L.zL[a][o] = (!L.first && free_o) ? zl_new : L.zL[a][o];
-      const R du_l = xL[a][o] - L.zL[a][o];
-      const R du_r = xR[a][o] - L.zR[a][o];
-      L.uL[a][o] += (o < P || !L.first) ? du_l : R(0);
-      L.uR[a][o] += (o < P || !L.last) ? du_r : R(0);
+      knot_update<FINAL, P>(o, xL[a][o], xR[a][o], xp, xn, L.has_left, L.has_right, L.first, L.last, L.fixpos,
+                            L.zL[a][o], L.zR[a][o], L.uL[a][o], L.uR[a][o], zfin[a][o]);
     }
+  }
+}
+
+// Velocity projection factors of one sample: Proj(g) = f g with f = min(1, vmax / ||g||); returns
+// q = (2f - 1) / T (right-hand side) and om = 1 - f (the g update).
+template <typename R>
+__device__ __forceinline__ void vel_factors(R g0, R g1, R g2, R vm, R iT, R& q, R& om) {
+  const R n2 = g0 * g0 + g1 * g1 + g2 * g2;
+  const R f = fmin(R(1), vm * inv_sqrt<R>(n2));
+  q = (R(2) * f - R(1)) * iT;
+  om = R(1) - f;
+}
+
+// The local work of one axis of one segment: the right-hand side r~, the local solve
+// c~ = (rho Htilde^-1) r~, the box and velocity pair updates and the end states xL / xR.  H(h) is
+// the packed matrix entry h; q / om are the velocity factors of the samples.
+template <bool FINAL, typename R, int P, int S, bool BOX, bool VEL, typename HF>
+__device__ __forceinline__ void axis_update(const HF& H, R iT, const R (&iTp)[S], R lo, R hi,
+                                            const R (&q)[VEL ? kSamples : 1], const R (&om)[VEL ? kSamples : 1],
+                                            const R (&zL)[S], const R (&zR)[S], const R (&uL)[S], const R (&uR)[S],
+                                            R (&yh)[BOX ? kSamples : 1], R (&yl)[BOX ? kSamples : 1],
+                                            R (&g)[VEL ? kSamples : 1], R (&xL)[S], R (&xR)[S], R (&cfin)[2 * P]) {
+  constexpr int N = 2 * P;
+  constexpr int M = kSamples;
+  R r[N];
+#pragma unroll
+  for (int j = 0; j < N; ++j) r[j] = R(0);
+  static_for<0, S>([&](auto o) {
+    const R wl_ = (zL[o] - uL[o]) * iTp[o];
+    constexpr R kf = R(cfact(o));
+    r[o] += kf * wl_;
+    const R wr_ = (zR[o] - uR[o]) * iTp[o];
+    static_for<o, N>([&](auto j) {
+      constexpr R k = R(cfall(o, j));
+      r[j] += k * wr_;
+    });
+  });
+  if constexpr (BOX) {
+    const R hl = hi + lo;
+    static_for<0, M>([&](auto s) {
+      const R b = hl - fabs(yh[s]) + fabs(yl[s]);
+      static_for<0, N>([&](auto j) {
+        constexpr R k = R(cpos(s, j));
+        r[j] += k * b;
+      });
+    });
+  }
+  if constexpr (VEL) {
+    static_for<0, M>([&](auto s) {
+      const R b = q[s] * g[s];
+      static_for<1, N>([&](auto j) {
+        constexpr R k = R(cvel(s, j));
+        r[j] += k * b;
+      });
+    });
+  }
+  R c[N];
+  static_for<0, N>([&](auto i) {
+    R acc = R(0);
+    static_for<0, N>([&](auto j) { acc += H(tri(N, i, j)) * r[j]; });
+    c[i] = acc;
+  });
+  if constexpr (BOX) {
+    static_for<0, M>([&](auto s) {
+      R pv = R(0);
+      static_for<0, N>([&](auto j) {
+        constexpr R k = R(cpos(s, j));
+        pv += k * c[j];
+      });
+      yh[s] = pv - hi + relu(yh[s]);
+      yl[s] = lo - pv + relu(yl[s]);
+    });
+  }
+  if constexpr (VEL) {
+    R ci[N];                                  // c~ / T: the velocity rows carry 1/T
+#pragma unroll
+    for (int j = 1; j < N; ++j) ci[j] = c[j] * iT;
+    static_for<0, M>([&](auto s) {
+      R vv = R(0);
+      static_for<1, N>([&](auto j) {
+        constexpr R k = R(cvel(s, j));
+        vv += k * ci[j];
+      });
+      g[s] = vv + om[s] * g[s];
+    });
+  }
+  static_for<0, S>([&](auto o) {
+    constexpr R kf = R(cfact(o));
+    xL[o] = kf * c[o] * iTp[o];
+    R acc = R(0);
+    static_for<o, N>([&](auto j) {
+      constexpr R k = R(cfall(o, j));
+      acc += k * c[j];
+    });
+    xR[o] = acc * iTp[o];
+  });
+  if constexpr (FINAL) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) cfin[j] = c[j];
   }
 }
 
@@ -109,20 +219,14 @@ __device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh
                                            R (*xl_sh)[3 * S], int wl, int wid, int nw,
                                            R (&cfin)[3][2 * P], R (&zfin)[3][S]) {
   using LT = Lane<R, P, S, BOX, VEL>;
-  constexpr int N = LT::N;
-  constexpr int M = LT::M;
   constexpr int MV = LT::MV;
 
-  // velocity projection factors: Proj(g) = f g with f = min(1, vmax / ||g||); per sample, shared by
-  // the three axes: q = (2f - 1) / T (right-hand side) and 1 - f (the g update)
+  // velocity projection factors, per sample, shared by the three axes
   R q[MV], om[MV];
 #pragma unroll
   for (int s = 0; s < MV; ++s) {
     if constexpr (VEL) {
-      const R n2 = L.g[0][s] * L.g[0][s] + L.g[1][s] * L.g[1][s] + L.g[2][s] * L.g[2][s];
-      const R f = fmin(R(1), L.vm * inv_sqrt<R>(n2));
-      q[s] = (R(2) * f - R(1)) * L.iT;
-      om[s] = R(1) - f;
+      vel_factors(L.g[0][s], L.g[1][s], L.g[2][s], L.vm, L.iT, q[s], om[s]);
     } else {
       q[s] = R(0);
       om[s] = R(0);
@@ -130,85 +234,11 @@ __device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh
   }
 
   R xL[3][S], xR[3][S];
+  const auto H = [&](int h) { return L.H[h]; };
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    R r[N];
-#pragma unroll
-    for (int j = 0; j < N; ++j) r[j] = R(0);
-    static_for<0, S>([&](auto o) {
-      const R wl_ = (L.zL[a][o] - L.uL[a][o]) * L.iTp[o];
-      constexpr R kf = R(cfact(o));
-      r[o] += kf * wl_;
-      const R wr_ = (L.zR[a][o] - L.uR[a][o]) * L.iTp[o];
-      static_for<o, N>([&](auto j) {
-        constexpr R k = R(cfall(o, j));
-        r[j] += k * wr_;
-      });
-    });
-    if constexpr (BOX) {
-      const R hl = L.hi[a] + L.lo[a];
-      static_for<0, M>([&](auto s) {
-        const R b = hl - fabs(L.yh[a][s]) + fabs(L.yl[a][s]);
-        static_for<0, N>([&](auto j) {
-          constexpr R k = R(cpos(s, j));
-          r[j] += k * b;
-        });
-      });
-    }
-    if constexpr (VEL) {
-      static_for<0, M>([&](auto s) {
-        const R b = q[s] * L.g[a][s];
-        static_for<1, N>([&](auto j) {
-          constexpr R k = R(cvel(s, j));
-          r[j] += k * b;
-        });
-      });
-    }
-    R c[N];
-    static_for<0, N>([&](auto i) {
-      R acc = R(0);
-      static_for<0, N>([&](auto j) { acc += L.H[tri(N, i, j)] * r[j]; });
-      c[i] = acc;
-    });
-    if constexpr (BOX) {
-      static_for<0, M>([&](auto s) {
-        R pv = R(0);
-        static_for<0, N>([&](auto j) {
-          constexpr R k = R(cpos(s, j));
-          pv += k * c[j];
-        });
-        L.yh[a][s] = pv - L.hi[a] + relu(L.yh[a][s]);
-        L.yl[a][s] = L.lo[a] - pv + relu(L.yl[a][s]);
-      });
-    }
-    if constexpr (VEL) {
-      R ci[N];                                  // c~ / T: the velocity rows carry 1/T
-#pragma unroll
-      for (int j = 1; j < N; ++j) ci[j] = c[j] * L.iT;
-      static_for<0, M>([&](auto s) {
-        R vv = R(0);
-        static_for<1, N>([&](auto j) {
-          constexpr R k = R(cvel(s, j));
-          vv += k * ci[j];
-        });
-        L.g[a][s] = vv + om[s] * L.g[a][s];
-      });
-    }
-    static_for<0, S>([&](auto o) {
-      constexpr R kf = R(cfact(o));
-      xL[a][o] = kf * c[o] * L.iTp[o];
-      R acc = R(0);
-      static_for<o, N>([&](auto j) {
-        constexpr R k = R(cfall(o, j));
-        acc += k * c[j];
-      });
-      xR[a][o] = acc * L.iTp[o];
-    });
-    if constexpr (FINAL) {
-#pragma unroll
-      for (int j = 0; j < N; ++j) cfin[a][j] = c[j];
-    }
-  }
+  for (int a = 0; a < 3; ++a)
+    axis_update<FINAL, R, P, S, BOX, VEL>(H, L.iT, L.iTp, L.lo[a], L.hi[a], q, om, L.zL[a], L.zR[a], L.uL[a],
+                                          L.uR[a], L.yh[a], L.yl[a], L.g[a], xL[a], xR[a], cfin[a]);
 
   knot_exchange<FINAL, P, S>(L, xL, xR, xr_sh, xl_sh, wl, wid, nw, zfin);
 }

@@ -237,6 +237,42 @@ def test_tiling_graph_and_split_are_bitwise_invariant():
     assert np.array_equal(c, base)
 
 
+@pytest.mark.parametrize("case", ["config1-fp64", "config1-fp32", "septic-fp32", "septic-fp64", "ragged-fp64"])
+def test_lane_forms_give_the_same_bits(case):
+    # one lane per segment and axis (lane_form 3) runs each axis' arithmetic as the one-lane form
+    # does: coefficients, cost and residuals agree bit for bit, whatever the tiles
+    if case.startswith("config1"):
+        w, K, t1, t3 = make_config(1), 120, {"tile_lanes": 256}, {}
+    elif case.startswith("septic"):
+        w, K, t1, t3 = make_config(2, scale=1 / 64), 70, {"tile_lanes": 128, "halo": 16}, {"halo": 16}
+    else:
+        lens = [1, 2, 63, 64, 65, 1, 128, 129, 300, 7]
+        w = random_walk_batch("ragged", lens, list(range(100, 100 + len(lens))), order=3,
+                              rho=[0.5, 1.0, 2.0, 1.0, 0.5, 2.0, 1.0, 1.0, 2.0, 0.5], precision="fp64")
+        K, t1, t3 = 60, {"tile_lanes": 128, "halo": 12}, {"tile_lanes": 64, "halo": 12}
+    prec = case.split("-")[1]
+    print(f"[parity] lane forms {case} S={w.n_seg} K={K}", flush=True)
+    one = run_gpu(w, K, prec, lane_form=1, **t1)
+    three = run_gpu(w, K, prec, lane_form=3, **t3)
+    for x, y in zip(one, three):
+        assert np.isfinite(x).all() and np.array_equal(x, y)
+    if prec == "fp64":
+        co, Jo, _, _ = run_oracle(w, K)
+        assert per_traj_rel(w, three[0], co) <= 1e-10 and rel(three[1], Jo) <= 1e-10
+
+
+def test_default_plan_of_long_trajectories_is_one_lane_per_axis():
+    from paper_2507_10290_amd import TopProblem
+    for w, prec in ((make_config(2, scale=1 / 16), "fp32"), (make_config(1), "fp64"), (make_config(3, n_traj=8), "fp32")):
+        prob = TopProblem.from_workload(w, precision=prec)
+        plan = prob.plan()
+        prob.close()
+        longest = int(w.traj_lengths().max())
+        print(f"[parity] {w.name} {prec} longest {longest}: {plan}", flush=True)
+        expect = 3 if longest > (512 if (prec == "fp32" and w.order == 3) else 256) else 1
+        assert plan["lane_form"] == expect
+
+
 def test_graph_replays_match_eager_launches():
     # equal iterate(k) calls are captured on their second appearance and replayed afterwards; every
     # step is compared with a handle that never uses graphs, with host synchronisation between them
