@@ -36,11 +36,12 @@ struct AxisLane {
   bool first, last, has_left, has_right, fixpos;
 };
 
-// Dynamic LDS: the tile's rho Htilde^-1 [NH][W], then the split values of the three axes, double
-// buffered by sweep parity [2][3][MV][W].
-inline size_t sweep_axis_lds_bytes(int p, bool vel, size_t rsz, int W) {
+// Dynamic LDS: the tile's rho Htilde^-1 [NH][TS], then the split values of the three axes, double
+// buffered by sweep parity [2][3][MV][TS], with the row stride TS the instance's largest tile (a
+// compile-time stride turns every LDS address into a constant offset from the lane's own).
+inline size_t sweep_axis_lds_bytes(int p, bool vel, size_t rsz, int TS) {
   const int n = 2 * p, nh = n * (n + 1) / 2;
-  return (size_t)(nh + 2 * 3 * (vel ? kSamples : 1)) * rsz * (size_t)W;
+  return (size_t)(nh + 2 * 3 * (vel ? kSamples : 1)) * rsz * (size_t)TS;
 }
 
 template <typename R, int P, int S, bool BOX, bool VEL, int LB>
@@ -53,12 +54,13 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
   constexpr int F_ZR = 0, F_UL = 3 * S, F_UR = 6 * S, F_YH = 9 * S;
   constexpr int F_YL = F_YH + (BOX ? 3 * M : 0);
   constexpr int F_G = 9 * S + (BOX ? 6 * M : 0);
+  constexpr int TS = LB / 3;   // LDS row stride: the largest tile
 
   __shared__ R xr_sh[2][3][kAxisMaxWaves][S];   // end states to the right neighbour (wave edges)
   __shared__ R xl_sh[2][3][kAxisMaxWaves][S];   // start states to the left neighbour
   extern __shared__ double axis_lds_raw[];
-  R* sh_H = reinterpret_cast<R*>(axis_lds_raw);
-  R* sh_g = sh_H + NH * A.W;
+  R* sh_H = reinterpret_cast<R*>(axis_lds_raw) + threadIdx.x % A.W;   // this lane's column
+  R* sh_g = sh_H + NH * TS;
 
   const int W = A.W;
   const int a = threadIdx.x / W;          // axis of this lane
@@ -71,10 +73,10 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
   const int64_t seg = active ? (int64_t)(ent & kSegMask) : 0;
   const uint8_t fl = active ? A.k.flags[seg] : (uint8_t)(kFirst | kLast);
   const int wl = lane & 63, wid = lane >> 6, nw = W >> 6;
-  auto G = [&](int buf, int ax, int s) -> R& { return sh_g[((buf * 3 + ax) * MV + s) * W + lane]; };
+  auto G = [&](int buf, int ax, int s) -> R& { return sh_g[((buf * 3 + ax) * MV + s) * TS]; };
 
   // the tile's matrices into LDS (the three lanes of a segment share the loads)
-  for (int h = a; h < NH; h += 3) sh_H[h * W + lane] = active ? A.k.Hr[h * ld + seg] : R(0);
+  for (int h = a; h < NH; h += 3) sh_H[h * TS] = active ? A.k.Hr[h * ld + seg] : R(0);
   if (__ballot(active) == 0) {            // a wave without segments keeps the barrier count
     __syncthreads();
     for (int it = 0; it < A.iters; ++it) __syncthreads();
@@ -130,7 +132,7 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
   for (int s = 0; s < MV; ++s) L.g[s] = a == 0 ? gall[0][s] : (a == 1 ? gall[1][s] : gall[2][s]);
   __syncthreads();   // the matrices are in LDS
 
-  const auto H = [&](int h) { return sh_H[h * W + lane]; };
+  const auto H = [&](int h) { return sh_H[h * TS]; };
   R cfin[N], zfin[S];
   int buf = 0;
   // One sweep; with FIN (the launch's last sweep when it writes outputs) the local solve and the end
@@ -221,7 +223,7 @@ hipError_t dispatch_sweep_axis(const Variant& v, const SweepArgs<R>& a, int n_ti
   if (v.num || v.faces || v.s == 2 * v.p - 1 || a.rec != nullptr || a.done != nullptr) return hipErrorInvalidValue;
   if (a.W <= 0 || a.W > LBT || (a.W & 63) != 0 || n_tiles <= 0) return hipErrorInvalidValue;
   dim3 grid(n_tiles), block(3 * a.W);
-  const size_t lds = sweep_axis_lds_bytes(v.p, v.vel != 0, sizeof(R), a.W);
+  const size_t lds = sweep_axis_lds_bytes(v.p, v.vel != 0, sizeof(R), LBT);
 #define TOP_AXIS_CASE(P_, S_, B_, V_)                                                             \
   if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_) {                      \
     auto k_ = sweep_axis_kernel<R, P_, S_, B_, V_, 3 * LBT>;                                     \
