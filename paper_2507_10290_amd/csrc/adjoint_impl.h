@@ -74,8 +74,11 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
   // lanes of the segment), the per-axis partial adjoints of the velocity factors [2][3][MV][W], and
   // the per-axis parameter adjoints [3][2][W] of the end.
   extern __shared__ double adj_lds_raw[];
-  R* sh_H = reinterpret_cast<R*>(adj_lds_raw);
-  R* sh_f = sh_H + 2 * NH * A.W;
+  // rows strided by the instance's largest tile TS (a compile-time stride: every LDS address is an
+  // immediate offset from the lane's own column)
+  constexpr int TS = LB / 3;
+  R* sh_H = reinterpret_cast<R*>(adj_lds_raw) + threadIdx.x % A.W;
+  R* sh_f = sh_H + 2 * NH * TS;
 
   const int W = A.W;
   const int a = threadIdx.x / W;      // axis of this lane
@@ -99,8 +102,8 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
   }
   const bool fixpos = A.fixpos != 0;
   const int wl = lane & 63, wid = lane >> 6, nw = W >> 6;
-  auto SF = [&](int buf, int ax, int s) -> R& { return sh_f[((buf * 3 + ax) * MV + s) * W + lane]; };
-  auto SA = [&](int ax, int q) -> R& { return sh_f[(2 * 3 * MV + ax * 2 + q) * W + lane]; };
+  auto SF = [&](int buf, int ax, int s) -> R& { return sh_f[((buf * 3 + ax) * MV + s) * TS]; };
+  auto SA = [&](int ax, int q) -> R& { return sh_f[(2 * 3 * MV + ax * 2 + q) * TS]; };
   if (__ballot(active) == 0) {
     for (int t = 0; t < A.steps; ++t) { __syncthreads(); __syncthreads(); }
     __syncthreads();
@@ -112,10 +115,10 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
   const R* Hsrc = a == 0 ? A.k.Hr : A.Hd;
   if (a < 2) {
 #pragma unroll
-    for (int h = 0; h < NH; ++h) sh_H[(a * NH + h) * W + lane] = active ? Hsrc[h * ld + seg] : R(0);
+    for (int h = 0; h < NH; ++h) sh_H[(a * NH + h) * TS] = active ? Hsrc[h * ld + seg] : R(0);
   }
-  auto H = [&](int h) -> R { return sh_H[h * W + lane]; };
-  auto Hd = [&](int h) -> R { return sh_H[(NH + h) * W + lane]; };
+  auto H = [&](int h) -> R { return sh_H[h * TS]; };
+  auto Hd = [&](int h) -> R { return sh_H[(NH + h) * TS]; };
   const R iT = active ? A.k.iT[seg] : R(1);
   const R vm = (VEL && active) ? A.k.vmax[seg] : R(1);
   const R lo = (BOX && active) ? A.k.lo[a * ld + seg] : R(0);
@@ -456,7 +459,7 @@ template <typename R, int LB>
 hipError_t dispatch_adjoint(const Variant& v, const AdjArgs<R>& a, int n_tiles, hipStream_t st) {
   if (a.W <= 0 || a.W > LB || (a.W & 63) != 0 || n_tiles <= 0 || a.steps <= 0) return hipErrorInvalidValue;
   dim3 grid(n_tiles), block(3 * a.W);
-  const size_t lds = adjoint_lds_bytes(v, sizeof(R), a.W);
+  const size_t lds = adjoint_lds_bytes(v, sizeof(R), LB);
 #define TOP_ADJ_CASE(P_, S_, B_, V_)                                                              \
   if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_) {                      \
     hipError_t e_ = hipFuncSetAttribute((const void*)(adjoint_kernel<R, P_, S_, B_, V_, 3 * LB>), \

@@ -62,9 +62,9 @@ int max_tile(const top::Variant& v, bool taped) {
     if (hipDeviceGetAttribute(&q, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && q > 0) lds = q;
   }
   const size_t rsz = v.prec == 0 ? 4 : 8;
-  int W = std::min(top::adjoint_max_tile(v.prec), max_tile(v));
-  while (W > 64 && top::adjoint_lds_bytes(v, rsz, W) + top::kAdjointStaticLds > (size_t)lds) W -= 64;
-  return W;
+  // the kernel's LDS rows are strided by its largest tile, whatever the launch's W
+  if (top::adjoint_lds_bytes(v, rsz, top::adjoint_max_tile(v.prec)) + top::kAdjointStaticLds > (size_t)lds) return 0;
+  return std::min(top::adjoint_max_tile(v.prec), max_tile(v));
 }
 
 struct Plan {
@@ -1289,6 +1289,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   }
   if (form == 0) form = (axis_ok && longest > max_tile(v, taped)) ? 3 : 1;
   const int wmax = form == 3 ? top::axis_max_tile(v.prec) : max_tile(v, taped);
+  if (wmax < 64) return fail(TOP_E_UNSUPPORTED, "the device's per-workgroup LDS is too small for the adjoint kernel");
   if (opt.tile_lanes != 0 && (opt.tile_lanes < 64 || opt.tile_lanes > wmax || opt.tile_lanes % 64 != 0))
     return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, %d] (got %d)", wmax, opt.tile_lanes);
   if (W == 0) W = wmax;

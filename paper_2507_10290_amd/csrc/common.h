@@ -322,7 +322,7 @@ constexpr int kMaxAxisWaves = 4;
 inline int adjoint_max_tile(int prec) { return prec == 0 ? 128 : 64; }
 // Dynamic LDS of the adjoint kernel: each segment's rho Htilde^-1 and its T-derivative, the per-axis
 // partial adjoints of the velocity factors (double buffered), then the per-axis parameter adjoints
-// summed at the end.
+// summed at the end; rows of W values (the kernel strides them by its largest tile).
 inline size_t adjoint_lds_bytes(const Variant& v, size_t rsz, int W) {
   const int n = 2 * v.p, nh = n * (n + 1) / 2;
   const int nf = 2 * nh + 2 * 3 * (v.vel ? kSamples : 1) + 6;

@@ -261,6 +261,24 @@ def test_lane_forms_give_the_same_bits(case):
         assert per_traj_rel(w, three[0], co) <= 1e-10 and rel(three[1], Jo) <= 1e-10
 
 
+def test_lane_per_axis_graph_replays_match_eager_launches():
+    # the lane-per-axis launches of a split trajectory, captured into a graph on their second
+    # appearance and replayed, against a handle that never uses graphs
+    from paper_2507_10290_amd import TopProblem
+    w = make_config(2, scale=1 / 32)
+    g = TopProblem.from_workload(w, precision="fp32", use_graph=True)
+    e = TopProblem.from_workload(w, precision="fp32", use_graph=False)
+    assert g.plan()["lane_form"] == 3 and g.plan()["halo"] > 0
+    for step in range(5):
+        g.iterate(40)
+        e.iterate(40)
+        torch.cuda.synchronize()
+        assert torch.equal(g.coeffs(), e.coeffs()), step
+        assert torch.equal(g.cost(), e.cost()), step
+    g.close()
+    e.close()
+
+
 def test_default_plan_of_long_trajectories_is_one_lane_per_axis():
     from paper_2507_10290_amd import TopProblem
     for w, prec in ((make_config(2, scale=1 / 16), "fp32"), (make_config(1), "fp64"), (make_config(3, n_traj=8), "fp32")):
