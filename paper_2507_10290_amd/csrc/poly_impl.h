@@ -34,8 +34,9 @@ struct PolyLane {
   bool first, last, has_left, has_right, fixpos;
 };
 
-template <bool FINAL, bool HL, typename R, int P, int S, bool VEL>
-__device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, const R* Hs, int W, int lane,
+// Hs: this lane's LDS column of the matrices (HL), rows TS apart.
+template <bool FINAL, bool HL, int TS, typename R, int P, int S, bool VEL>
+__device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, const R* Hs,
                                                 R (*xr_sh)[3 * S], R (*xl_sh)[3 * S], int wl, int wid, int nw,
                                                 R (&cfin)[3][2 * P], R (&zfin)[3][S]) {
   using LT = PolyLane<R, P, S, VEL>;
@@ -118,7 +119,7 @@ __device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, const
         R acc = R(0);
         static_for<0, N>([&](auto j) {
           constexpr int h = tri(N, i, j);
-          const R hv = HL ? Hs[(ax * LT::NH + h) * W + lane] : L.H[ax][h];
+          const R hv = HL ? Hs[(ax * LT::NH + h) * TS] : L.H[ax][h];
           acc += hv * rr[ax][j];
         });
         cr[ax][i] = acc;
@@ -220,14 +221,16 @@ __global__ __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   L.fixpos = A.fixpos != 0;
 
   // ---- per-segment constants
+  // matrices in LDS: rows strided by the largest tile LB (a compile-time stride: every LDS address
+  // is an immediate offset from the lane's own column)
   extern __shared__ double poly_lds_raw[];
-  R* Hs = reinterpret_cast<R*>(poly_lds_raw);
+  R* Hs = reinterpret_cast<R*>(poly_lds_raw) + lane;
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax)
 #pragma unroll
     for (int h = 0; h < NH; ++h) {
       const R v = active ? A.k.Hr[(ax * NH + h) * ld + seg] : R(0);
-      if constexpr (HL) Hs[(ax * NH + h) * W + lane] = v;
+      if constexpr (HL) Hs[(ax * NH + h) * LB] = v;
       else L.H[ax][h] = v;
     }
 #pragma unroll
@@ -276,9 +279,9 @@ __global__ __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(WPE))) void 
   const int n_plain = A.final_out ? A.iters - 1 : A.iters;
   int it = 0;
   for (; it < n_plain; ++it)
-    poly_sweep_once<false, HL>(L, Hs, W, lane, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
+    poly_sweep_once<false, HL, LB>(L, Hs, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
   if (A.final_out && A.iters > 0) {
-    poly_sweep_once<true, HL>(L, Hs, W, lane, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
+    poly_sweep_once<true, HL, LB>(L, Hs, xr_sh[it & 1], xl_sh[it & 1], wl, wid, nw, cfin, zfin);
     if (core && !frozen) {
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -326,7 +329,7 @@ hipError_t dispatch_poly_sweep(const Variant& v, const SweepArgs<R>& a, int n_ti
     constexpr bool HL_ = hl3 && P_ == 3;                                                    \
     constexpr int NH_ = 2 * P_ * (2 * P_ + 1) / 2;                                          \
     if (a.W > (HL_ ? 512 : 256)) return hipErrorInvalidValue;                               \
-    const size_t lds = HL_ ? (size_t)3 * NH_ * a.W * sizeof(R) : 0;                         \
+    const size_t lds = HL_ ? (size_t)3 * NH_ * 512 * sizeof(R) : 0;                         \
     auto k_ = poly_sweep_kernel<R, P_, S_, V_, HL_ ? 512 : 256, HL_, HL_ ? 2 : 1>;          \
     if (HL_) {                                                                              \
       hipError_t e_ = hipFuncSetAttribute((const void*)k_, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
