@@ -178,7 +178,7 @@ __device__ __forceinline__ void poly_sweep_once(PolyLane<R, P, S, VEL>& L, const
       for (int j = 0; j < N; ++j) cfin[a][j] = c[a][j];
     }
   }
-  knot_exchange<FINAL, P, S>(L, xL, xR, xr_sh, xl_sh, wl, wid, nw, zfin);
+  knot_exchange_by_order<FINAL, P, S>(L, xL, xR, xr_sh, xl_sh, wl, wid, nw, zfin);
 }
 
 template <typename R, int P, int S, bool VEL, int LB, bool HL, int WPE>

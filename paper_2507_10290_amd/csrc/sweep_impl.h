@@ -59,6 +59,165 @@ struct Lane {
   bool first, last, has_left, has_right, fixpos;
 };
 
+// Knot consensus and the u update after the local solves (eqs. UpdateZ, UpdateU): neighbours
+// inside the wave by shuffles, across waves through LDS (one barrier).  LT is any lane type with
+// the knot state zL, zR, uL, uR [3][S] and the neighbour flags.
+template <bool FINAL, int P, int S, typename LT, typename R>
+__device__ __forceinline__ void knot_exchange(LT& L, R (&xL)[3][S], R (&xR)[3][S], R (*xr_sh)[3 * S],
+                                              R (*xl_sh)[3 * S], int wl, int wid, int nw, R (&zfin)[3][S]) {
+  if (wl == 63) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = 0; o < S; ++o) xr_sh[wid][a * S + o] = xR[a][o];
+  }
+  if (wl == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int o = 0; o < S; ++o) xl_sh[wid][a * S + o] = xL[a][o];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+#pragma unroll
+    for (int o = 0; o < S; ++o) {
+      R xp = __shfl_up(xR[a][o], 1);
+      R xn = __shfl_down(xL[a][o], 1);
+      if (wl == 0 && wid > 0) xp = xr_sh[wid - 1][a * S + o];
+      if (wl == 63 && wid < nw - 1) xn = xl_sh[wid + 1][a * S + o];
+      xp = L.has_left ? xp : xL[a][o];
+      xn = L.has_right ? xn : xR[a][o];
+      if constexpr (FINAL) zfin[a][o] = L.zR[a][o];
+      const bool free_o = (o > 0) || !L.fixpos;
+      const R zr_new = R(0.5) * (xR[a][o] + xn);
+      const R zl_new = R(0.5) * (xp + xL[a][o]);
+      L.zR[a][o] = (!L.last && free_o) ? zr_new : L.zR[a][o];
+      L.zL[a][o] = (!L.first && free_o) ? zl_new : L.zL[a][o];
+      const R du_l = xL[a][o] - L.zL[a][o];
+      const R du_r = xR[a][o] - L.zR[a][o];
+      L.uL[a][o] += (o < P || !L.first) ? du_l : R(0);
+      L.uR[a][o] += (o < P || !L.last) ? du_r : R(0);
+    }
+  }
+}
+
+// One sweep of one lane's segment.  With FINAL the local solve c~ and the end knot before its
+// update are returned through cfin / zfin.
+template <bool FINAL, typename R, int P, int S, bool BOX, bool VEL>
+__device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh)[3 * S],
+                                           R (*xl_sh)[3 * S], int wl, int wid, int nw,
+                                           R (&cfin)[3][2 * P], R (&zfin)[3][S]) {
+  using LT = Lane<R, P, S, BOX, VEL>;
+  constexpr int N = LT::N;
+  constexpr int M = LT::M;
+  constexpr int MV = LT::MV;
+
+  // velocity projection factors: Proj(g) = f g with f = min(1, vmax / ||g||); per sample, shared by
+  // the three axes: q = (2f - 1) / T (right-hand side) and 1 - f (the g update)
+  R q[MV], om[MV];
+#pragma unroll
+  for (int s = 0; s < MV; ++s) {
+    if constexpr (VEL) {
+      const R n2 = L.g[0][s] * L.g[0][s] + L.g[1][s] * L.g[1][s] + L.g[2][s] * L.g[2][s];
+      const R f = fmin(R(1), L.vm * inv_sqrt<R>(n2));
+      q[s] = (R(2) * f - R(1)) * L.iT;
+      om[s] = R(1) - f;
+    } else {
+      q[s] = R(0);
+      om[s] = R(0);
+    }
+  }
+
+  R xL[3][S], xR[3][S];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    R r[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) r[j] = R(0);
+    static_for<0, S>([&](auto o) {
+      const R wl_ = (L.zL[a][o] - L.uL[a][o]) * L.iTp[o];
+      constexpr R kf = R(cfact(o));
+      r[o] += kf * wl_;
+      const R wr_ = (L.zR[a][o] - L.uR[a][o]) * L.iTp[o];
+      static_for<o, N>([&](auto j) {
+        constexpr R k = R(cfall(o, j));
+        r[j] += k * wr_;
+      });
+    });
+    if constexpr (BOX) {
+      const R hl = L.hi[a] + L.lo[a];
+      static_for<0, M>([&](auto s) {
+        const R b = hl - fabs(L.yh[a][s]) + fabs(L.yl[a][s]);
+        static_for<0, N>([&](auto j) {
+          constexpr R k = R(cpos(s, j));
+          r[j] += k * b;
+        });
+      });
+    }
+    if constexpr (VEL) {
+      static_for<0, M>([&](auto s) {
+        const R b = q[s] * L.g[a][s];
+        static_for<1, N>([&](auto j) {
+          constexpr R k = R(cvel(s, j));
+          r[j] += k * b;
+        });
+      });
+    }
+    R c[N];
+    static_for<0, N>([&](auto i) {
+      R acc = R(0);
+      static_for<0, N>([&](auto j) { acc += L.H[tri(N, i, j)] * r[j]; });
+      c[i] = acc;
+    });
+    if constexpr (BOX) {
+      static_for<0, M>([&](auto s) {
+        R pv = R(0);
+        static_for<0, N>([&](auto j) {
+          constexpr R k = R(cpos(s, j));
+          pv += k * c[j];
+        });
+        L.yh[a][s] = pv - L.hi[a] + relu(L.yh[a][s]);
+        L.yl[a][s] = L.lo[a] - pv + relu(L.yl[a][s]);
+      });
+    }
+    if constexpr (VEL) {
+      R ci[N];                                  // c~ / T: the velocity rows carry 1/T
+#pragma unroll
+      for (int j = 1; j < N; ++j) ci[j] = c[j] * L.iT;
+      static_for<0, M>([&](auto s) {
+        R vv = R(0);
+        static_for<1, N>([&](auto j) {
+          constexpr R k = R(cvel(s, j));
+          vv += k * ci[j];
+        });
+        L.g[a][s] = vv + om[s] * L.g[a][s];
+      });
+    }
+    static_for<0, S>([&](auto o) {
+      constexpr R kf = R(cfact(o));
+      xL[a][o] = kf * c[o] * L.iTp[o];
+      R acc = R(0);
+      static_for<o, N>([&](auto j) {
+        constexpr R k = R(cfall(o, j));
+        acc += k * c[j];
+      });
+      xR[a][o] = acc * L.iTp[o];
+    });
+    if constexpr (FINAL) {
+#pragma unroll
+      for (int j = 0; j < N; ++j) cfin[a][j] = c[j];
+    }
+  }
+
+  knot_exchange<FINAL, P, S>(L, xL, xR, xr_sh, xl_sh, wl, wid, nw, zfin);
+}
+
+// ---- The same arithmetic split by axis, for the lane-per-axis sweep (sweep_axis_impl.h).  Each
+// function repeats, statement for statement, the corresponding part of knot_exchange and sweep_once
+// above (which keep their own inline form: the one-lane kernel's schedule is tuned around it), so both
+// forms compute the same bits; the GPU tests compare them.
+
 // Consensus and dual update of one knot order of one axis (eqs. UpdateZ, UpdateU), given the
 // segment's own end states xl / xr and its neighbours' (xp: the left neighbour's end state, xn: the
 // right neighbour's start state; ignored without a neighbour).
@@ -80,12 +239,12 @@ __device__ __forceinline__ void knot_update(int o, R xl, R xr, R xp, R xn, bool 
   uR += (o < P || !last) ? du_r : R(0);
 }
 
-// Knot consensus and the u update after the local solves (eqs. UpdateZ, UpdateU): neighbours
-// inside the wave by shuffles, across waves through LDS (one barrier).  LT is any lane type with
-// the knot state zL, zR, uL, uR [3][S] and the neighbour flags.
+// knot_exchange with the per-order update of knot_update (the same arithmetic); the polytope sweep
+// uses this form, which schedules better there (10.2 against 11.2 ms for the 8-face batched solve).
 template <bool FINAL, int P, int S, typename LT, typename R>
-__device__ __forceinline__ void knot_exchange(LT& L, R (&xL)[3][S], R (&xR)[3][S], R (*xr_sh)[3 * S],
-                                              R (*xl_sh)[3 * S], int wl, int wid, int nw, R (&zfin)[3][S]) {
+__device__ __forceinline__ void knot_exchange_by_order(LT& L, R (&xL)[3][S], R (&xR)[3][S], R (*xr_sh)[3 * S],
+                                                       R (*xl_sh)[3 * S], int wl, int wid, int nw,
+                                                       R (&zfin)[3][S]) {
   if (wl == 63) {
 #pragma unroll
     for (int a = 0; a < 3; ++a)
@@ -210,37 +369,6 @@ __device__ __forceinline__ void axis_update(const HF& H, R iT, const R (&iTp)[S]
 #pragma unroll
     for (int j = 0; j < N; ++j) cfin[j] = c[j];
   }
-}
-
-// One sweep of one lane's segment.  With FINAL the local solve c~ and the end knot before its
-// update are returned through cfin / zfin.
-template <bool FINAL, typename R, int P, int S, bool BOX, bool VEL>
-__device__ __forceinline__ void sweep_once(Lane<R, P, S, BOX, VEL>& L, R (*xr_sh)[3 * S],
-                                           R (*xl_sh)[3 * S], int wl, int wid, int nw,
-                                           R (&cfin)[3][2 * P], R (&zfin)[3][S]) {
-  using LT = Lane<R, P, S, BOX, VEL>;
-  constexpr int MV = LT::MV;
-
-  // velocity projection factors, per sample, shared by the three axes
-  R q[MV], om[MV];
-#pragma unroll
-  for (int s = 0; s < MV; ++s) {
-    if constexpr (VEL) {
-      vel_factors(L.g[0][s], L.g[1][s], L.g[2][s], L.vm, L.iT, q[s], om[s]);
-    } else {
-      q[s] = R(0);
-      om[s] = R(0);
-    }
-  }
-
-  R xL[3][S], xR[3][S];
-  const auto H = [&](int h) { return L.H[h]; };
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-    axis_update<FINAL, R, P, S, BOX, VEL>(H, L.iT, L.iTp, L.lo[a], L.hi[a], q, om, L.zL[a], L.zR[a], L.uL[a],
-                                          L.uR[a], L.yh[a], L.yl[a], L.g[a], xL[a], xR[a], cfin[a]);
-
-  knot_exchange<FINAL, P, S>(L, xL, xR, xr_sh, xl_sh, wl, wid, nw, zfin);
 }
 
 // Waves per SIMD the compiler must leave room for.  The float32 septic box + velocity instance
