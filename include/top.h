@@ -93,11 +93,12 @@ typedef struct top_options {
                                 0 records nothing                                                     */
   int32_t max_taped_iters;   /* sweeps the tape can hold when checkpoint_every > 0                    */
   int32_t tile_lanes;        /* segments per workgroup tile, a multiple of 64 from 64 up to the
-                                variant's maximum (TOP_E_INVALID above it): 512 for float32 order 3
-                                (closed form with n_cont < 2p-1, or a polytope corridor), 64 for
-                                NumericSolve, 256 otherwise; with a tape at most 256, less where the
-                                adjoint's LDS column would not fit.  0 picks the maximum (or the
-                                tuned value after top_tune)                                           */
+                                variant's maximum (TOP_E_INVALID above it).  One lane per segment:
+                                512 for float32 order 3 (closed form with n_cont < 2p-1, or a
+                                polytope corridor), 64 for NumericSolve, 256 otherwise; with a tape
+                                128 (float32) or 64 (float64), the adjoint's tiles.  One lane per
+                                segment and axis (lane_form): 320 (float32) or 128 (float64).  0
+                                picks the maximum (or the tuned value after top_tune)                 */
   int32_t halo;              /* sweeps per launch for trajectories longer than a tile (their halo
                                 width); 0 picks the default.  With a tape it must be >= 2: the
                                 reverse pass runs halo - 1 steps per launch                           */
@@ -270,7 +271,7 @@ top_status top_set_state(top_problem* h, const void* state);
 
 /* Execution plan actually in use (host struct). */
 typedef struct top_plan_info {
-  int32_t tile_lanes;        /* lanes (segments) per workgroup tile                         */
+  int32_t tile_lanes;        /* segments per workgroup tile (3x as many lanes with lane_form 3) */
   int32_t n_tiles;           /* workgroups per launch                                       */
   int32_t halo;              /* sweeps per launch when some trajectory is split, else 0     */
   int32_t n_traj;
