@@ -105,7 +105,7 @@ def sweep_kernel_ms(w, d, K, reps=3, precision="fp32"):
     """Average device time of the sweep launches of top_iterate(K), and launches per call."""
     prob = _problem(w, d, precision=precision)
     plan = prob.plan()
-    launches = 1 if plan["halo"] == 0 else -(-K // plan["halo"])
+    launches = 1 if plan["halo"] == 0 or plan["chained"] else -(-K // plan["halo"])
     prob.time_sweeps(K)                       # warm-up
     ms = [prob.time_sweeps(K) for _ in range(reps)]
     prob.close()
@@ -253,7 +253,8 @@ def septic_leg(w2, d2):
         "segment_updates_per_s": round(w2.n_seg * w2.iters / sec2, 1),
         "sweep_only_segment_updates_per_s": round(w2.n_seg * w2.iters / (kms2 * 1e-3), 1),
         "ms_per_solve": round(sec2 * 1e3, 3), "phases_ms": ph2, "tile_lanes": plan2["tile_lanes"],
-        "halo": plan2["halo"], "lanes_per_segment": plan2["lane_form"], "n_tiles": plan2["n_tiles"], "launches": l2,
+        "halo": plan2["halo"], "lanes_per_segment": plan2["lane_form"], "n_tiles": plan2["n_tiles"],
+        "chained": bool(plan2["chained"]), "launches": l2,
         "alu_frac": round(flops_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters / (kms2 * 1e-3)
                           / PEAK_FP32_NONPACKED, 4),
         "hbm_yardstick_frac": round(bytes_per_update(4, 4, 8, True, True) * w2.n_seg * w2.iters

@@ -135,6 +135,13 @@ typedef struct top_options {
                                 TOP_E_UNSUPPORTED otherwise); 0 picks 3 where allowed and some
                                 trajectory is longer than the largest one-lane tile, else 1 (or the
                                 tuned form after top_tune)                                            */
+  int32_t chain;             /* 0: where the plan has halo tiles and the device can hold all of them at
+                                once, one top_iterate call runs all its sweeps in one cooperative
+                                launch (lane_form 3 only): between epochs of halo sweeps each tile
+                                publishes the core segments its neighbours copy and waits for theirs,
+                                instead of ending the launch (the same results, bit for bit, without
+                                one state reload per epoch); such calls are not captured into graphs.
+                                1: one launch per epoch.                                              */
 } top_options;
 
 /* Fill *opt with the defaults: p = 3, s = p, pinned interior, M = 8, FP32, no tape, graph on,
@@ -247,7 +254,9 @@ top_status top_tune(top_problem* h, int32_t k_probe);
  * and 0. */
 top_status top_convergence(const top_problem* h, int32_t* iters, double* rho, uint8_t* done);
 
-/* Block on the stream; TOP_E_NONFINITE if any sweep so far produced a non-finite value. */
+/* Block on the stream; TOP_E_NONFINITE if any sweep so far produced a non-finite value;
+ * TOP_E_HIP if a tile of a chained launch gave up waiting for a neighbour (about a second: the
+ * device did not run all tiles at once after all; the iterate is then wrong). */
 top_status top_sync_status(top_problem* h);
 
 /* Copy of the iterate state (checkpoint and resume), in the iterate precision (float or double),
@@ -284,6 +293,8 @@ typedef struct top_plan_info {
   int32_t n_fields;          /* rows of the iterate state (see top_get_state)               */
   int64_t ld;                /* elements per state row, n_seg rounded up to a multiple of 64 */
   int32_t lane_form;         /* lanes per segment of the sweep launches: 1 or 3                */
+  int32_t chained;           /* 1: an iterate call of more than halo sweeps runs as one chained
+                                launch (see top_options.chain)                                  */
 } top_plan_info;
 
 top_status top_get_plan(const top_problem* h, top_plan_info* info);

@@ -44,7 +44,7 @@ class TopOptions(ctypes.Structure):
                 ("check_every", ctypes.c_int32), ("adapt_rho", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("mu", ctypes.c_double), ("tau_incr", ctypes.c_double), ("tau_decr", ctypes.c_double),
                 ("local_solve", ctypes.c_int32), ("lbfgs_iters", ctypes.c_int32), ("vel_norm", ctypes.c_int32),
-                ("lane_form", ctypes.c_int32)]
+                ("lane_form", ctypes.c_int32), ("chain", ctypes.c_int32)]
 
 
 class TopPlanInfo(ctypes.Structure):
@@ -52,7 +52,7 @@ class TopPlanInfo(ctypes.Structure):
                 ("n_traj", ctypes.c_int32), ("n_seg", ctypes.c_int64), ("used_lanes", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("order", ctypes.c_int32), ("n_cont", ctypes.c_int32),
                 ("iters_done", ctypes.c_int32), ("n_fields", ctypes.c_int32), ("ld", ctypes.c_int64),
-                ("lane_form", ctypes.c_int32)]
+                ("lane_form", ctypes.c_int32), ("chained", ctypes.c_int32)]
 
 
 class TopError(RuntimeError):
@@ -282,7 +282,8 @@ class TopProblem:
                  tile_lanes: int = 0, halo: int = 0, use_graph: bool = True, check_every: int = 0,
                  adapt_rho: bool = False, tol: float = 0.05, mu: float = 10.0, tau_incr: float = 1.1,
                  tau_decr: float = 1.1, numeric: bool = False, lbfgs_iters: int = 10, vel_norm: int = 2,
-                 lane_form: int = 0, device: str = "cuda:0", stream=None, library_pool: bool = False):
+                 lane_form: int = 0, chain: int = 0, device: str = "cuda:0", stream=None,
+                 library_pool: bool = False):
         """Create the handle.  By default its state lives in a workspace allocated by torch on the
         handle's stream (released with the handle); library_pool=True uses the library's pool."""
         import torch
@@ -309,6 +310,7 @@ class TopProblem:
         o.lbfgs_iters = int(lbfgs_iters)
         o.vel_norm = int(vel_norm)
         o.lane_form = int(lane_form)
+        o.chain = int(chain)
         self.options = o
         self.h = None
         self.workspace = None

@@ -67,13 +67,83 @@ int max_tile(const top::Variant& v, bool taped) {
   return std::min(top::adjoint_max_tile(v.prec), max_tile(v));
 }
 
+// Whether the sweep of this variant and these options can run one lane per segment and axis.
+static bool axis_allowed(const top::Variant& v, const top_options& opt) {
+  return !v.num && !v.faces && v.s != 2 * v.p - 1 && opt.checkpoint_every == 0 && opt.check_every == 0;
+}
+
 struct Plan {
   int W = 0;
   int n_tiles = 0;
   int halo = 0;          // > 0 when some trajectory is split across tiles
   int64_t used = 0;
   std::vector<int32_t> lanes;
+  // Chained launches (several halo epochs in one launch): per tile the left / right tile whose core
+  // holds its halo copies (-1: none) and its core lane range [lo, hi); empty when the plan has no
+  // halo or its tiles do not meet the conditions (checked by chain_table).
+  std::vector<int32_t> chain;
+  size_t table_elems() const { return lanes.size() + chain.size(); }
 };
+
+// The chain table of a plan with halo tiles (see Plan::chain), or empty.  A chained epoch relies
+// on every halo copy, and the start knot of every halo copy's segment, being published by a
+// neighbouring tile: the core segments within `halo` of a core edge that has a neighbour, plus one
+// more on the right.  The table is built from the tiles' core ranges and then checked against that
+// rule lane by lane.
+std::vector<int32_t> chain_table(const Plan& pl, const std::vector<int64_t>& off) {
+  std::vector<int32_t> ch;
+  const int W = pl.W, h = pl.halo;
+  if (h <= 0 || pl.n_tiles <= 0) return ch;
+  const int64_t S = off.back();
+  ch.assign(4 * (size_t)pl.n_tiles, 0);
+  std::vector<int32_t> owner((size_t)S, -1), owner_lane((size_t)S, -1);
+  for (int t = 0; t < pl.n_tiles; ++t) {
+    const int32_t* L = pl.lanes.data() + (size_t)t * W;
+    int lo = -1, hi = -1;
+    for (int i = 0; i < W; ++i) {
+      if (L[i] < 0 || (L[i] & top::kHaloBit)) continue;
+      if (lo < 0) lo = i;
+      hi = i + 1;
+      owner[L[i] & top::kSegMask] = t;
+      owner_lane[L[i] & top::kSegMask] = i;
+    }
+    const bool left = W > 0 && L[0] >= 0 && (L[0] & top::kHaloBit);
+    bool right = false;
+    for (int i = W - 1; i >= 0; --i)
+      if (L[i] >= 0) { right = (L[i] & top::kHaloBit) != 0; break; }
+    int32_t* c = ch.data() + 4 * (size_t)t;
+    c[0] = left ? t - 1 : -1;
+    c[1] = right ? t + 1 : -1;
+    c[2] = lo < 0 ? 0 : lo;
+    c[3] = hi < 0 ? 0 : hi;
+  }
+  // whether tile t publishes segment s (its core lane i) at the end of an epoch
+  auto published = [&](int64_t s) {
+    const int t = owner[(size_t)s], i = owner_lane[(size_t)s];
+    if (t < 0) return false;
+    const int32_t* c = ch.data() + 4 * (size_t)t;
+    return (c[0] >= 0 && i < c[2] + h) || (c[1] >= 0 && i >= c[3] - h - 1);
+  };
+  std::vector<uint8_t> first((size_t)S, 0);
+  for (size_t b = 0; b + 1 < off.size(); ++b) first[(size_t)off[b]] = 1;
+  for (int t = 0; t < pl.n_tiles; ++t) {
+    const int32_t* L = pl.lanes.data() + (size_t)t * W;
+    const int32_t* c = ch.data() + 4 * (size_t)t;
+    for (int i = 0; i < W; ++i) {
+      if (L[i] < 0 || !(L[i] & top::kHaloBit)) continue;
+      const int64_t s = L[i] & top::kSegMask;
+      const int dep = i < c[2] ? c[0] : c[1];
+      if (dep < 0 || owner[(size_t)s] != dep || !published(s)) return {};
+      // a copy reloads its start knot as the end knot of the segment before it, which must be
+      // published too (by this tile or a neighbour)
+      if (!first[(size_t)s]) {
+        const int o = owner[(size_t)(s - 1)];
+        if ((o != c[0] && o != c[1] && o != t) || !published(s - 1)) return {};
+      }
+    }
+  }
+  return ch;
+}
 
 // Pack whole trajectories of at most W segments into W-lane tiles (first-fit decreasing); split
 // longer ones into tiles whose core segments are flanked by up to `halo` copied neighbours.
@@ -132,6 +202,7 @@ Plan make_plan(const std::vector<int64_t>& off, int W, int halo) {
     }
   }
   pl.n_tiles = (int)(pl.lanes.size() / W);
+  pl.chain = chain_table(pl, off);
   return pl;
 }
 
@@ -308,12 +379,16 @@ top_status get_plan(const std::vector<int64_t>& off, int W, int halo, std::share
   e->plan = make_plan(off, W, halo);
   e->off = off;
   e->device = dev;
-  const size_t bytes = e->plan.lanes.size() * sizeof(int32_t);
+  // the lane map, then the chain table
+  const size_t bytes = e->plan.table_elems() * sizeof(int32_t);
   void* q = nullptr;
   hipError_t he = hipMalloc(&q, bytes);
   if (he != hipSuccess) return fail(TOP_E_NOMEM, "hipMalloc(%zu) for the lane map failed", bytes);
   e->dev = static_cast<int32_t*>(q);
-  he = hipMemcpy(e->dev, e->plan.lanes.data(), bytes, hipMemcpyHostToDevice);
+  he = hipMemcpy(e->dev, e->plan.lanes.data(), e->plan.lanes.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  if (he == hipSuccess && !e->plan.chain.empty())
+    he = hipMemcpy(e->dev + e->plan.lanes.size(), e->plan.chain.data(), e->plan.chain.size() * sizeof(int32_t),
+                   hipMemcpyHostToDevice);
   if (he != hipSuccess) return fail(TOP_E_HIP, "lane map upload failed: %s", hipGetErrorString(he));
   std::lock_guard<std::mutex> lk(g_plan_mu);
   // keep at most 16 shapes; drop the ones no handle uses any more
@@ -615,7 +690,7 @@ struct top_problem {
 
   template <typename R>
   top_status launch_one(const Plan& pl, const int32_t* lane_map, const void* in, void* outp, int n, bool fin,
-                        hipStream_t st, bool store_frozen, void* rec) {
+                        hipStream_t st, bool store_frozen, void* rec, bool chain) {
     top::SweepArgs<R> a = sweep_args<R>(pl, lane_map);
     a.st_in = (const R*)in;
     a.st_out = (R*)outp;
@@ -623,6 +698,12 @@ struct top_problem {
     a.final_out = fin ? 1 : 0;
     a.store_frozen = store_frozen ? 1 : 0;
     a.inner = opt.lbfgs_iters;
+    if (chain) {  // the epochs of n sweeps in one launch; both state buffers are written
+      a.chain_halo = pl.halo;
+      a.chain = lane_map + pl.lanes.size();
+      a.chain_flag = chain_flag;
+      a.chain_err = flag_dev + 2;
+    }
     if (rec != nullptr) {  // recording launch: the state after sweep i < n - 1 goes to slot i + 1
       a.rec = (R*)rec;
       a.rec_slot = (int64_t)nf * ld;
@@ -636,10 +717,30 @@ struct top_problem {
   }
 
   top_status sweep_launch(const Plan& pl, const int32_t* lane_map, const void* in, void* outp, int n, bool fin,
-                          hipStream_t st, bool store_frozen = false, void* rec = nullptr) {
-    return v.prec == 0 ? launch_one<float>(pl, lane_map, in, outp, n, fin, st, store_frozen, rec)
-                       : launch_one<double>(pl, lane_map, in, outp, n, fin, st, store_frozen, rec);
+                          hipStream_t st, bool store_frozen = false, void* rec = nullptr, bool chain = false) {
+    return v.prec == 0 ? launch_one<float>(pl, lane_map, in, outp, n, fin, st, store_frozen, rec, chain)
+                       : launch_one<double>(pl, lane_map, in, outp, n, fin, st, store_frozen, rec, chain);
   }
+
+  // Chained launches (SweepArgs::chain_halo): the epoch flags, the tiles they cover, and the
+  // device's co-resident tile count for the plan's tile width (cached).
+  unsigned long long* chain_flag = nullptr;
+  int64_t chain_cap = 0;
+  int resident_W = 0, resident_tiles = 0;
+  // Whether the handle's plan may chain: option, lane form, chain table, flag room, residency.
+  bool can_chain() {
+    const Plan& pl = plan_ref();
+    if (opt.chain != 0 || !axis || pl.chain.empty() || tape != nullptr || opt.check_every > 0 || v.num || v.faces)
+      return false;
+    if (pl.n_tiles > chain_cap) return false;
+    if (resident_W != pl.W) {
+      resident_tiles = v.prec == 0 ? top::sweep_axis_resident<float>(v, pl.W) : top::sweep_axis_resident<double>(v, pl.W);
+      resident_W = pl.W;
+    }
+    return pl.n_tiles <= resident_tiles;
+  }
+  // k sweeps as one chained launch: more than one epoch on a plan that can chain
+  bool chains(int k) { return k > plan_ref().halo && can_chain(); }
 
   // Elements of the reverse pass's zero-initialised allocation: the adjoint of the state after the
   // last sweep (adjb[0]) and the per-segment accumulators (1/T, rho Htilde^-1, start knot).
@@ -673,7 +774,11 @@ struct top_problem {
     TOP_ALLOC(rho_seg, l * sizeof(double));
     TOP_ALLOC(part, 3 * (size_t)S * sizeof(double));
     TOP_ALLOC(out, 3 * (size_t)B * sizeof(double));
-    TOP_ALLOC(flag_dev, 2 * sizeof(int));
+    TOP_ALLOC(flag_dev, 4 * sizeof(int));   // non-finite, invalid input, chained-launch wait
+    // epoch flags of chained launches: one per tile of any plan whose tile cores hold 64 segments
+    // or more (the lane-per-axis variants only)
+    chain_cap = axis_allowed(v, opt) ? S / 64 + B + 1 : 0;
+    if (chain_cap > 0) TOP_ALLOC(chain_flag, (size_t)chain_cap * sizeof(unsigned long long));
     TOP_ALLOC(rho_traj, (size_t)B * sizeof(double));
     TOP_ALLOC(chunk_sum, 3 * (size_t)std::max<int64_t>(n_chunks, 1) * sizeof(double));
     if (opt.check_every > 0) {
@@ -968,6 +1073,17 @@ struct top_problem {
     const size_t sbytes = (size_t)nf * ld * rsz;
     if (ev0 != nullptr) TOP_HIP(hipEventRecord(ev0, st));
     bool checked_last = false;
+    if (chains(k)) {
+      // all k sweeps in one launch; its epochs alternate the state buffers like separate launches
+      const Plan& pl = plan_ref();
+      hipError_t e = top::launch_zero_u64(chain_flag, pl.n_tiles, st);
+      if (e != hipSuccess) return fail(TOP_E_HIP, "chain flag reset failed: %s", hipGetErrorString(e));
+      top_status s = sweep_launch(pl, lanes(), state[c], state[c ^ 1], k, true, st, false, nullptr, true);
+      if (s != TOP_OK) return s;
+      const int epochs = (k + pl.halo - 1) / pl.halo;
+      c ^= epochs & 1;
+      remaining = 0;
+    }
     const int m = opt.checkpoint_every;
     const int j_last = tape != nullptr ? (done0 + k - 1) / m : -1;  // block of this call's last sweep
     while (remaining > 0) {
@@ -1120,11 +1236,6 @@ void top_trim(void) {
   if (have_dev) (void)hipSetDevice(dev0);
 }
 
-// Whether the sweep of this variant and these options can run one lane per segment and axis.
-static bool axis_allowed(const top::Variant& v, const top_options& opt) {
-  return !v.num && !v.faces && v.s != 2 * v.p - 1 && opt.checkpoint_every == 0 && opt.check_every == 0;
-}
-
 // Options after defaults, checked as far as they can be without the trajectory lengths, and the
 // kernel variant they select.  box/vel/polytope say which corridor and bound are given.
 static top_status resolve_options(const top_options* opt_in, bool box, bool vel, bool polytope, top_options* opt_out,
@@ -1160,6 +1271,7 @@ static top_status resolve_options(const top_options* opt_in, bool box, bool vel,
   if (polytope && taped) return fail(TOP_E_UNSUPPORTED, "a polytope corridor cannot be combined with a tape");
   if (opt.lane_form != 0 && opt.lane_form != 1 && opt.lane_form != 3)
     return fail(TOP_E_INVALID, "lane_form must be 0, 1 or 3 (got %d)", opt.lane_form);
+  if (opt.chain != 0 && opt.chain != 1) return fail(TOP_E_INVALID, "chain must be 0 or 1 (got %d)", opt.chain);
   if (opt.lane_form == 3 && !axis_allowed(v, opt))
     return fail(TOP_E_UNSUPPORTED, "one lane per axis needs the closed form with n_cont < 2p-1, no polytope, "
                                    "no tape and no residual checks");
@@ -1312,7 +1424,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
       top_problem sz;
       sz.sizing = true;
       sz.B = n_traj;
-      (void)sz.allocate_tables(n_chunks, own_plan.lanes.size());
+      (void)sz.allocate_tables(n_chunks, own_plan.table_elems());
       need += sz.ws_used;
     }
     if (workspace_bytes < ws_pad + need)
@@ -1368,7 +1480,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     h->own_tables = true;
     h->own_plan = std::move(own_plan);
     chunk_tables(h->off, &h->own_chunk_off, &h->own_chunk_traj);
-    if ((st = h->allocate_tables(h->n_chunks, h->own_plan.lanes.size())) != TOP_OK) return bail(st);
+    if ((st = h->allocate_tables(h->n_chunks, h->own_plan.table_elems())) != TOP_OK) return bail(st);
     hipError_t e = hipMemcpyAsync(const_cast<int64_t*>(h->off_dev), h->off.data(), h->off.size() * sizeof(int64_t),
                                   hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
@@ -1380,6 +1492,9 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     if (e == hipSuccess)
       e = hipMemcpyAsync(h->own_lanes, h->own_plan.lanes.data(), h->own_plan.lanes.size() * sizeof(int32_t),
                          hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && !h->own_plan.chain.empty())
+      e = hipMemcpyAsync(h->own_lanes + h->own_plan.lanes.size(), h->own_plan.chain.data(),
+                         h->own_plan.chain.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "table upload failed: %s", hipGetErrorString(e)));
   }
   if (opt.check_every > 0) {
@@ -1408,7 +1523,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "input copy failed: %s", hipGetErrorString(e)));
   }
   {
-    hipError_t e = hipMemsetAsync(h->flag_dev, 0, 2 * sizeof(int), stream);
+    hipError_t e = hipMemsetAsync(h->flag_dev, 0, 4 * sizeof(int), stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "flag reset failed: %s", hipGetErrorString(e)));
   }
   top::SetupArgs sa{waypoints, durations, bc, box_lo, box_hi, faces, n_faces, vmax, rho, h->off_dev, n_traj, S,
@@ -1525,12 +1640,13 @@ top_status top_iterate(top_problem* h, int32_t k) {
   // A sequence is captured into a graph the second time it is asked for; the first call launches it
   // directly (a one-shot solve would only pay for the capture).
   const auto key = std::make_tuple(k, h->cur, h->opt.check_every > 0 ? h->iters_done % h->opt.check_every : 0);
-  const bool graph = h->opt.use_graph != 0 && h->tape == nullptr &&
+  // (a chained launch is cooperative and is launched directly)
+  const bool graph = h->opt.use_graph != 0 && h->tape == nullptr && !h->chains(k) &&
                      (h->graphs.count(key) != 0 || h->graph_seen.count(key) != 0);
   if (!graph) {
     top_status s = h->enqueue(k, h->cur, h->iters_done, h->stream);
     if (s != TOP_OK) return s;
-    if (h->opt.use_graph != 0 && h->tape == nullptr) h->graph_seen.insert(key);
+    if (h->opt.use_graph != 0 && h->tape == nullptr && !h->chains(k)) h->graph_seen.insert(key);
   } else {
     auto it = h->graphs.find(key);
     if (it == h->graphs.end()) {
@@ -1628,9 +1744,10 @@ top_status top_convergence(const top_problem* h, int32_t* iters, double* rho, ui
 
 top_status top_sync_status(top_problem* h) {
   if (h == nullptr) return fail(TOP_E_INVALID, "handle is NULL");
-  int flag[2] = {0, 0};
+  int flag[4] = {0, 0, 0, 0};
   TOP_HIP(hipMemcpyAsync(flag, h->flag_dev, sizeof flag, hipMemcpyDeviceToHost, h->stream));
   TOP_HIP(hipStreamSynchronize(h->stream));
+  if (flag[2] != 0) return fail(TOP_E_HIP, "a tile of a chained sweep launch gave up waiting for a neighbour");
   if (flag[0] != 0) return fail(TOP_E_NONFINITE, "a sweep produced a non-finite value");
   return TOP_OK;
 }
@@ -1650,6 +1767,7 @@ top_status top_get_plan(const top_problem* h, top_plan_info* info) {
   info->n_fields = h->nf;
   info->ld = h->ld;
   info->lane_form = h->axis ? 3 : 1;
+  info->chained = const_cast<top_problem*>(h)->can_chain() ? 1 : 0;
   return TOP_OK;
 }
 

@@ -33,6 +33,9 @@ constexpr int kMaxWaves = 16;    // 1024-lane workgroups at most
 constexpr int32_t kHaloBit = 1 << 30;
 constexpr size_t kScratchLimit = 8192;  // per-lane stack limit the library sets; no kernel may exceed it
 constexpr int32_t kSegMask = kHaloBit - 1;
+// Polls of a neighbour's epoch flag before a chained launch gives up on it (a poll is a memory
+// round trip plus a short sleep, so roughly a second in all; an epoch takes tens of microseconds).
+constexpr int kChainSpin = 1 << 20;
 
 enum : uint8_t { kFirst = 1, kLast = 2 };
 
@@ -132,6 +135,15 @@ struct SweepArgs {
                             // state, for an output buffer that does not hold it yet (tuning probes)
   R* rec;                   // recording launches (reverse-pass replay): the state after sweep i of the
   int64_t rec_slot;         // launch, i < iters - 1, goes to rec + (i + 1) * rec_slot; else null
+  // Chained launch (lane-per-axis sweep): `iters` sweeps in epochs of chain_halo sweeps inside one
+  // cooperative launch.  Between epochs every tile publishes the core segments its neighbours copy
+  // into their halos (to the other state buffer) and reloads its own halo copies once its two
+  // neighbours have published; 0 runs one epoch (the ordinary launch).
+  int chain_halo;
+  const int32_t* chain;            // [n_tiles][4]: left / right source tile of the halo (-1: none),
+                                   // first core lane, one past the last core lane
+  unsigned long long* chain_flag;  // [n_tiles] epochs published by each tile, zero at launch
+  int* chain_err;                  // set to 1 when a wait for a neighbour gave up
 };
 
 struct Variant {
@@ -152,6 +164,12 @@ constexpr int kAxisTileMax = 320;
 inline int axis_max_tile(int prec) { return prec == 0 ? kAxisTileMax : 128; }
 template <typename R>
 hipError_t launch_sweep_axis(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
+// Workgroups of the lane-per-axis sweep for W-segment tiles that the device holds at once (the
+// bound of a chained launch), or 0 when the device has no cooperative launch.
+template <typename R>
+int sweep_axis_resident(const Variant& v, int W);
+// zero n unsigned 64-bit words (the epoch flags of a chained launch)
+hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
 // the same launch for a general polytope corridor (v.faces = kFaces)
 template <typename R>
 hipError_t launch_poly_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);

@@ -14,6 +14,25 @@
 // its knot end states, and after the sweep's one barrier it reads the other two axes' values for the
 // next sweep's factors.  Each segment's rho Htilde^-1 is read from LDS by its three lanes.  This form
 // has no recording instance and no stopped-trajectory handling (no tape, no residual checks).
+//
+// Chained launches.  Run as one launch per `halo` sweeps, every launch reloads and stores the whole
+// state of every tile, a fixed cost of about six sweeps' time for a 320-segment tile.  A chained
+// launch (SweepArgs::chain_halo > 0, cooperative, so that every tile is resident) runs all the
+// sweeps of the call in epochs of at most `halo` sweeps: at the end of an epoch a tile stores only
+// the core segments its neighbours copy (the `halo` segments next to each core edge, one more on the
+// right for the start knot of the neighbour's outermost copy) into the other state buffer, publishes
+// the epoch in its flag, waits until both neighbours have published theirs, and reloads its halo
+// copies from that buffer.  The halo copies then hold exactly what a fresh launch would load, and
+// the core segments keep their registers, so the results are the same bits as one launch per epoch.
+//
+// Ordering of the exchange.  The published values and the flags are written and read only with
+// device-scope atomic accesses (relaxed), which the L2 caches of the chip's dies do not hold
+// incoherently.  A writer's wave waits for its stores to complete before the tile's barrier, and only
+// after that barrier does one thread store the flag; a reader's one polling thread sees the flag
+// before the tile's barrier, and only after it do the waves load the values.  So every value is
+// complete before its flag is written and read only after the flag is seen: the order a release and
+// an acquire would give, without their write-back and invalidation of the whole L2 (which cost more
+// than the launch they replace).
 #pragma once
 
 #include "sweep_impl.h"
@@ -42,6 +61,27 @@ struct AxisLane {
 inline size_t sweep_axis_lds_bytes(int p, bool vel, size_t rsz, int TS) {
   const int n = 2 * p, nh = n * (n + 1) / 2;
   return (size_t)(nh + 2 * 3 * (vel ? kSamples : 1)) * rsz * (size_t)TS;
+}
+
+// x, hidden from the optimiser: address arithmetic built on it is redone at every use instead of
+// being hoisted out of the epoch loop into registers held across every sweep.
+__device__ __forceinline__ int64_t opaque(int64_t x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
+// s_waitcnt operand that waits for every outstanding vector memory access (vmcnt 0) and for
+// nothing else (expcnt 7, lgkmcnt 15: their maxima, in the GFX9 encoding).
+constexpr int kWaitStores = 0x0F70;
+
+// Wait until tile t has published at least `epochs` epochs; false if the poll bound ran out.  The
+// polls are device-scope atomic loads; every load of the values the flag guards comes after them.
+__device__ inline bool chain_wait(const unsigned long long* flag, int t, unsigned long long epochs) {
+  for (int i = 0; i < kChainSpin; ++i) {
+    if (__hip_atomic_load(flag + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epochs) return true;
+    __builtin_amdgcn_s_sleep(2);
+  }
+  return false;
 }
 
 template <typename R, int P, int S, bool BOX, bool VEL, int LB>
@@ -75,11 +115,24 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
   const int wl = lane & 63, wid = lane >> 6, nw = W >> 6;
   auto G = [&](int buf, int ax, int s) -> R& { return sh_g[((buf * 3 + ax) * MV + s) * TS]; };
 
+  // epochs: one, or ceil(iters / chain_halo) in a chained launch, each with a barrier before its
+  // flag and one after the wait that follows (chain: neighbour tiles and the core lane range)
+  const int ep_len = A.chain_halo > 0 ? A.chain_halo : A.iters;
+  const int n_ep = A.chain_halo > 0 ? (A.iters + ep_len - 1) / ep_len : 1;
+  int dep_l = -1, dep_r = -1, core_lo = 0, core_hi = W;
+  if (A.chain_halo > 0) {
+    const int32_t* c = A.chain + 4 * (int64_t)blockIdx.x;
+    dep_l = c[0];
+    dep_r = c[1];
+    core_lo = c[2];
+    core_hi = c[3];
+  }
+
   // the tile's matrices into LDS (the three lanes of a segment share the loads)
   for (int h = a; h < NH; h += 3) sh_H[h * TS] = active ? A.k.Hr[h * ld + seg] : R(0);
   if (__ballot(active) == 0) {            // a wave without segments keeps the barrier count
     __syncthreads();
-    for (int it = 0; it < A.iters; ++it) __syncthreads();
+    for (int it = 0; it < A.iters + 2 * (n_ep - 1); ++it) __syncthreads();
     return;
   }
 
@@ -107,29 +160,70 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
   for (int o = 1; o < S; ++o) L.iTp[o] = L.iTp[o - 1] * L.iT;
 
   // ---- state of this axis, and the split values of all three for the first sweep's factors
-  const R* in = A.st_in;
-#pragma unroll
-  for (int o = 0; o < S; ++o) {
-    const int f = a * S + o;
-    L.zR[o] = active ? in[(F_ZR + f) * ld + seg] : R(0);
-    L.uL[o] = active ? in[(F_UL + f) * ld + seg] : R(0);
-    L.uR[o] = active ? in[(F_UR + f) * ld + seg] : R(0);
-    L.zL[o] = !active ? R(0)
-            : L.first ? A.k.bcL[((int64_t)tr * 3 + a) * S + o]
-                      : in[(F_ZR + f) * ld + seg - 1];
-  }
-#pragma unroll
-  for (int s = 0; s < LT::MB; ++s) {
-    L.yh[s] = (BOX && active) ? in[(F_YH + a * M + s) * ld + seg] : R(0);
-    L.yl[s] = (BOX && active) ? in[(F_YL + a * M + s) * ld + seg] : R(0);
-  }
   R gall[3][MV];
 #pragma unroll
-  for (int b = 0; b < 3; ++b)
+  for (int o = 0; o < S; ++o) L.zL[o] = (active && L.first) ? A.k.bcL[((int64_t)tr * 3 + a) * S + o] : R(0);
+  // (a trajectory's first segment keeps its start knot, which no sweep changes)
+  auto get = [](const R* p, auto dev) -> R {
+    if constexpr (decltype(dev)::value) return __hip_atomic_load(const_cast<R*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else return *p;
+  };
+  auto load = [&](const R* in0, auto dev) {
+    const R* in = in0 + opaque(seg);
 #pragma unroll
-    for (int s = 0; s < MV; ++s) gall[b][s] = (VEL && active) ? in[(F_G + b * M + s) * ld + seg] : R(0);
+    for (int o = 0; o < S; ++o) {
+      const int f = a * S + o;
+      L.zR[o] = active ? get(&in[(F_ZR + f) * ld], dev) : R(0);
+      L.uL[o] = active ? get(&in[(F_UL + f) * ld], dev) : R(0);
+      L.uR[o] = active ? get(&in[(F_UR + f) * ld], dev) : R(0);
+      if (active && !L.first) L.zL[o] = get(&in[(F_ZR + f) * ld - 1], dev);
+    }
 #pragma unroll
-  for (int s = 0; s < MV; ++s) L.g[s] = a == 0 ? gall[0][s] : (a == 1 ? gall[1][s] : gall[2][s]);
+    for (int s = 0; s < LT::MB; ++s) {
+      L.yh[s] = (BOX && active) ? get(&in[(F_YH + a * M + s) * ld], dev) : R(0);
+      L.yl[s] = (BOX && active) ? get(&in[(F_YL + a * M + s) * ld], dev) : R(0);
+    }
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int s = 0; s < MV; ++s) gall[b][s] = (VEL && active) ? get(&in[(F_G + b * M + s) * ld], dev) : R(0);
+    // (the own axis' values loaded again rather than picked out of gall by axis: a pick by the
+    // lane's axis index can turn gall into an indexed array in scratch memory)
+#pragma unroll
+    for (int s = 0; s < MV; ++s) L.g[s] = (VEL && active) ? get(&in[(F_G + a * M + s) * ld], dev) : R(0);
+  };
+  // this axis' state fields of the segment; DEV: as device-coherent accesses (the exchange between
+  // the tiles of a chained launch)
+  auto put = [](R* p, R x, auto dev) {
+    if constexpr (decltype(dev)::value) __hip_atomic_store(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else *p = x;
+  };
+  auto store = [&](R* out0, auto dev) {
+    R* out = out0 + opaque(seg);
+#pragma unroll
+    for (int o = 0; o < S; ++o) {
+      const int f = a * S + o;
+      put(&out[(F_ZR + f) * ld], L.zR[o], dev);
+      put(&out[(F_UL + f) * ld], L.uL[o], dev);
+      put(&out[(F_UR + f) * ld], L.uR[o], dev);
+    }
+    if constexpr (BOX) {
+#pragma unroll
+      for (int s = 0; s < M; ++s) {
+        put(&out[(F_YH + a * M + s) * ld], L.yh[s], dev);
+        put(&out[(F_YL + a * M + s) * ld], L.yl[s], dev);
+      }
+    }
+    if constexpr (VEL) {
+#pragma unroll
+      for (int s = 0; s < M; ++s) put(&out[(F_G + a * M + s) * ld], L.g[s], dev);
+    }
+  };
+  // epoch e reads buffer e % 2 (0: st_in) and writes the other
+  R* const buf0 = const_cast<R*>(A.st_in);
+  R* const buf1 = A.st_out;
+  auto bufs = [&](int q) { return (q & 1) ? buf1 : buf0; };
+  load(buf0, std::false_type{});
   __syncthreads();   // the matrices are in LDS
 
   const auto H = [&](int h) { return sh_H[h * TS]; };
@@ -183,8 +277,40 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
     }
     buf ^= 1;
   };
-  const int n_plain = A.final_out ? A.iters - 1 : A.iters;
-  for (int it = 0; it < n_plain; ++it) sweep(std::false_type{});
+  int left = A.iters;
+  for (int e = 0; e < n_ep; ++e) {
+    if (e > 0) {
+      // the neighbours' core edges of the last epoch are in bufs[e % 2]: reload the halo copies
+      // one thread waits for the tile; the values are loaded after the barrier
+      if (threadIdx.x == 0) {
+        bool ok = true;
+        if (dep_l >= 0) ok = chain_wait(A.chain_flag, dep_l, (unsigned long long)e);
+        if (ok && dep_r >= 0) ok = chain_wait(A.chain_flag, dep_r, (unsigned long long)e);
+        if (!ok) atomicOr(A.chain_err, 1);
+      }
+      __syncthreads();
+      if (active && !core) load(bufs(e), std::true_type{});
+    }
+    const int n = e + 1 < n_ep ? ep_len : left;
+    // the call's last sweep (with its outputs) runs after the loop
+    const int n_plain = e + 1 == n_ep && A.final_out && n > 0 ? n - 1 : n;
+    for (int it = 0; it < n_plain; ++it) sweep(std::false_type{});
+    left -= n;
+    if (e + 1 < n_ep) {
+      // publish the core segments the neighbours copy: the chain_halo next to each core edge that
+      // has a neighbour, and on the right one more (the start knot of the neighbour's outermost
+      // copy is that segment's end knot)
+      const int ln = (int)threadIdx.x % W;
+      if (core && ((dep_l >= 0 && ln < core_lo + A.chain_halo) || (dep_r >= 0 && ln >= core_hi - A.chain_halo - 1)))
+        store(bufs(e + 1), std::true_type{});
+      __builtin_amdgcn_s_waitcnt(kWaitStores);   // this wave's exchange stores are complete
+      __syncthreads();
+      if (threadIdx.x == 0)
+        __hip_atomic_store(A.chain_flag + blockIdx.x, (unsigned long long)(e + 1), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+
   if (A.final_out && A.iters > 0) sweep(std::true_type{});
 
   if (core) {
@@ -194,44 +320,17 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
 #pragma unroll
       for (int o = 0; o < S; ++o) A.zold_out[(a * S + o) * ld + seg] = zfin[o];
     }
-    R* out = A.st_out;
-#pragma unroll
-    for (int o = 0; o < S; ++o) {
-      const int f = a * S + o;
-      out[(F_ZR + f) * ld + seg] = L.zR[o];
-      out[(F_UL + f) * ld + seg] = L.uL[o];
-      out[(F_UR + f) * ld + seg] = L.uR[o];
-    }
-    if constexpr (BOX) {
-#pragma unroll
-      for (int s = 0; s < M; ++s) {
-        out[(F_YH + a * M + s) * ld + seg] = L.yh[s];
-        out[(F_YL + a * M + s) * ld + seg] = L.yl[s];
-      }
-    }
-    if constexpr (VEL) {
-#pragma unroll
-      for (int s = 0; s < M; ++s) out[(F_G + a * M + s) * ld + seg] = L.g[s];
-    }
+    store(bufs(n_ep), std::false_type{});
   }
 }
 
-// Launch over tiles of W <= LBT segments (3 W threads each); closed form, s in {p, p+1}, no
-// recording and no stopped trajectories.
+// The kernel instance of variant v, or nullptr.
 template <typename R, int LBT>
-hipError_t dispatch_sweep_axis(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st) {
-  if (v.num || v.faces || v.s == 2 * v.p - 1 || a.rec != nullptr || a.done != nullptr) return hipErrorInvalidValue;
-  if (a.W <= 0 || a.W > LBT || (a.W & 63) != 0 || n_tiles <= 0) return hipErrorInvalidValue;
-  dim3 grid(n_tiles), block(3 * a.W);
-  const size_t lds = sweep_axis_lds_bytes(v.p, v.vel != 0, sizeof(R), LBT);
+void* sweep_axis_instance(const Variant& v) {
+  if (v.num || v.faces || v.s == 2 * v.p - 1) return nullptr;
 #define TOP_AXIS_CASE(P_, S_, B_, V_)                                                             \
-  if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_) {                      \
-    auto k_ = sweep_axis_kernel<R, P_, S_, B_, V_, 3 * LBT>;                                     \
-    hipError_t e_ = hipFuncSetAttribute((const void*)k_, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
-    if (e_ != hipSuccess) return e_;                                                             \
-    hipLaunchKernelGGL(k_, grid, block, lds, st, a);                                             \
-    return hipGetLastError();                                                                    \
-  }
+  if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_)                        \
+    return reinterpret_cast<void*>(sweep_axis_kernel<R, P_, S_, B_, V_, 3 * LBT>);
 #define TOP_AXIS_PS(P_, S_)                                                                        \
   TOP_AXIS_CASE(P_, S_, true, true)                                                                \
   TOP_AXIS_CASE(P_, S_, true, false)                                                               \
@@ -243,7 +342,47 @@ hipError_t dispatch_sweep_axis(const Variant& v, const SweepArgs<R>& a, int n_ti
   TOP_AXIS_PS(4, 5)
 #undef TOP_AXIS_PS
 #undef TOP_AXIS_CASE
-  return hipErrorInvalidValue;
+  return nullptr;
+}
+
+// Launch over tiles of W <= LBT segments (3 W threads each); closed form, s in {p, p+1}, no
+// recording and no stopped trajectories.  A chained launch (a.chain_halo > 0) is cooperative: the
+// runtime refuses it unless every tile can be resident at once.
+template <typename R, int LBT>
+hipError_t dispatch_sweep_axis(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st) {
+  if (a.rec != nullptr || a.done != nullptr) return hipErrorInvalidValue;
+  if (a.W <= 0 || a.W > LBT || (a.W & 63) != 0 || n_tiles <= 0) return hipErrorInvalidValue;
+  if (a.chain_halo > 0 && (a.chain == nullptr || a.chain_flag == nullptr || a.chain_err == nullptr))
+    return hipErrorInvalidValue;
+  void* k = sweep_axis_instance<R, LBT>(v);
+  if (k == nullptr) return hipErrorInvalidValue;
+  dim3 grid(n_tiles), block(3 * a.W);
+  const size_t lds = sweep_axis_lds_bytes(v.p, v.vel != 0, sizeof(R), LBT);
+  hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  if (a.chain_halo > 0) {
+    SweepArgs<R> arg = a;
+    void* params[] = {&arg};
+    return hipLaunchCooperativeKernel(k, grid, block, params, (unsigned)lds, st);
+  }
+  SweepArgs<R> arg = a;
+  void* params[] = {&arg};
+  return hipLaunchKernel(k, grid, block, params, lds, st);
+}
+
+// Tiles of W segments that the device holds at once, 0 without cooperative launches.
+template <typename R, int LBT>
+int resident_sweep_axis(const Variant& v, int W) {
+  void* k = sweep_axis_instance<R, LBT>(v);
+  if (k == nullptr || W <= 0 || W > LBT) return 0;
+  int dev = 0, coop = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || coop == 0) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const size_t lds = sweep_axis_lds_bytes(v.p, v.vel != 0, sizeof(R), LBT);
+  if (hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 3 * W, lds) != hipSuccess) return 0;
+  return per_cu * cus;
 }
 
 }  // namespace top

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 def test_default_options_and_error_text():
     o = binding.default_options()
     assert (o.order, o.n_cont, o.fix_interior, o.n_samples, o.precision, o.use_graph) == (3, 0, 1, 8, 0, 1)
-    assert (o.local_solve, o.lbfgs_iters, o.vel_norm, o.lane_form) == (0, 10, 2, 0)
+    assert (o.local_solve, o.lbfgs_iters, o.vel_norm, o.lane_form, o.chain) == (0, 10, 2, 0, 0)
     assert isinstance(binding.lib().top_last_error(), bytes)
 
 
@@ -86,6 +86,10 @@ def test_host_argument_errors():
     o.lane_form = 2
     st, h, msg = _create(1, [0, 3], o)
     assert st == binding.TOP_E_INVALID and "lane_form" in msg
+    o = binding.default_options()
+    o.chain = 2
+    st, h, msg = _create(1, [0, 3], o)
+    assert st == binding.TOP_E_INVALID and "chain" in msg
     o = binding.default_options()
     o.check_every = -1
     st, h, msg = _create(1, [0, 3], o)
