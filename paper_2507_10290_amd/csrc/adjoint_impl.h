@@ -129,6 +129,10 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
   for (int o = 1; o < N; ++o) iTp[o] = iTp[o - 1] * iT;
   const int tr = active ? A.k.traj[seg] : 0;
   const R dc = (active && A.with_cost) ? (R)A.dcost[tr] : R(0);
+  // the trajectory's start-knot state (the forward start knot of a first segment)
+  R zL0[S];
+#pragma unroll
+  for (int o = 0; o < S; ++o) zL0[o] = (active && first) ? A.k.bcL[((int64_t)tr * 3 + a) * S + o] : R(0);
 
   // adjoint state of this axis, in registers
   R lz[S], luL[S], luR[S], az0[S], LYH[MB], LYL[MB], LG[MV];
@@ -153,6 +157,34 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
     const R* st = (t == 0 && A.blk0 != nullptr) ? A.blk0 : A.blk + (int64_t)t * A.slot;
     const bool cost_step = A.with_cost && (t == A.steps - 1);
     const int buf = t & 1;
+
+    // ---- forward state before this sweep: this axis' values, and the velocity factors (from all
+    // three axes' split values, the same operations on each lane of the segment).  Loaded before
+    // the first exchange, whose barrier then hides part of the loads' latency.
+    // (every lane loads unconditionally: an idle lane's seg is 0, a valid column, so it computes on
+    // finite values that reach no active lane and no output; a first segment reads its own column
+    // for the start knot and takes the boundary state instead)
+    R zL[S], zR[S], uL[S], uR[S], yh[MB], yl[MB], g[MV];
+    const int64_t prev = (active && !first) ? seg - 1 : seg;
+#pragma unroll
+    for (int o = 0; o < S; ++o) {
+      const int fo = a * S + o;
+      zR[o] = st[(F_ZR + fo) * ld + seg];
+      uL[o] = st[(F_UL + fo) * ld + seg];
+      uR[o] = st[(F_UR + fo) * ld + seg];
+      const R vzl = st[(F_ZR + fo) * ld + prev];
+      zL[o] = first ? zL0[o] : vzl;
+    }
+#pragma unroll
+    for (int s = 0; s < MB; ++s) {
+      yh[s] = BOX ? st[(F_YH + a * M + s) * ld + seg] : R(0);
+      yl[s] = BOX ? st[(F_YL + a * M + s) * ld + seg] : R(0);
+    }
+    R gs[3][MV];
+#pragma unroll
+    for (int s = 0; s < MV; ++s)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) gs[b][s] = VEL ? st[(F_G + b * M + s) * ld + seg] : R(0);
 
     // ---- E1: adjoints of the new knot values.  Lam_k = lz(i) - luR(i) - luL(i+1) at an
     // interior knot k between segments i and i+1; both lanes form it with the same operations.
@@ -182,35 +214,14 @@ __global__ __launch_bounds__(LB) void adjoint_kernel(AdjArgs<R> A) {
       LamL[o] = has_left ? (pz - pu) - luL[o] : -(mL ? luL[o] : R(0));
     }
 
-    // ---- forward state before this sweep: this axis' values, and the velocity factors (from all
-    // three axes' split values, the same operations on each lane of the segment)
-    R zL[S], zR[S], uL[S], uR[S], yh[MB], yl[MB], g[MV];
-#pragma unroll
-    for (int o = 0; o < S; ++o) {
-      const int fo = a * S + o;
-      zR[o] = active ? st[(F_ZR + fo) * ld + seg] : R(0);
-      uL[o] = active ? st[(F_UL + fo) * ld + seg] : R(0);
-      uR[o] = active ? st[(F_UR + fo) * ld + seg] : R(0);
-      zL[o] = !active ? R(0)
-            : first ? A.k.bcL[((int64_t)tr * 3 + a) * S + o]
-                    : st[(F_ZR + fo) * ld + seg - 1];
-    }
-#pragma unroll
-    for (int s = 0; s < MB; ++s) {
-      yh[s] = (BOX && active) ? st[(F_YH + a * M + s) * ld + seg] : R(0);
-      yl[s] = (BOX && active) ? st[(F_YL + a * M + s) * ld + seg] : R(0);
-    }
     R f[MV], rs2[MV], lf[MV];
     bool outside[MV];
 #pragma unroll
     for (int s = 0; s < MV; ++s) {
       lf[s] = R(0);
       if constexpr (VEL) {
-        R gs[3];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) gs[b] = active ? st[(F_G + b * M + s) * ld + seg] : R(0);
-        g[s] = a == 0 ? gs[0] : (a == 1 ? gs[1] : gs[2]);
-        const R n2 = gs[0] * gs[0] + gs[1] * gs[1] + gs[2] * gs[2];
+        g[s] = a == 0 ? gs[0][s] : (a == 1 ? gs[1][s] : gs[2][s]);
+        const R n2 = gs[0][s] * gs[0][s] + gs[1][s] * gs[1][s] + gs[2][s] * gs[2][s];
         const R q = vm * inv_sqrt<R>(n2);
         outside[s] = q < R(1);
         f[s] = fmin(R(1), q);
