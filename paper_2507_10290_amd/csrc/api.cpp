@@ -45,6 +45,15 @@ top_status fail(top_status s, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(TOP_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
+// SIMDs of the current device (four per compute unit), or 1024 if the runtime does not say.
+int device_simds() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+      cus > 0)
+    return 4 * cus;
+  return 1024;
+}
+
 int max_tile(const top::Variant& v) {
   if (v.num) return 64;
   if (v.faces) return (v.prec == 0 && v.p == 3) ? 512 : 256;  // the polytope kernel's LDS-matrix instance
@@ -1399,7 +1408,16 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
       }
     }
   }
-  if (form == 0) form = (axis_ok && longest > max_tile(v, taped)) ? 3 : 1;
+  if (form == 0) {
+    // Three lanes per segment where allowed and either some trajectory is longer than a one-lane
+    // tile, or (no tile width given) one lane per segment would give fewer waves than half the
+    // device's SIMDs: a small problem is latency-bound, and three times the waves each with a third
+    // of the work finish sooner (a 64-segment trajectory: 0.60 against 1.44 ms for 1,000 sweeps;
+    // 15,384 segments in 64 trajectories: 0.64 against 0.77 ms for 200; at 67,259 segments, one wave
+    // per SIMD with one lane, the one-lane form is ahead, 0.82 against 1.26 ms).
+    const bool few_waves = opt.tile_lanes == 0 && (S + 63) / 64 < device_simds() / 2;
+    form = (axis_ok && (longest > max_tile(v, taped) || few_waves)) ? 3 : 1;
+  }
   const int wmax = form == 3 ? top::axis_max_tile(v.prec) : max_tile(v, taped);
   if (wmax < 64) return fail(TOP_E_UNSUPPORTED, "the device's per-workgroup LDS is too small for the adjoint kernel");
   if (opt.tile_lanes != 0 && (opt.tile_lanes < 64 || opt.tile_lanes > wmax || opt.tile_lanes % 64 != 0))
@@ -1803,7 +1821,7 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
         if (4 * halo <= W) cands.push_back({W, halo, form});
   };
   for (int W = 64; W <= max_tile(h->v, h->tape != nullptr); W *= 2) add(W, 1);
-  if (h->axis_ok && mx > 64)   // one lane per axis: for tiles that hold parts of long trajectories
+  if (h->axis_ok)   // one lane per axis: for long trajectories, and small problems
     for (int W = 128; W <= top::axis_max_tile(h->v.prec); W += 64) add(W, 3);
   hipEvent_t e0, e1;
   TOP_HIP(hipEventCreate(&e0));

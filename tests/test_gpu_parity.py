@@ -279,16 +279,27 @@ def test_lane_per_axis_graph_replays_match_eager_launches():
     e.close()
 
 
-def test_default_plan_of_long_trajectories_is_one_lane_per_axis():
+def test_default_lane_form():
+    # three lanes per segment for trajectories longer than a one-lane tile, and for problems whose
+    # one-lane waves would fill fewer than half the SIMDs; one lane otherwise
     from paper_2507_10290_amd import TopProblem
-    for w, prec in ((make_config(2, scale=1 / 16), "fp32"), (make_config(1), "fp64"), (make_config(3, n_traj=8), "fp32")):
+    simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    cases = ((make_config(2, scale=1 / 16), "fp32"), (make_config(1), "fp64"), (make_config(3, n_traj=8), "fp32"),
+             (make_config(3, n_traj=600), "fp32"))
+    for w, prec in cases:
         prob = TopProblem.from_workload(w, precision=prec)
         plan = prob.plan()
         prob.close()
         longest = int(w.traj_lengths().max())
-        print(f"[parity] {w.name} {prec} longest {longest}: {plan}", flush=True)
-        expect = 3 if longest > (512 if (prec == "fp32" and w.order == 3) else 256) else 1
-        assert plan["lane_form"] == expect
+        print(f"[parity] {w.name} {prec} longest {longest} S={w.n_seg}: {plan}", flush=True)
+        long_traj = longest > (512 if (prec == "fp32" and w.order == 3) else 256)
+        few_waves = (w.n_seg + 63) // 64 < simds // 2
+        assert plan["lane_form"] == (3 if long_traj or few_waves else 1)
+    # an explicit tile width keeps the one-lane form for a small problem
+    w = make_config(3, n_traj=8)
+    prob = TopProblem.from_workload(w, precision="fp32", tile_lanes=512)
+    assert prob.plan()["lane_form"] == 1 and prob.plan()["tile_lanes"] == 512
+    prob.close()
 
 
 def test_graph_replays_match_eager_launches():
@@ -367,7 +378,10 @@ def test_autotune_keeps_results():
     ref = run_gpu(w, 30, "fp32")[0]
     prob = TopProblem.from_workload(w, precision="fp32")
     plan = prob.tune(5)
-    assert plan["tile_lanes"] in (64, 128, 256, 512)
+    if plan["lane_form"] == 3:
+        assert plan["tile_lanes"] in (128, 192, 256, 320)
+    else:
+        assert plan["tile_lanes"] in (64, 128, 256, 512)
     prob.iterate(30)
     c = prob.coeffs().cpu().numpy()
     prob.close()
