@@ -712,6 +712,7 @@ struct top_problem {
       a.chain = lane_map + pl.lanes.size();
       a.chain_flag = chain_flag;
       a.chain_err = flag_dev + 2;
+      a.chain_spin = chain_spin;
     }
     if (rec != nullptr) {  // recording launch: the state after sweep i < n - 1 goes to slot i + 1
       a.rec = (R*)rec;
@@ -735,6 +736,7 @@ struct top_problem {
   // device's co-resident tile count for the plan's tile width (cached).
   unsigned long long* chain_flag = nullptr;
   int64_t chain_cap = 0;
+  int chain_spin = top::kChainSpin;
   int resident_W = 0, resident_tiles = 0;
   // Whether the handle's plan may chain: option, lane form, chain table, flag room, residency.
   bool can_chain() {
@@ -1473,6 +1475,11 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   h->explicit_tile = opt.tile_lanes != 0 || opt.lane_form != 0;
   h->axis = form == 3;
   h->axis_ok = axis_ok;
+  if (const char* e = std::getenv("TOP_CHAIN_SPIN")) {
+    char* end = nullptr;
+    const long n = std::strtol(e, &end, 10);
+    if (end != e && n >= 0 && n < top::kChainSpin) h->chain_spin = (int)n;
+  }
   for (int b = 0; b < n_traj; ++b) h->max_len = std::max<int64_t>(h->max_len, seg_offsets[b + 1] - seg_offsets[b]);
   h->stream = stream;
   if (workspace != nullptr) {

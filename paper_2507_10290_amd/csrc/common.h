@@ -35,6 +35,8 @@ constexpr size_t kScratchLimit = 8192;  // per-lane stack limit the library sets
 constexpr int32_t kSegMask = kHaloBit - 1;
 // Polls of a neighbour's epoch flag before a chained launch gives up on it (a poll is a memory
 // round trip plus a short sleep, so roughly a second in all; an epoch takes tens of microseconds).
+// The environment variable TOP_CHAIN_SPIN, read when a handle is created, can lower it (a test of
+// the give-up path sets 0).
 constexpr int kChainSpin = 1 << 20;
 
 enum : uint8_t { kFirst = 1, kLast = 2 };
@@ -144,6 +146,7 @@ struct SweepArgs {
                                    // first core lane, one past the last core lane
   unsigned long long* chain_flag;  // [n_tiles] epochs published by each tile, zero at launch
   int* chain_err;                  // set to 1 when a wait for a neighbour gave up
+  int chain_spin;                  // polls of a neighbour's flag before giving up (kChainSpin)
 };
 
 struct Variant {

@@ -76,8 +76,8 @@ constexpr int kWaitStores = 0x0F70;
 
 // Wait until tile t has published at least `epochs` epochs; false if the poll bound ran out.  The
 // polls are device-scope atomic loads; every load of the values the flag guards comes after them.
-__device__ inline bool chain_wait(const unsigned long long* flag, int t, unsigned long long epochs) {
-  for (int i = 0; i < kChainSpin; ++i) {
+__device__ inline bool chain_wait(const unsigned long long* flag, int t, unsigned long long epochs, int spin) {
+  for (int i = 0; i < spin; ++i) {
     if (__hip_atomic_load(flag + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epochs) return true;
     __builtin_amdgcn_s_sleep(2);
   }
@@ -284,8 +284,8 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
       // one thread waits for the tile; the values are loaded after the barrier
       if (threadIdx.x == 0) {
         bool ok = true;
-        if (dep_l >= 0) ok = chain_wait(A.chain_flag, dep_l, (unsigned long long)e);
-        if (ok && dep_r >= 0) ok = chain_wait(A.chain_flag, dep_r, (unsigned long long)e);
+        if (dep_l >= 0) ok = chain_wait(A.chain_flag, dep_l, (unsigned long long)e, A.chain_spin);
+        if (ok && dep_r >= 0) ok = chain_wait(A.chain_flag, dep_r, (unsigned long long)e, A.chain_spin);
         if (!ok) atomicOr(A.chain_err, 1);
       }
       __syncthreads();

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from paper_2507_10290_amd.workloads import make_config, random_walk_batch
+from paper_2507_10290_amd.workloads import curve_workload, make_config, random_walk_batch
 from tests._harness import gpu_available, per_traj_rel, rel, run_oracle
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
@@ -44,6 +44,17 @@ CASES = {
     "quintic-fp64-halo": (lambda: make_config(1), (50, 7), "fp64", {"tile_lanes": 128, "halo": 8}),
     "ragged-fp64": (lambda: _ragged("fp64"), (60,), "fp64", {"tile_lanes": 64, "halo": 12}),
     "ragged-fp32": (lambda: _ragged("fp32"), (25, 26), "fp32", {"tile_lanes": 128, "halo": 12}),
+    # the other corridor / bound instances and consensus orders
+    "septic-box-only-fp32": (lambda: random_walk_batch("sbox", [700, 90], [5, 6], order=4, box=True, vmax=None,
+                                                       precision="fp32"), (40,), "fp32", {"halo": 16}),
+    "quintic-vel-only-fp64": (lambda: random_walk_batch("qvel", [400, 250], [7, 8], order=3, box=False, vmax=3.0,
+                                                        precision="fp64"), (30,), "fp64",
+                              {"tile_lanes": 128, "halo": 8}),
+    "quintic-s4-fp64": (lambda: random_walk_batch("q4", [300], [9], order=3, n_cont=4, precision="fp64"), (27,),
+                        "fp64", {"tile_lanes": 128, "halo": 8}),
+    "septic-s5-fp32": (lambda: random_walk_batch("s5", [900], [10], order=4, n_cont=5, precision="fp32"), (50,),
+                       "fp32", {"halo": 16}),
+    "curve-end-states-fp32": (lambda: curve_workload(1500, order=3, precision="fp32"), (100,), "fp32", {"halo": 32}),
 }
 
 
@@ -87,4 +98,27 @@ def test_chained_calls_mixed_with_single_epoch_calls():
     plain, _ = _run(w, calls, "fp32", chain=1, halo=16)
     assert plan["chained"] == 1
     for x, y in zip(chained, plain):
+        assert np.array_equal(x, y)
+
+
+def test_a_wait_that_gives_up_is_reported(monkeypatch):
+    # the neighbour waits of a chained launch are bounded; with the bound forced to zero polls from
+    # the host every wait gives up at once, the launch still ends, and top_sync_status reports it
+    from paper_2507_10290_amd import TopProblem
+    from paper_2507_10290_amd.binding import TOP_E_HIP, TopError
+    w = make_config(2, scale=1 / 32)
+    monkeypatch.setenv("TOP_CHAIN_SPIN", "0")
+    prob = TopProblem.from_workload(w, precision="fp32", lane_form=3, halo=16)
+    try:
+        assert prob.plan()["chained"] == 1
+        prob.iterate(40)
+        with pytest.raises(TopError) as ei:
+            prob.sync_status()
+        assert ei.value.status == TOP_E_HIP and "gave up waiting" in str(ei.value)
+    finally:
+        prob.close()
+    monkeypatch.delenv("TOP_CHAIN_SPIN")
+    ok, _ = _run(w, (40,), "fp32", chain=0, halo=16)
+    ref, _ = _run(w, (40,), "fp32", chain=1, halo=16)
+    for x, y in zip(ok, ref):
         assert np.array_equal(x, y)
