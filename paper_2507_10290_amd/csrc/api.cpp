@@ -1084,7 +1084,10 @@ struct top_problem {
     const size_t sbytes = (size_t)nf * ld * rsz;
     if (ev0 != nullptr) TOP_HIP(hipEventRecord(ev0, st));
     bool checked_last = false;
-    if (chains(k)) {
+    // (not while a caller captures the stream into a graph: a cooperative launch is not captured)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const bool capturing = hipStreamIsCapturing(st, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
+    if (!capturing && chains(k)) {
       // all k sweeps in one launch; its epochs alternate the state buffers like separate launches
       const Plan& pl = plan_ref();
       hipError_t e = top::launch_zero_u64(chain_flag, pl.n_tiles, st);

@@ -122,3 +122,30 @@ def test_a_wait_that_gives_up_is_reported(monkeypatch):
     ref, _ = _run(w, (40,), "fp32", chain=1, halo=16)
     for x, y in zip(ok, ref):
         assert np.array_equal(x, y)
+
+
+def test_iterate_in_a_callers_graph_capture_runs_one_launch_per_epoch():
+    # a caller capturing the handle's stream gets the ordinary launches (a cooperative launch is not
+    # captured); two epochs return the state to its buffer, so the graph can be replayed in turn
+    from paper_2507_10290_amd import TopProblem
+    w = make_config(2, scale=1 / 32)
+    s = torch.cuda.Stream()
+    cap = TopProblem.from_workload(w, precision="fp32", lane_form=3, halo=16, use_graph=False, stream=s)
+    ref = TopProblem.from_workload(w, precision="fp32", lane_form=3, halo=16, use_graph=False)
+    try:
+        assert cap.plan()["chained"] == 1
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=s):
+            cap.iterate(32)
+        for step in range(3):
+            graph.replay()
+            ref.iterate(32)
+            torch.cuda.synchronize()
+            assert torch.equal(cap.coeffs(), ref.coeffs()), step
+            assert torch.equal(cap.cost(), ref.cost()), step
+        cap.sync_status()
+        ref.sync_status()
+    finally:
+        cap.close()
+        ref.close()
