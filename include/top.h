@@ -141,8 +141,9 @@ typedef struct top_options {
                                 launch (lane_form 3 only): between epochs of halo sweeps each tile
                                 publishes the core segments its neighbours copy and waits for theirs,
                                 instead of ending the launch (the same results, bit for bit, without
-                                one state reload per epoch); such calls are not captured into graphs.
-                                1: one launch per epoch.                                              */
+                                one state reload per epoch); such calls are not captured into the
+                                handle's graphs, and while the caller captures the stream the call
+                                takes one launch per epoch instead.  1: one launch per epoch.         */
 } top_options;
 
 /* Fill *opt with the defaults: p = 3, s = p, pinned interior, M = 8, FP32, no tape, graph on,
