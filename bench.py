@@ -492,6 +492,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps and the roofline")
     ap.add_argument("--calib-copy", action="store_true", help="also run a 1 GiB device copy (counter scale)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuning of the batched workload's plan (keep the default plan)")
     ap.add_argument("--counters-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the markdown summary of two rocprofv3 counter runs and exit (no GPU)")
     ap.add_argument("--leg", choices=["fwd_bwd", "septic"],
@@ -543,9 +545,12 @@ def main():
     torch.cuda.synchronize()
 
     # the execution plan is autotuned once per shape class (top_tune), outside the timed region
-    pt = _problem(w, d, precision="fp32")
-    pt.tune(20)
-    pt.close()
+    # (--no-tune keeps the default plan: for runs under a counter profiler, whose per-dispatch
+    # overhead the tuner's timings would include)
+    if not a.no_tune:
+        pt = _problem(w, d, precision="fp32")
+        pt.tune(20)
+        pt.close()
     sec = time_steps(lambda: solve_step(w, d, K), a.steps, a.warmup)
     value = w.n_seg * K / sec
 
