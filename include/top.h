@@ -133,9 +133,10 @@ typedef struct top_options {
                                 waves, for trajectories longer than a tile; tiles of at most 320
                                 segments; closed form with n_cont < 2p-1, no tape, no checks,
                                 TOP_E_UNSUPPORTED otherwise); 0 picks 3 where allowed and some
-                                trajectory is longer than the largest one-lane tile or, with no
-                                tile_lanes given, one lane per segment would make fewer waves than
-                                half the device's SIMDs; else 1 (or the tuned form after top_tune)  */
+                                trajectory is longer than the largest one-lane tile or, in FP32 with
+                                no tile_lanes given, one lane per segment would make fewer waves
+                                than half the device's SIMDs; else 1 (or the tuned form after
+                                top_tune)                                                           */
   int32_t chain;             /* 0: where the plan has halo tiles and the device can hold all of them at
                                 once, one top_iterate call runs all its sweeps in one cooperative
                                 launch (lane_form 3 only): between epochs of halo sweeps each tile

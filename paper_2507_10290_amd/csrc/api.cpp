@@ -1415,12 +1415,12 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   }
   if (form == 0) {
     // Three lanes per segment where allowed and either some trajectory is longer than a one-lane
-    // tile, or (no tile width given) one lane per segment would give fewer waves than half the
-    // device's SIMDs: a small problem is latency-bound, and three times the waves each with a third
-    // of the work finish sooner (a 64-segment trajectory: 0.60 against 1.44 ms for 1,000 sweeps;
-    // 15,384 segments in 64 trajectories: 0.64 against 0.77 ms for 200; at 67,259 segments, one wave
-    // per SIMD with one lane, the one-lane form is ahead, 0.82 against 1.26 ms).
-    const bool few_waves = opt.tile_lanes == 0 && (S + 63) / 64 < device_simds() / 2;
+    // tile, or (float32, no tile width given) one lane per segment would give fewer waves than half
+    // the device's SIMDs: a small problem is latency-bound, and three times the waves each with a
+    // third of the work finish sooner (a 64-segment trajectory: 0.60 against 1.44 ms for 1,000
+    // sweeps; 15,384 segments in 64 trajectories: 0.64 against 0.77 ms for 200; at 67,259 segments,
+    // one wave per SIMD with one lane, the one-lane form is ahead, 0.82 against 1.26 ms).
+    const bool few_waves = opt.tile_lanes == 0 && v.prec == 0 && (S + 63) / 64 < device_simds() / 2;
     form = (axis_ok && (longest > max_tile(v, taped) || few_waves)) ? 3 : 1;
   }
   const int wmax = form == 3 ? top::axis_max_tile(v.prec) : max_tile(v, taped);

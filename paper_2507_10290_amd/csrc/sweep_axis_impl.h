@@ -280,8 +280,8 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
   int left = A.iters;
   for (int e = 0; e < n_ep; ++e) {
     if (e > 0) {
-      // the neighbours' core edges of the last epoch are in bufs[e % 2]: reload the halo copies
-      // one thread waits for the tile; the values are loaded after the barrier
+      // The neighbours' core edges of the last epoch are in bufs(e): once both have published
+      // them (one thread waits for the tile), the halo copies reload after the barrier.
       if (threadIdx.x == 0) {
         bool ok = true;
         if (dep_l >= 0) ok = chain_wait(A.chain_flag, dep_l, (unsigned long long)e, A.chain_spin);
@@ -360,13 +360,9 @@ hipError_t dispatch_sweep_axis(const Variant& v, const SweepArgs<R>& a, int n_ti
   const size_t lds = sweep_axis_lds_bytes(v.p, v.vel != 0, sizeof(R), LBT);
   hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  if (a.chain_halo > 0) {
-    SweepArgs<R> arg = a;
-    void* params[] = {&arg};
-    return hipLaunchCooperativeKernel(k, grid, block, params, (unsigned)lds, st);
-  }
   SweepArgs<R> arg = a;
   void* params[] = {&arg};
+  if (a.chain_halo > 0) return hipLaunchCooperativeKernel(k, grid, block, params, (unsigned)lds, st);
   return hipLaunchKernel(k, grid, block, params, lds, st);
 }
 

@@ -280,8 +280,8 @@ def test_lane_per_axis_graph_replays_match_eager_launches():
 
 
 def test_default_lane_form():
-    # three lanes per segment for trajectories longer than a one-lane tile, and for problems whose
-    # one-lane waves would fill fewer than half the SIMDs; one lane otherwise
+    # three lanes per segment for trajectories longer than a one-lane tile, and for float32 problems
+    # whose one-lane waves would fill fewer than half the SIMDs; one lane otherwise
     from paper_2507_10290_amd import TopProblem
     simds = 4 * torch.cuda.get_device_properties(0).multi_processor_count
     cases = ((make_config(2, scale=1 / 16), "fp32"), (make_config(1), "fp64"), (make_config(3, n_traj=8), "fp32"),
@@ -293,7 +293,7 @@ def test_default_lane_form():
         longest = int(w.traj_lengths().max())
         print(f"[parity] {w.name} {prec} longest {longest} S={w.n_seg}: {plan}", flush=True)
         long_traj = longest > (512 if (prec == "fp32" and w.order == 3) else 256)
-        few_waves = (w.n_seg + 63) // 64 < simds // 2
+        few_waves = prec == "fp32" and (w.n_seg + 63) // 64 < simds // 2
         assert plan["lane_form"] == (3 if long_traj or few_waves else 1)
     # an explicit tile width keeps the one-lane form for a small problem
     w = make_config(3, n_traj=8)
