@@ -325,9 +325,10 @@ void top_trim(void);
  *   coeffs       [dev] float64 [S][3][2p], or NULL
  *   cost         [dev] float64 [B], or NULL
  *   r_primal/r_dual  [dev] float64 [B], or NULL (both NULL when k = 0: TOP_E_STATE otherwise)
- * Options: a tape (checkpoint_every > 0) is TOP_E_UNSUPPORTED; use_graph is ignored.  A problem
- * whose buffers exceed the scratch returns TOP_E_WORKSPACE before any device work (about 2.0 KB per
- * segment in float64, 1.05 KB in float32, for quintic box + velocity: some 8,000 or 15,000 segments).
+ * Options: a tape (checkpoint_every > 0) is TOP_E_UNSUPPORTED; use_graph and chain are ignored (no
+ * graph, one launch per epoch).  A problem whose buffers exceed the scratch returns TOP_E_WORKSPACE
+ * before any device work (about 2.0 KB per segment in float64, 1.05 KB in float32, for quintic box +
+ * velocity: some 8,000 or 15,000 segments).
  * Blocks until the outputs are written and returns TOP_E_NONFINITE like top_sync_status.  Every
  * call on a device shares that device's copy of the array (one per process), which keeps what the
  * last call left; a call writes everything it reads first.  Calls that overlapped on one device

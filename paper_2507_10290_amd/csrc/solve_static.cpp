@@ -60,6 +60,7 @@ extern "C" top_status top_solve_static(int32_t n_traj, const int64_t* seg_offset
   if (opt_in != nullptr) opt = *opt_in; else top_default_options(&opt);
   if (opt.checkpoint_every != 0) return top::internal_error(TOP_E_UNSUPPORTED, "top_solve_static records no tape");
   opt.use_graph = 0;  // direct launches: a graph would be instantiated (allocated) per call
+  opt.chain = 1;      // ordinary launches only (the runtime may set up state for a cooperative one)
   StaticScratch* sc = nullptr;
   top_status st = static_scratch(&sc);
   if (st != TOP_OK) return st;
