@@ -33,7 +33,7 @@ STATUS_NAMES = {0: "TOP_OK", -1: "TOP_E_INVALID", -2: "TOP_E_WORKSPACE", -3: "TO
 EXPORTED = ["top_default_options", "top_workspace_bytes", "top_workspace_bytes_polytope", "top_create",
             "top_create_polytope", "top_iterate", "top_time_sweeps", "top_residuals", "top_cost",
             "top_coeffs", "top_backward", "top_tune", "top_convergence", "top_get_state", "top_set_state",
-            "top_sync_status", "top_get_plan", "top_destroy", "top_trim", "top_solve_static", "top_last_error"]
+            "top_sync_status", "top_get_plan", "top_plan_tiles", "top_destroy", "top_trim", "top_solve_static", "top_last_error"]
 
 
 class TopOptions(ctypes.Structure):
@@ -109,6 +109,9 @@ def lib() -> ctypes.CDLL:
     L.top_sync_status.restype = ctypes.c_int
     L.top_get_plan.argtypes = [vp, ctypes.POINTER(TopPlanInfo)]
     L.top_get_plan.restype = ctypes.c_int
+    L.top_plan_tiles.argtypes = [i32, i64p, i32, i32, vp, ctypes.c_int64, vp, ctypes.c_int64,
+                                 ctypes.POINTER(TopPlanInfo)]
+    L.top_plan_tiles.restype = ctypes.c_int
     L.top_destroy.argtypes = [vp]
     L.top_destroy.restype = None
     L.top_trim.argtypes = []
@@ -259,6 +262,24 @@ def top_get_plan(h: int) -> dict:
     info = TopPlanInfo()
     _check(lib().top_get_plan(ctypes.c_void_p(h), ctypes.byref(info)))
     return {f: getattr(info, f) for f, _ in TopPlanInfo._fields_}
+
+
+TOP_HALO_BIT = 1 << 30
+
+
+def top_plan_tiles(seg_offsets, tile_lanes: int, halo: int):
+    """Host only: the tile plan for these trajectory lengths (top_plan_tiles).  Returns (info dict,
+    lanes int32 [n_tiles, tile_lanes], chain int32 [n_tiles, 4] or an empty [0, 4] array)."""
+    off = np.ascontiguousarray(seg_offsets, dtype=np.int64)
+    n_traj = len(off) - 1
+    offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
+    info = TopPlanInfo()
+    _check(lib().top_plan_tiles(n_traj, offp, tile_lanes, halo, None, 0, None, 0, ctypes.byref(info)))
+    lanes = np.empty((info.n_tiles, tile_lanes), dtype=np.int32)
+    chain = np.empty((info.n_tiles if info.chained else 0, 4), dtype=np.int32)
+    _check(lib().top_plan_tiles(n_traj, offp, tile_lanes, halo, lanes.ctypes.data, lanes.size,
+                                chain.ctypes.data, chain.size, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in TopPlanInfo._fields_}, lanes, chain
 
 
 def top_destroy(h: int) -> None:

@@ -1357,47 +1357,14 @@ static size_t workspace_bytes_impl(int32_t n_traj, int64_t n_seg_total, int32_t 
   return need == 0 ? 0 : need + kWsAlign;  // room to align an arbitrary base
 }
 
-static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
-                              const double* durations, const double* bc, const double* box_lo,
-                              const double* box_hi, int32_t n_faces, const double* faces, const double* vmax,
-                              const double* rho, const top_options* opt_in, void* workspace, size_t workspace_bytes,
-                              hipStream_t stream, top_problem** out, top::Mem mem = top::Mem::kCallerWs) {
-  using top::Mem;
-  if (out == nullptr) return fail(TOP_E_INVALID, "out is NULL");
-  *out = nullptr;
-  if (n_traj < 1) return fail(TOP_E_INVALID, "n_traj must be >= 1 (got %d)", n_traj);
-  if (seg_offsets == nullptr) return fail(TOP_E_INVALID, "seg_offsets is NULL");
-  if (waypoints == nullptr || durations == nullptr || rho == nullptr)
-    return fail(TOP_E_INVALID, "waypoints, durations and rho are required");
-  if ((box_lo == nullptr) != (box_hi == nullptr)) return fail(TOP_E_INVALID, "give both box_lo and box_hi, or neither");
-  if ((workspace == nullptr) != (workspace_bytes == 0))
-    return fail(TOP_E_INVALID, "give a workspace with its size, or NULL and 0 for the library's pool");
-  if (seg_offsets[0] != 0) return fail(TOP_E_INVALID, "seg_offsets[0] must be 0");
-  for (int b = 0; b < n_traj; ++b)
-    if (seg_offsets[b + 1] <= seg_offsets[b])
-      return fail(TOP_E_INVALID, "trajectory %d has no segment (seg_offsets must increase strictly)", b);
-  const int64_t S = seg_offsets[n_traj];
-  if (S + n_traj >= (int64_t)top::kHaloBit) return fail(TOP_E_UNSUPPORTED, "too many segments (%lld)", (long long)S);
-  top_options opt;
-  top::Variant v;
-  top_status st = resolve_options(opt_in, box_lo != nullptr, vmax != nullptr, faces != nullptr, &opt, &v);
-  if (st != TOP_OK) return st;
-  const int s = opt.n_cont;
-  const bool taped = opt.checkpoint_every > 0;
-  if (opt.check_every > 0) {
-    int64_t longest = 0;
-    for (int b = 0; b < n_traj; ++b) longest = std::max<int64_t>(longest, seg_offsets[b + 1] - seg_offsets[b]);
-    if (longest > 65535LL * 128)  // the check kernels' trajectory-major grids
-      return fail(TOP_E_UNSUPPORTED, "residual checks support trajectories of at most %lld segments",
-                  65535LL * 128);
-  }
-  if (mem == Mem::kPool) workspace = nullptr, workspace_bytes = 0;
-  const std::vector<int64_t> off(seg_offsets, seg_offsets + n_traj + 1);
-  int64_t longest = 0;
-  for (int b = 0; b < n_traj; ++b) longest = std::max<int64_t>(longest, off[b + 1] - off[b]);
-  // execution plan: explicit, tuned for this shape class, or the default.  Lane form: one lane per
-  // segment and axis where allowed and some trajectory is longer than a one-lane tile.
+// The execution plan's tile width, halo and lane form for this shape and these options: explicit,
+// tuned for the shape class (top_tune), or the default (see top_options.lane_form).
+static top_status choose_plan(const top::Variant& v, const top_options& opt, const std::vector<int64_t>& off,
+                              bool taped, int* W_out, int* halo_out, int* form_out) {
   const bool axis_ok = axis_allowed(v, opt);
+  const int64_t S = off.back();
+  int64_t longest = 0;
+  for (size_t b = 0; b + 1 < off.size(); ++b) longest = std::max<int64_t>(longest, off[b + 1] - off[b]);
   int W = opt.tile_lanes, halo = opt.halo, form = opt.lane_form;
   if (W == 0 && form == 0) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1434,6 +1401,51 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     if (opt.halo != 0) return fail(TOP_E_INVALID, "a handle that records a tape needs halo >= 2 (got %d)", halo);
     halo = 2;
   }
+  *W_out = W;
+  *halo_out = halo;
+  *form_out = form;
+  return TOP_OK;
+}
+
+static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const double* waypoints,
+                              const double* durations, const double* bc, const double* box_lo,
+                              const double* box_hi, int32_t n_faces, const double* faces, const double* vmax,
+                              const double* rho, const top_options* opt_in, void* workspace, size_t workspace_bytes,
+                              hipStream_t stream, top_problem** out, top::Mem mem = top::Mem::kCallerWs) {
+  using top::Mem;
+  if (out == nullptr) return fail(TOP_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (n_traj < 1) return fail(TOP_E_INVALID, "n_traj must be >= 1 (got %d)", n_traj);
+  if (seg_offsets == nullptr) return fail(TOP_E_INVALID, "seg_offsets is NULL");
+  if (waypoints == nullptr || durations == nullptr || rho == nullptr)
+    return fail(TOP_E_INVALID, "waypoints, durations and rho are required");
+  if ((box_lo == nullptr) != (box_hi == nullptr)) return fail(TOP_E_INVALID, "give both box_lo and box_hi, or neither");
+  if ((workspace == nullptr) != (workspace_bytes == 0))
+    return fail(TOP_E_INVALID, "give a workspace with its size, or NULL and 0 for the library's pool");
+  if (seg_offsets[0] != 0) return fail(TOP_E_INVALID, "seg_offsets[0] must be 0");
+  for (int b = 0; b < n_traj; ++b)
+    if (seg_offsets[b + 1] <= seg_offsets[b])
+      return fail(TOP_E_INVALID, "trajectory %d has no segment (seg_offsets must increase strictly)", b);
+  const int64_t S = seg_offsets[n_traj];
+  if (S + n_traj >= (int64_t)top::kHaloBit) return fail(TOP_E_UNSUPPORTED, "too many segments (%lld)", (long long)S);
+  top_options opt;
+  top::Variant v;
+  top_status st = resolve_options(opt_in, box_lo != nullptr, vmax != nullptr, faces != nullptr, &opt, &v);
+  if (st != TOP_OK) return st;
+  const int s = opt.n_cont;
+  const bool taped = opt.checkpoint_every > 0;
+  if (opt.check_every > 0) {
+    int64_t longest = 0;
+    for (int b = 0; b < n_traj; ++b) longest = std::max<int64_t>(longest, seg_offsets[b + 1] - seg_offsets[b]);
+    if (longest > 65535LL * 128)  // the check kernels' trajectory-major grids
+      return fail(TOP_E_UNSUPPORTED, "residual checks support trajectories of at most %lld segments",
+                  65535LL * 128);
+  }
+  if (mem == Mem::kPool) workspace = nullptr, workspace_bytes = 0;
+  const std::vector<int64_t> off(seg_offsets, seg_offsets + n_traj + 1);
+  const bool axis_ok = axis_allowed(v, opt);
+  int W = 0, halo = 0, form = 0;
+  if ((st = choose_plan(v, opt, off, taped, &W, &halo, &form)) != TOP_OK) return st;
   Plan own_plan;
   if (mem == Mem::kStatic) own_plan = make_plan(off, W, halo);
   // The workspace must hold this problem's buffers (checked before any device work).
@@ -1796,6 +1808,40 @@ top_status top_get_plan(const top_problem* h, top_plan_info* info) {
   info->ld = h->ld;
   info->lane_form = h->axis ? 3 : 1;
   info->chained = const_cast<top_problem*>(h)->can_chain() ? 1 : 0;
+  return TOP_OK;
+}
+
+top_status top_plan_tiles(int32_t n_traj, const int64_t* seg_offsets, int32_t tile_lanes, int32_t halo,
+                          int32_t* lanes, int64_t lanes_cap, int32_t* chain, int64_t chain_cap,
+                          top_plan_info* info) {
+  if (n_traj <= 0 || seg_offsets == nullptr || info == nullptr)
+    return fail(TOP_E_INVALID, "n_traj > 0, seg_offsets and info are required");
+  if (seg_offsets[0] != 0) return fail(TOP_E_INVALID, "seg_offsets[0] must be 0");
+  for (int b = 0; b < n_traj; ++b)
+    if (seg_offsets[b + 1] <= seg_offsets[b])
+      return fail(TOP_E_INVALID, "trajectory %d has no segment (seg_offsets must increase strictly)", b);
+  const int64_t S = seg_offsets[n_traj];
+  if (S + n_traj >= (int64_t)top::kHaloBit) return fail(TOP_E_UNSUPPORTED, "too many segments (%lld)", (long long)S);
+  if (tile_lanes < 64 || tile_lanes > 512 || tile_lanes % 64 != 0)
+    return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, 512] (got %d)", tile_lanes);
+  if (halo < 1 || 2 * halo >= tile_lanes)
+    return fail(TOP_E_INVALID, "halo must be in [1, tile_lanes / 2) (got %d for %d-lane tiles)", halo, tile_lanes);
+  const std::vector<int64_t> off(seg_offsets, seg_offsets + n_traj + 1);
+  const Plan pl = make_plan(off, tile_lanes, halo);
+  if (lanes != nullptr && lanes_cap < (int64_t)pl.lanes.size())
+    return fail(TOP_E_INVALID, "lanes holds %lld entries; the plan has %zu", (long long)lanes_cap, pl.lanes.size());
+  if (chain != nullptr && chain_cap < (int64_t)pl.chain.size())
+    return fail(TOP_E_INVALID, "chain holds %lld entries; the plan has %zu", (long long)chain_cap, pl.chain.size());
+  *info = top_plan_info{};
+  info->tile_lanes = pl.W;
+  info->n_tiles = pl.n_tiles;
+  info->halo = pl.halo;
+  info->n_traj = n_traj;
+  info->n_seg = S;
+  info->used_lanes = pl.used;
+  info->chained = pl.chain.empty() ? 0 : 1;
+  if (lanes != nullptr) std::copy(pl.lanes.begin(), pl.lanes.end(), lanes);
+  if (chain != nullptr) std::copy(pl.chain.begin(), pl.chain.end(), chain);
   return TOP_OK;
 }
 
