@@ -246,7 +246,10 @@ top_status top_backward(top_problem* h, const double* dcost, double* dwaypoints,
 
 /* Time the candidate tile shapes on this problem (k_probe sweeps each, on scratch state, leaving the
  * iterate untouched), keep the fastest and remember it for problems of the same shape class.
- * Blocks.  A tile shape given explicitly in the options is not overridden. */
+ * Blocks.  A tile shape given explicitly in the options is not overridden.  A candidate that would
+ * run as a chained launch (see top_options.chain) is timed as one, on a copy of the iterate in a
+ * state-sized block taken from the library's pool for the call (also for a handle on a caller's
+ * workspace) and kept in the pool afterwards; TOP_E_NOMEM if it cannot be had. */
 top_status top_tune(top_problem* h, int32_t k_probe);
 
 /* Per-trajectory outcome of the checks (Sec. III-D.3), written on the handle's stream:

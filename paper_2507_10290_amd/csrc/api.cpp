@@ -738,10 +738,11 @@ struct top_problem {
   int64_t chain_cap = 0;
   int chain_spin = top::kChainSpin;
   int resident_W = 0, resident_tiles = 0;
-  // Whether the handle's plan may chain: option, lane form, chain table, flag room, residency.
-  bool can_chain() {
-    const Plan& pl = plan_ref();
-    if (opt.chain != 0 || !axis || pl.chain.empty() || tape != nullptr || opt.check_every > 0 || v.num || v.faces)
+  // Whether plan pl (in the lane form `axis_form`) may chain on this handle: option, lane form,
+  // chain table, flag room, residency.
+  bool plan_chains(const Plan& pl, bool axis_form) {
+    if (opt.chain != 0 || !axis_form || pl.chain.empty() || tape != nullptr || opt.check_every > 0 || v.num ||
+        v.faces)
       return false;
     if (pl.n_tiles > chain_cap) return false;
     if (resident_W != pl.W) {
@@ -750,8 +751,14 @@ struct top_problem {
     }
     return pl.n_tiles <= resident_tiles;
   }
+  bool can_chain() { return plan_chains(plan_ref(), axis); }
   // k sweeps as one chained launch: more than one epoch on a plan that can chain
-  bool chains(int k) { return k > plan_ref().halo && can_chain(); }
+  // (each edge's 32-bit export count reaches epochs times up to 15 waves)
+  bool chains(int k) { return chains(plan_ref(), axis, k); }
+  bool chains(const Plan& pl, bool axis_form, int k) {
+    const int h = pl.halo;
+    return h > 0 && k > h && k / h < (1 << 27) && plan_chains(pl, axis_form);
+  }
 
   // Elements of the reverse pass's zero-initialised allocation: the adjoint of the state after the
   // last sweep (adjb[0]) and the per-segment accumulators (1/T, rho Htilde^-1, start knot).
@@ -1873,7 +1880,7 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   auto add = [&](int W, int form) {
     if (mx <= W) cands.push_back({W, 0, form});
     else
-      for (int halo : {8, 16, 32})
+      for (int halo : {8, 16, 24, 32})
         if (4 * halo <= W) cands.push_back({W, halo, form});
   };
   for (int W = 64; W <= max_tile(h->v, h->tape != nullptr); W *= 2) add(W, 1);
@@ -1886,6 +1893,12 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   const TuneChoice curc{h->plan_ref().W, h->plan_ref().halo, h->axis ? 3 : 1};
   TuneChoice bestc = curc;
   top_status s = TOP_OK;
+  // A candidate that would chain is timed as the chained launch an iterate call makes.  Its epochs
+  // write both of its state buffers, so it runs on a copy of the iterate in a block taken from the
+  // library's pool for the tuning (returned at the end) and the scratch buffer.
+  const size_t sbytes = (size_t)h->nf * h->ld * h->rsz;
+  void* probe_in = nullptr;
+  int probe_dev = 0;
   for (const TuneChoice& c : cands) {
     std::shared_ptr<PlanEntry> cand;
     s = get_plan(h->off, c.W, c.halo > 0 ? c.halo : 1, &cand);
@@ -1893,22 +1906,51 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
     const Plan& pl = cand->plan;
     h->probe_plan = &pl;
     h->probe_axis = c.form == 3;
+    const bool chain = h->chains(pl, c.form == 3, k_probe);
+    if (chain && probe_in == nullptr) {
+      const hipError_t e = pool_get(sbytes, h->stream, &probe_in, &probe_dev);
+      if (e != hipSuccess) {
+        probe_in = nullptr;
+        s = fail(TOP_E_NOMEM, "device allocation of %zu bytes for a tuning probe failed: %s", sbytes,
+                 hipGetErrorString(e));
+        break;
+      }
+    }
     float tbest = 1e30f;
     for (int rep = 0; rep < 3 && s == TOP_OK; ++rep) {
-      TOP_HIP(hipEventRecord(e0, h->stream));
-      int remaining = k_probe;
-      while (remaining > 0) {
-        const int n = pl.halo > 0 ? std::min(remaining, pl.halo) : remaining;
-        // probe sweeps read the live state; the iterate is not advanced
-        s = h->sweep_launch(pl, cand->dev, h->state[h->cur], probe_out, n, false, h->stream, true);
-        if (s != TOP_OK) break;
-        remaining -= n;
+      if (chain) {
+        hipError_t e = hipMemcpyAsync(probe_in, h->state[h->cur], sbytes, hipMemcpyDeviceToDevice, h->stream);
+        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+        if (e == hipSuccess) e = top::launch_zero_u64(h->chain_flag, pl.n_tiles, h->stream);
+        if (e != hipSuccess) {
+          s = fail(TOP_E_HIP, "tuning probe set-up failed: %s", hipGetErrorString(e));
+          break;
+        }
+        s = h->sweep_launch(pl, cand->dev, probe_in, probe_out, k_probe, false, h->stream, true, nullptr, true);
+      } else {
+        const hipError_t e = hipEventRecord(e0, h->stream);
+        if (e != hipSuccess) {
+          s = fail(TOP_E_HIP, "hipEventRecord failed: %s", hipGetErrorString(e));
+          break;
+        }
+        int remaining = k_probe;
+        while (remaining > 0) {
+          const int n = pl.halo > 0 ? std::min(remaining, pl.halo) : remaining;
+          // probe sweeps read the live state; the iterate is not advanced
+          s = h->sweep_launch(pl, cand->dev, h->state[h->cur], probe_out, n, false, h->stream, true);
+          if (s != TOP_OK) break;
+          remaining -= n;
+        }
       }
       if (s != TOP_OK) break;
-      TOP_HIP(hipEventRecord(e1, h->stream));
-      TOP_HIP(hipEventSynchronize(e1));
       float ms = 0.f;
-      TOP_HIP(hipEventElapsedTime(&ms, e0, e1));
+      hipError_t e = hipEventRecord(e1, h->stream);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        s = fail(TOP_E_HIP, "probe timing failed: %s", hipGetErrorString(e));
+        break;
+      }
       tbest = std::min(tbest, ms);
     }
     h->probe_plan = nullptr;
@@ -1921,6 +1963,10 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   }
   // the handle's plan stays unless another is faster by more than the timing noise (3 %)
   if (cur_ms < 1e30f && cur_ms <= 1.03f * best) bestc = curc;
+  if (probe_in != nullptr) {   // back to the pool once the probes that used it have run
+    (void)hipStreamSynchronize(h->stream);
+    pool_put(probe_in, sbytes, probe_dev, h->stream, nullptr);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s != TOP_OK) return s;

@@ -144,7 +144,7 @@ struct SweepArgs {
   int chain_halo;
   const int32_t* chain;            // [n_tiles][4]: left / right source tile of the halo (-1: none),
                                    // first core lane, one past the last core lane
-  unsigned long long* chain_flag;  // [n_tiles] epochs published by each tile, zero at launch
+  unsigned long long* chain_flag;  // [n_tiles] waves' exports per tile (left edge low, right high), zero at launch
   int* chain_err;                  // set to 1 when a wait for a neighbour gave up
   int chain_spin;                  // polls of a neighbour's flag before giving up (kChainSpin)
 };

@@ -18,21 +18,24 @@
 // Chained launches.  Run as one launch per `halo` sweeps, every launch reloads and stores the whole
 // state of every tile, a fixed cost of about six sweeps' time for a 320-segment tile.  A chained
 // launch (SweepArgs::chain_halo > 0, cooperative, so that every tile is resident) runs all the
-// sweeps of the call in epochs of at most `halo` sweeps: at the end of an epoch a tile stores only
-// the core segments its neighbours copy (the `halo` segments next to each core edge, one more on the
-// right for the start knot of the neighbour's outermost copy) into the other state buffer, publishes
-// the epoch in its flag, waits until both neighbours have published theirs, and reloads its halo
-// copies from that buffer.  The halo copies then hold exactly what a fresh launch would load, and
-// the core segments keep their registers, so the results are the same bits as one launch per epoch.
+// sweeps of the call in epochs of at most `halo` sweeps.  At the end of an epoch each wave holding
+// core segments a neighbour copies (the `halo` segments next to each core edge, one more on the
+// right for the start knot of the neighbour's outermost copy) stores them into the other state
+// buffer and counts itself in the tile's flag, one 32-bit count per edge; each wave holding halo
+// copies waits until the edges it copies from have been counted by all of their waves for this
+// epoch, and reloads its copies.  The halo copies then hold exactly what a fresh launch would load,
+// and the core segments keep their registers, so the results are the same bits as one launch per
+// epoch.  No tile-wide barrier is added: the sweep's own barrier keeps a tile's waves together.
 //
-// Ordering of the exchange.  The published values and the flags are written and read only with
+// Ordering of the exchange.  The published values and the counts are written and read only with
 // device-scope atomic accesses (relaxed), which the L2 caches of the chip's dies do not hold
-// incoherently.  A writer's wave waits for its stores to complete before the tile's barrier, and only
-// after that barrier does one thread store the flag; a reader's one polling thread sees the flag
-// before the tile's barrier, and only after it do the waves load the values.  So every value is
-// complete before its flag is written and read only after the flag is seen: the order a release and
-// an acquire would give, without their write-back and invalidation of the whole L2 (which cost more
-// than the launch they replace).
+// incoherently.  A writer wave waits for its stores to complete before one of its lanes adds to the
+// count; a reader wave's polling lane sees the count before the wave issues its loads.  So every
+// value is complete before it is counted and read only after the count is seen: the order a release
+// and an acquire would give, without their write-back and invalidation of the whole L2 (which cost
+// more than the launch they replace).  A buffer is written again two epochs later, after both
+// neighbours have counted the epoch in between, which they do only after their sweeps have used
+// every value they loaded from it.
 #pragma once
 
 #include "sweep_impl.h"
@@ -74,11 +77,13 @@ __device__ __forceinline__ int64_t opaque(int64_t x) {
 // nothing else (expcnt 7, lgkmcnt 15: their maxima, in the GFX9 encoding).
 constexpr int kWaitStores = 0x0F70;
 
-// Wait until tile t has published at least `epochs` epochs; false if the poll bound ran out.  The
-// polls are device-scope atomic loads; every load of the values the flag guards comes after them.
-__device__ inline bool chain_wait(const unsigned long long* flag, int t, unsigned long long epochs, int spin) {
+// Wait until the 32-bit count at bit `shift` of a tile's flag reaches `count`; false if the poll
+// bound ran out.  The polls are device-scope atomic loads; every load of the values the count
+// guards comes after them.
+__device__ inline bool chain_wait(const unsigned long long* flag, int shift, unsigned long long count, int spin) {
   for (int i = 0; i < spin; ++i) {
-    if (__hip_atomic_load(flag + t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= epochs) return true;
+    const unsigned long long f = __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (((f >> shift) & 0xFFFFFFFFull) >= count) return true;
     __builtin_amdgcn_s_sleep(2);
   }
   return false;
@@ -103,7 +108,9 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
   R* sh_g = sh_H + NH * TS;
 
   const int W = A.W;
-  const int a = threadIdx.x / W;          // axis of this lane
+  // axis of this lane, the same for every lane of a wave (W is a multiple of 64): taken as a scalar,
+  // every state field's offset is one scalar for the wave
+  const int a = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
   const int lane = threadIdx.x - a * W;   // segment lane within the tile
   const int64_t base = (int64_t)blockIdx.x * W;
   const int64_t ld = A.k.ld;
@@ -115,8 +122,8 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
   const int wl = lane & 63, wid = lane >> 6, nw = W >> 6;
   auto G = [&](int buf, int ax, int s) -> R& { return sh_g[((buf * 3 + ax) * MV + s) * TS]; };
 
-  // epochs: one, or ceil(iters / chain_halo) in a chained launch, each with a barrier before its
-  // flag and one after the wait that follows (chain: neighbour tiles and the core lane range)
+  // epochs: one, or ceil(iters / chain_halo) in a chained launch (chain: neighbour tiles and the
+  // core lane range)
   const int ep_len = A.chain_halo > 0 ? A.chain_halo : A.iters;
   const int n_ep = A.chain_halo > 0 ? (A.iters + ep_len - 1) / ep_len : 1;
   int dep_l = -1, dep_r = -1, core_lo = 0, core_hi = W;
@@ -132,7 +139,7 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
   for (int h = a; h < NH; h += 3) sh_H[h * TS] = active ? A.k.Hr[h * ld + seg] : R(0);
   if (__ballot(active) == 0) {            // a wave without segments keeps the barrier count
     __syncthreads();
-    for (int it = 0; it < A.iters + 2 * (n_ep - 1); ++it) __syncthreads();
+    for (int it = 0; it < A.iters; ++it) __syncthreads();
     return;
   }
 
@@ -277,37 +284,60 @@ __global__ __launch_bounds__(LB) void sweep_axis_kernel(SweepArgs<R> A) {
     }
     buf ^= 1;
   };
+  // Chained epochs, wave by wave (no tile barrier at an epoch boundary): a wave holding core lanes a
+  // neighbour copies stores them and adds one to the tile's count for that edge (low half of its
+  // flag: left edge, high half: right edge); a wave holding halo copies waits until the count of
+  // every edge it copies from has reached the epoch times the number of waves that export that edge,
+  // then reloads.  The other waves go straight on; the sweep's barrier holds them.
+  const int h = A.chain_halo;
+  const bool exp_l = core && dep_l >= 0 && lane < core_lo + h;
+  const bool exp_r = core && dep_r >= 0 && lane >= core_hi - h - 1;
+  const bool cp_l = active && !core && lane < core_lo;
+  const bool cp_r = active && !core && lane >= core_hi;
+  const unsigned long long add = (__ballot(exp_l) != 0 ? 1ull : 0ull) + (__ballot(exp_r) != 0 ? 1ull << 32 : 0ull);
+  const bool wait_l = __ballot(cp_l) != 0, wait_r = __ballot(cp_r) != 0;
+  // waves (three axes) holding the lanes [lo, hi) of an axis
+  auto waves_over = [](int lo, int hi) { return hi > lo ? 3 * (((hi - 1) >> 6) - (lo >> 6) + 1) : 0; };
+  unsigned long long need_l = 0, need_r = 0, need_own = 0;   // per epoch
+  if (h > 0) {
+    if (wait_l) {   // dep_l's right edge
+      const int lo2 = A.chain[4 * (int64_t)dep_l + 2], hi2 = A.chain[4 * (int64_t)dep_l + 3];
+      need_l = waves_over(max(lo2, hi2 - h - 1), hi2);
+    }
+    if (wait_r) {   // dep_r's left edge, and this tile's right edge (the start knot of the first copy)
+      const int lo2 = A.chain[4 * (int64_t)dep_r + 2], hi2 = A.chain[4 * (int64_t)dep_r + 3];
+      need_r = waves_over(lo2, min(hi2, lo2 + h));
+      need_own = waves_over(max(core_lo, core_hi - h - 1), core_hi);
+    }
+  }
   int left = A.iters;
   for (int e = 0; e < n_ep; ++e) {
-    if (e > 0) {
-      // The neighbours' core edges of the last epoch are in bufs(e): once both have published
-      // them (one thread waits for the tile), the halo copies reload after the barrier.
-      if (threadIdx.x == 0) {
+    if (e > 0 && (wait_l || wait_r)) {
+      // the neighbours' core edges of the last epoch are in bufs(e) once their counts show it
+      if (wl == 0) {
+        const unsigned long long E = (unsigned long long)e;
         bool ok = true;
-        if (dep_l >= 0) ok = chain_wait(A.chain_flag, dep_l, (unsigned long long)e, A.chain_spin);
-        if (ok && dep_r >= 0) ok = chain_wait(A.chain_flag, dep_r, (unsigned long long)e, A.chain_spin);
+        if (wait_l) ok = chain_wait(A.chain_flag + dep_l, 32, E * need_l, A.chain_spin);
+        if (ok && wait_r) ok = chain_wait(A.chain_flag + dep_r, 0, E * need_r, A.chain_spin);
+        if (ok && wait_r) ok = chain_wait(A.chain_flag + blockIdx.x, 32, E * need_own, A.chain_spin);
         if (!ok) atomicOr(A.chain_err, 1);
       }
-      __syncthreads();
-      if (active && !core) load(bufs(e), std::true_type{});
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");   // no load moves above the polls
+      if (cp_l || cp_r) load(bufs(e), std::true_type{});
     }
     const int n = e + 1 < n_ep ? ep_len : left;
     // the call's last sweep (with its outputs) runs after the loop
     const int n_plain = e + 1 == n_ep && A.final_out && n > 0 ? n - 1 : n;
     for (int it = 0; it < n_plain; ++it) sweep(std::false_type{});
     left -= n;
-    if (e + 1 < n_ep) {
+    if (e + 1 < n_ep && add != 0) {
       // publish the core segments the neighbours copy: the chain_halo next to each core edge that
       // has a neighbour, and on the right one more (the start knot of the neighbour's outermost
       // copy is that segment's end knot)
-      const int ln = (int)threadIdx.x % W;
-      if (core && ((dep_l >= 0 && ln < core_lo + A.chain_halo) || (dep_r >= 0 && ln >= core_hi - A.chain_halo - 1)))
-        store(bufs(e + 1), std::true_type{});
+      if (exp_l || exp_r) store(bufs(e + 1), std::true_type{});
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");   // no store moves below the count
       __builtin_amdgcn_s_waitcnt(kWaitStores);   // this wave's exchange stores are complete
-      __syncthreads();
-      if (threadIdx.x == 0)
-        __hip_atomic_store(A.chain_flag + blockIdx.x, (unsigned long long)(e + 1), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+      if (wl == 0) __hip_atomic_fetch_add(A.chain_flag + blockIdx.x, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 
