@@ -149,3 +149,31 @@ def test_iterate_in_a_callers_graph_capture_runs_one_launch_per_epoch():
     finally:
         cap.close()
         ref.close()
+
+
+def test_tuning_times_chained_candidates_on_a_copy():
+    # top_tune runs a candidate that would chain as a chained launch, on a copy of the iterate: the
+    # iterate is untouched, and the solve goes on to the same bits as an untuned handle (the results
+    # do not depend on the tiling)
+    from paper_2507_10290_amd import TopProblem
+    w = random_walk_batch("tunechain", [3000], [11], order=4, precision="fp32")
+    tuned = TopProblem.from_workload(w, precision="fp32")
+    plain = TopProblem.from_workload(w, precision="fp32")
+    try:
+        assert tuned.plan()["lane_form"] == 3
+        tuned.iterate(20)
+        plain.iterate(20)
+        before = tuned.get_state().clone()
+        plan = tuned.tune(40)   # more sweeps than any candidate halo: the axis candidates chain
+        print(f"[chain] tuned plan {plan}", flush=True)
+        assert torch.equal(tuned.get_state(), before)
+        tuned.iterate(40)
+        plain.iterate(40)
+        torch.cuda.synchronize()
+        assert torch.equal(tuned.coeffs(), plain.coeffs())
+        assert torch.equal(tuned.cost(), plain.cost())
+        tuned.sync_status()
+        plain.sync_status()
+    finally:
+        tuned.close()
+        plain.close()
