@@ -97,8 +97,10 @@ typedef struct top_options {
                                 512 for float32 order 3 (closed form with n_cont < 2p-1, or a
                                 polytope corridor), 64 for NumericSolve, 256 otherwise; with a tape
                                 128 (float32) or 64 (float64), the adjoint's tiles.  One lane per
-                                segment and axis (lane_form): 320 (float32) or 128 (float64).  0
-                                picks the maximum (or the tuned value after top_tune)                 */
+                                segment and axis (lane_form 3): 320 (float32) or 128 (float64);
+                                NumericSolve's four lanes per segment: 128 (float32) or 64
+                                (float64).  0 picks the maximum (64 for NumericSolve's four-lane
+                                form), or the tuned value after top_tune                             */
   int32_t halo;              /* sweeps per launch for trajectories longer than a tile (their halo
                                 width); 0 picks the default.  With a tape it must be >= 2: the
                                 reverse pass runs halo - 1 steps per launch                           */
@@ -131,11 +133,13 @@ typedef struct top_options {
                                 (TOP_E_UNSUPPORTED otherwise), as h = ||v||_4 - vmax in g = max{0,h}^2 */
   int32_t lane_form;         /* lanes per segment of the sweep: 1, or 3 (one per axis: three times the
                                 waves, for trajectories longer than a tile; tiles of at most 320
-                                segments; closed form with n_cont < 2p-1, no tape, no checks,
-                                TOP_E_UNSUPPORTED otherwise); 0 picks 3 where allowed and some
-                                trajectory is longer than the largest one-lane tile or, in FP32 with
-                                no tile_lanes given, one lane per segment would make fewer waves
-                                than half the device's SIMDs; else 1 (or the tuned form after
+                                segments; n_cont < 2p-1, no polytope, no tape, no checks,
+                                TOP_E_UNSUPPORTED otherwise; with NumericSolve four lanes, the three
+                                axes and a spare, whose L-BFGS sums are reduced across the four);
+                                0 picks 3 where allowed and either the local update is NumericSolve,
+                                or some trajectory is longer than the largest one-lane tile, or, in
+                                FP32 with no tile_lanes given, one lane per segment would make fewer
+                                waves than half the device's SIMDs; else 1 (or the tuned form after
                                 top_tune)                                                           */
   int32_t chain;             /* 0: where the plan has halo tiles and the device can hold all of them at
                                 once, one top_iterate call runs all its sweeps in one cooperative

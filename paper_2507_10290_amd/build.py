@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libtop.so")
 
-SOURCES = ["sweep_f32.hip", "sweep_f64.hip", "sweep_axis.hip", "poly_f32.hip", "poly_f64.hip", "numeric_f32.hip", "numeric_f64.hip", "adjoint_f32.hip", "adjoint_f64.hip",
+SOURCES = ["sweep_f32.hip", "sweep_f64.hip", "sweep_axis.hip", "poly_f32.hip", "poly_f64.hip", "numeric_f32.hip", "numeric_f64.hip", "numeric_quad_f32.hip", "numeric_quad_f64.hip", "adjoint_f32.hip", "adjoint_f64.hip",
            "setup.hip",
            "finalize.hip", "grad.hip", "adapt.hip", "api.cpp", "solve_static.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -77,8 +77,13 @@ int max_tile(const top::Variant& v, bool taped) {
 }
 
 // Whether the sweep of this variant and these options can run one lane per segment and axis.
+// (NumericSolve takes it as four lanes per segment: three axes and a spare.)
 static bool axis_allowed(const top::Variant& v, const top_options& opt) {
-  return !v.num && !v.faces && v.s != 2 * v.p - 1 && opt.checkpoint_every == 0 && opt.check_every == 0;
+  return !v.faces && v.s != 2 * v.p - 1 && opt.checkpoint_every == 0 && opt.check_every == 0;
+}
+// Largest tile (segments) of that form.
+static int axis_tile_max(const top::Variant& v) {
+  return v.num ? top::num_quad_max_tile(v.prec) : top::axis_max_tile(v.prec);
 }
 
 struct Plan {
@@ -718,7 +723,8 @@ struct top_problem {
       a.rec = (R*)rec;
       a.rec_slot = (int64_t)nf * ld;
     }
-    hipError_t e = v.num     ? top::launch_numeric_sweep<R>(v, a, pl.n_tiles, st)
+    hipError_t e = v.num     ? (axis_of(pl) ? top::launch_numeric_quad<R>(v, a, pl.n_tiles, st)
+                                          : top::launch_numeric_sweep<R>(v, a, pl.n_tiles, st))
                  : v.faces ? top::launch_poly_sweep<R>(v, a, pl.n_tiles, st)
                  : (axis_of(pl) && rec == nullptr) ? top::launch_sweep_axis<R>(v, a, pl.n_tiles, st)
                            : top::launch_sweep<R>(v, a, pl.n_tiles, st);
@@ -795,7 +801,7 @@ struct top_problem {
     TOP_ALLOC(flag_dev, 4 * sizeof(int));   // non-finite, invalid input, chained-launch wait
     // epoch flags of chained launches: one per tile of any plan whose tile cores hold 64 segments
     // or more (the lane-per-axis variants only)
-    chain_cap = axis_allowed(v, opt) ? S / 64 + B + 1 : 0;
+    chain_cap = axis_allowed(v, opt) && !v.num ? S / 64 + B + 1 : 0;
     if (chain_cap > 0) TOP_ALLOC(chain_flag, (size_t)chain_cap * sizeof(unsigned long long));
     TOP_ALLOC(rho_traj, (size_t)B * sizeof(double));
     TOP_ALLOC(chunk_sum, 3 * (size_t)std::max<int64_t>(n_chunks, 1) * sizeof(double));
@@ -1294,8 +1300,8 @@ static top_status resolve_options(const top_options* opt_in, bool box, bool vel,
     return fail(TOP_E_INVALID, "lane_form must be 0, 1 or 3 (got %d)", opt.lane_form);
   if (opt.chain != 0 && opt.chain != 1) return fail(TOP_E_INVALID, "chain must be 0 or 1 (got %d)", opt.chain);
   if (opt.lane_form == 3 && !axis_allowed(v, opt))
-    return fail(TOP_E_UNSUPPORTED, "one lane per axis needs the closed form with n_cont < 2p-1, no polytope, "
-                                   "no tape and no residual checks");
+    return fail(TOP_E_UNSUPPORTED, "one lane per axis needs n_cont < 2p-1, no polytope, no tape and no "
+                                   "residual checks");
   if (opt.halo < 0) return fail(TOP_E_INVALID, "halo must be >= 0");
   if (opt.check_every < 0) return fail(TOP_E_INVALID, "check_every must be >= 0 (got %d)", opt.check_every);
   if (opt.check_every > 0) {
@@ -1379,7 +1385,7 @@ static top_status choose_plan(const top::Variant& v, const top_options& opt, con
     auto it = g_tune.find(shape_key(v, off));
     if (it != g_tune.end()) {
       const TuneChoice& t = it->second;
-      const bool valid = t.form == 3 ? (axis_ok && t.W <= top::axis_max_tile(v.prec)) : t.W <= max_tile(v, taped);
+      const bool valid = t.form == 3 ? (axis_ok && t.W <= axis_tile_max(v)) : t.W <= max_tile(v, taped);
       if (valid) {
         W = t.W;
         form = t.form;
@@ -1388,20 +1394,23 @@ static top_status choose_plan(const top::Variant& v, const top_options& opt, con
     }
   }
   if (form == 0) {
-    // Three lanes per segment where allowed and either some trajectory is longer than a one-lane
+    // NumericSolve: four lanes per segment where allowed (256 batched trajectories, 67,259 segments,
+    // 50 sweeps of 10 L-BFGS iterations: 7.4 against 12.3 ms in float32, 15 against 62 ms in float64).
+    // Closed form: three lanes per segment where allowed and either some trajectory is longer than a one-lane
     // tile, or (float32, no tile width given) one lane per segment would give fewer waves than half
     // the device's SIMDs: a small problem is latency-bound, and three times the waves each with a
     // third of the work finish sooner (a 64-segment trajectory: 0.60 against 1.44 ms for 1,000
     // sweeps; 15,384 segments in 64 trajectories: 0.64 against 0.77 ms for 200; at 67,259 segments,
     // one wave per SIMD with one lane, the one-lane form is ahead, 0.82 against 1.26 ms).
     const bool few_waves = opt.tile_lanes == 0 && v.prec == 0 && (S + 63) / 64 < device_simds() / 2;
-    form = (axis_ok && (longest > max_tile(v, taped) || few_waves)) ? 3 : 1;
+    form = (axis_ok && (v.num || longest > max_tile(v, taped) || few_waves)) ? 3 : 1;
   }
-  const int wmax = form == 3 ? top::axis_max_tile(v.prec) : max_tile(v, taped);
+  const int wmax = form == 3 ? axis_tile_max(v) : max_tile(v, taped);
   if (wmax < 64) return fail(TOP_E_UNSUPPORTED, "the device's per-workgroup LDS is too small for the adjoint kernel");
   if (opt.tile_lanes != 0 && (opt.tile_lanes < 64 || opt.tile_lanes > wmax || opt.tile_lanes % 64 != 0))
     return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, %d] (got %d)", wmax, opt.tile_lanes);
-  if (W == 0) W = wmax;
+  // (NumericSolve's four-lane form: 64-segment tiles, three per CU, ahead of 128-segment ones)
+  if (W == 0) W = (form == 3 && v.num) ? 64 : wmax;
   if (halo == 0) halo = std::max(1, std::min(32, W / 8));
   if (2 * halo >= W) return fail(TOP_E_INVALID, "halo %d too large for %d-lane tiles", halo, W);
   if (taped && halo < 2) {
@@ -1885,7 +1894,7 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   };
   for (int W = 64; W <= max_tile(h->v, h->tape != nullptr); W *= 2) add(W, 1);
   if (h->axis_ok)   // one lane per axis: for long trajectories, and small problems
-    for (int W = 128; W <= top::axis_max_tile(h->v.prec); W += 64) add(W, 3);
+    for (int W = h->v.num ? 64 : 128; W <= axis_tile_max(h->v); W += 64) add(W, 3);
   hipEvent_t e0, e1;
   TOP_HIP(hipEventCreate(&e0));
   TOP_HIP(hipEventCreate(&e1));

@@ -179,6 +179,12 @@ hipError_t launch_poly_sweep(const Variant& v, const SweepArgs<R>& a, int n_tile
 // the same launch with the NumericSolve local update (v.num = 1)
 template <typename R>
 hipError_t launch_numeric_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
+// ... with four lanes per segment (three axes and a spare; 4 W threads per tile of W <=
+// num_quad_max_tile segments)
+constexpr int kNumQuadTileMax = 128;
+constexpr int num_quad_max_tile(int prec) { return prec == 0 ? kNumQuadTileMax : 64; }
+template <typename R>
+hipError_t launch_numeric_quad(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
 
 // One-time setup (precompute + Init), float64 arithmetic, output in R.
 struct SetupArgs {

@@ -76,6 +76,8 @@ def _check_steps(w, inner, Ks, floor, rel, box, norm=2, **kw):
     pr = cadmm.problem_from_workload(w)
     mats = cadmm.segment_matrices(pr)
     prob = _problem(w, inner, vel_norm=norm, **kw)
+    if "lane_form" in kw:
+        assert prob.plan()["lane_form"] == kw["lane_form"]
     done = 0
     worst = 0.0
     for K in Ks:
@@ -99,27 +101,30 @@ def _check_steps(w, inner, Ks, floor, rel, box, norm=2, **kw):
     return worst
 
 
+@pytest.mark.parametrize("lane_form", [1, 3])
 @pytest.mark.parametrize("order,box,vmax,inner", [(3, True, 1.5, 10), (3, False, 1.2, 6), (4, True, 1.5, 8)])
-def test_fp64_numeric_steps_match_oracle(order, box, vmax, inner):
+def test_fp64_numeric_steps_match_oracle(order, box, vmax, inner, lane_form):
     w = random_walk_batch("num", [4, 6, 3], [21, 22, 23], order=order, box=box, vmax=vmax, rho=[1.0, 2.0, 0.5],
                           precision="fp64")
-    _check_steps(w, inner, [0, 3, 8, 14], 1e-10, 1e-14, box)
+    _check_steps(w, inner, [0, 3, 8, 14], 1e-10, 1e-14, box, lane_form=lane_form)
 
 
+@pytest.mark.parametrize("lane_form", [1, 3])
 @pytest.mark.parametrize("order,box,vmax,inner", [(3, True, 1.2, 10), (4, False, 1.0, 8)])
-def test_fp64_numeric_l4_bound_steps_match_oracle(order, box, vmax, inner):
+def test_fp64_numeric_l4_bound_steps_match_oracle(order, box, vmax, inner, lane_form):
     # the l4 speed bound (no closed-form projection): h = ||v||_4 - vmax in the squared hinge
     w = random_walk_batch("numl4", [4, 6, 3], [31, 32, 33], order=order, box=box, vmax=vmax, rho=[1.0, 2.0, 0.5],
                           precision="fp64")
-    _check_steps(w, inner, [0, 3, 8, 14], 1e-10, 1e-14, box, norm=4)
+    _check_steps(w, inner, [0, 3, 8, 14], 1e-10, 1e-14, box, norm=4, lane_form=lane_form)
 
 
-def test_fp64_numeric_l4_first_sweeps_match_oracle_runs():
+@pytest.mark.parametrize("lane_form", [1, 3])
+def test_fp64_numeric_l4_first_sweeps_match_oracle_runs(lane_form):
     w = random_walk_batch("numl4", [4, 6, 3], [31, 32, 33], order=3, vmax=1.2, rho=[1.0, 2.0, 0.5], precision="fp64")
     pr = cadmm.problem_from_workload(w)
     mats = cadmm.segment_matrices(pr)
     for K in (1, 2):
-        prob = _problem(w, 10, vel_norm=4)
+        prob = _problem(w, 10, vel_norm=4, lane_form=lane_form)
         prob.iterate(K)
         c = prob.coeffs().cpu().numpy()
         prob.close()
@@ -132,16 +137,18 @@ def test_fp64_numeric_l4_first_sweeps_match_oracle_runs():
     assert (numeric.velocity_excess(vel, pr.vmax[pr.traj][:, None], 4)[0] > 0).any()
 
 
-def test_fp32_numeric_l4_steps_close_to_oracle():
+@pytest.mark.parametrize("lane_form", [1, 3])
+def test_fp32_numeric_l4_steps_close_to_oracle(lane_form):
     w = random_walk_batch("numl432", [5, 7], [35, 36], order=3, vmax=1.2, rho=1.0, precision="fp32")
-    _check_steps(w, 10, [0, 3], 1e-4, 1e-6, True, norm=4)
+    _check_steps(w, 10, [0, 3], 1e-4, 1e-6, True, norm=4, lane_form=lane_form)
 
 
-def test_fp64_numeric_first_sweeps_match_oracle_runs():
+@pytest.mark.parametrize("lane_form", [1, 3])
+def test_fp64_numeric_first_sweeps_match_oracle_runs(lane_form):
     w = random_walk_batch("num", [4, 6, 3], [21, 22, 23], order=3, vmax=1.5, rho=[1.0, 2.0, 0.5], precision="fp64")
     pr = cadmm.problem_from_workload(w)
     for K, inner in ((1, 10), (2, 10), (5, 0)):
-        prob = _problem(w, inner)
+        prob = _problem(w, inner, lane_form=lane_form)
         prob.iterate(K)
         c, J = prob.coeffs().cpu().numpy(), prob.cost().cpu().numpy()
         prob.close()
@@ -152,19 +159,22 @@ def test_fp64_numeric_first_sweeps_match_oracle_runs():
         assert np.allclose(J, res.J.numpy(), rtol=1e-8)
 
 
-def test_fp64_numeric_steps_on_halo_tiles():
+@pytest.mark.parametrize("lane_form", [1, 3])
+def test_fp64_numeric_steps_on_halo_tiles(lane_form):
     w = random_walk_batch("numhalo", [90], [24], order=3, vmax=1.5, rho=1.0, precision="fp64")
-    _check_steps(w, 6, [0, 5, 11], 1e-10, 1e-14, True, tile_lanes=64, halo=4)
+    _check_steps(w, 6, [0, 5, 11], 1e-10, 1e-14, True, tile_lanes=64, halo=4, lane_form=lane_form)
 
 
-def test_fp32_numeric_steps_close_to_oracle():
+@pytest.mark.parametrize("lane_form", [1, 3])
+def test_fp32_numeric_steps_close_to_oracle(lane_form):
     w = random_walk_batch("num32", [5, 7], [25, 26], order=3, vmax=1.5, rho=1.0, precision="fp32")
-    _check_steps(w, 10, [0, 3], 1e-4, 1e-6, True)
+    _check_steps(w, 10, [0, 3], 1e-4, 1e-6, True, lane_form=lane_form)
 
 
-def test_state_round_trip_and_resume():
+@pytest.mark.parametrize("lane_form", [1, 3])
+def test_state_round_trip_and_resume(lane_form):
     w = random_walk_batch("numrt", [5, 4], [28, 29], order=3, vmax=1.5, precision="fp64")
-    a, b = _problem(w, 8), _problem(w, 8)
+    a, b = _problem(w, 8, lane_form=lane_form), _problem(w, 8, lane_form=lane_form)
     assert a.get_state().shape[1] > a.S and (a.get_state()[:, a.S:] == 0).all()   # padding columns
     a.iterate(6)
     assert (a.get_state()[:, a.S:] == 0).all()
