@@ -305,37 +305,51 @@ typedef struct top_plan_info {
   int32_t lane_form;         /* lanes per segment of the sweep launches: 1 or 3                */
   int32_t chained;           /* 1: an iterate call of more than halo sweeps runs as one chained
                                 launch (see top_options.chain)                                  */
+  int32_t tail_tiles;        /* tiles of the tail launch that follows each sweep launch, one lane
+                                per segment and axis (0: none): when nothing is split and the
+                                tiles would leave a last round of the device holding only a few of
+                                them, those tiles' trajectories run there instead               */
+  int32_t tail_tile_lanes;   /* segments per tail tile                                          */
 } top_plan_info;
 
 top_status top_get_plan(const top_problem* h, top_plan_info* info);
 
 /* Host only (touches no device; for callers that inspect or check the tiling): the tile plan
- * top_create builds for these trajectory lengths at a given tile width and halo, the batching of
+ * top_create builds for these trajectory lengths at a given tile width, halo and tail, the batching of
  * the per-segment solves of one sweep (Sec. III-D.1, Alg. 1: the segments' local updates of an
  * iteration are independent of each other) into workgroup tiles.
  *   n_traj, seg_offsets  as top_create
  *   tile_lanes   segments per tile, a multiple of 64 in [64, 512]
  *   halo         1 <= halo < tile_lanes / 2: segment copies on each side a split trajectory's tile
  *                keeps, and the sweeps per launch
- *   lanes        [host] int32 [n_tiles][tile_lanes], or NULL: per lane its segment (global index),
- *                | TOP_HALO_BIT for a halo copy, -1 for an idle lane.  Trajectories of at most
- *                tile_lanes segments share tiles, packed first-fit in decreasing length; longer ones
- *                run over consecutive tiles whose core segments partition the trajectory
+ *   tiles_per_round  tiles the device holds at once (top_create asks the runtime), or 0 for no tail
+ *   tail_tile_lanes  segments per tail tile, a multiple of 64 in [64, 320] (ignored when
+ *                tiles_per_round is 0).  When no trajectory is split and the last round would hold
+ *                at most tiles_per_round / 8 tiles, those tiles' trajectories are repacked
+ *                (first-fit decreasing) into tail tiles of this width, run by a second launch with
+ *                one lane per segment and axis
+ *   lanes        [host] int32 [n_tiles][tile_lanes] then [tail_tiles][tail_tile_lanes], or NULL: per
+ *                lane its segment (global index), | TOP_HALO_BIT for a halo copy, -1 for an idle
+ *                lane.  Trajectories of at most tile_lanes segments share tiles, packed first-fit
+ *                in decreasing length; longer ones run over consecutive tiles whose core segments
+ *                partition the trajectory
  *   chain        [host] int32 [n_tiles][4], or NULL: per tile the left and right tile holding its halo
  *                copies in their cores (-1 none) and its core lane range [lo, hi); the plan chains
  *                (info->chained = 1) only when every halo copy, and the start knot of its segment,
  *                is in a neighbour's published edge (within halo of a core edge, one more on the
  *                right), else the table is empty
- *   lanes_cap, chain_cap  entries the caller's arrays hold (n_tiles * tile_lanes and 4 * n_tiles
- *                suffice; call once with NULL arrays and read info to size them)
- *   info         [host] tile_lanes, n_tiles, halo (0 if no trajectory is split), n_traj, n_seg,
- *                used_lanes and chained; the other fields are 0
+ *   lanes_cap, chain_cap  entries the caller's arrays hold (n_tiles * tile_lanes + tail_tiles *
+ *                tail_tile_lanes and 4 * n_tiles suffice; call once with NULL arrays and read info
+ *                to size them)
+ *   info         [host] tile_lanes, n_tiles (main launch), halo (0 if no trajectory is split),
+ *                n_traj, n_seg, used_lanes (both launches), chained, tail_tiles and
+ *                tail_tile_lanes; the other fields are 0
  * TOP_E_INVALID for bad offsets or sizes, or arrays smaller than the plan (nothing written to
  * them then). */
 #define TOP_HALO_BIT (1 << 30)
 top_status top_plan_tiles(int32_t n_traj, const int64_t* seg_offsets, int32_t tile_lanes, int32_t halo,
-                          int32_t* lanes, int64_t lanes_cap, int32_t* chain, int64_t chain_cap,
-                          top_plan_info* info);
+                          int32_t tiles_per_round, int32_t tail_tile_lanes, int32_t* lanes, int64_t lanes_cap,
+                          int32_t* chain, int64_t chain_cap, top_plan_info* info);
 
 /* Release the handle; NULL is a no-op.  Handles that captured graphs wait for their stream first;
  * others return at once.  A handle on a caller's workspace leaves the workspace

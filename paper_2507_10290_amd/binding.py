@@ -52,7 +52,8 @@ class TopPlanInfo(ctypes.Structure):
                 ("n_traj", ctypes.c_int32), ("n_seg", ctypes.c_int64), ("used_lanes", ctypes.c_int64),
                 ("precision", ctypes.c_int32), ("order", ctypes.c_int32), ("n_cont", ctypes.c_int32),
                 ("iters_done", ctypes.c_int32), ("n_fields", ctypes.c_int32), ("ld", ctypes.c_int64),
-                ("lane_form", ctypes.c_int32), ("chained", ctypes.c_int32)]
+                ("lane_form", ctypes.c_int32), ("chained", ctypes.c_int32), ("tail_tiles", ctypes.c_int32),
+                ("tail_tile_lanes", ctypes.c_int32)]
 
 
 class TopError(RuntimeError):
@@ -109,7 +110,7 @@ def lib() -> ctypes.CDLL:
     L.top_sync_status.restype = ctypes.c_int
     L.top_get_plan.argtypes = [vp, ctypes.POINTER(TopPlanInfo)]
     L.top_get_plan.restype = ctypes.c_int
-    L.top_plan_tiles.argtypes = [i32, i64p, i32, i32, vp, ctypes.c_int64, vp, ctypes.c_int64,
+    L.top_plan_tiles.argtypes = [i32, i64p, i32, i32, i32, i32, vp, ctypes.c_int64, vp, ctypes.c_int64,
                                  ctypes.POINTER(TopPlanInfo)]
     L.top_plan_tiles.restype = ctypes.c_int
     L.top_destroy.argtypes = [vp]
@@ -267,19 +268,24 @@ def top_get_plan(h: int) -> dict:
 TOP_HALO_BIT = 1 << 30
 
 
-def top_plan_tiles(seg_offsets, tile_lanes: int, halo: int):
+def top_plan_tiles(seg_offsets, tile_lanes: int, halo: int, tiles_per_round: int = 0, tail_tile_lanes: int = 0):
     """Host only: the tile plan for these trajectory lengths (top_plan_tiles).  Returns (info dict,
-    lanes int32 [n_tiles, tile_lanes], chain int32 [n_tiles, 4] or an empty [0, 4] array)."""
+    lanes int32 [n_tiles, tile_lanes], chain int32 [n_tiles, 4] or an empty [0, 4] array, tail lanes
+    int32 [tail_tiles, tail_tile_lanes])."""
     off = np.ascontiguousarray(seg_offsets, dtype=np.int64)
     n_traj = len(off) - 1
     offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     info = TopPlanInfo()
-    _check(lib().top_plan_tiles(n_traj, offp, tile_lanes, halo, None, 0, None, 0, ctypes.byref(info)))
-    lanes = np.empty((info.n_tiles, tile_lanes), dtype=np.int32)
+    _check(lib().top_plan_tiles(n_traj, offp, tile_lanes, halo, tiles_per_round, tail_tile_lanes, None, 0, None, 0,
+                                ctypes.byref(info)))
+    n_main = info.n_tiles * tile_lanes
+    allv = np.empty(n_main + info.tail_tiles * info.tail_tile_lanes, dtype=np.int32)
     chain = np.empty((info.n_tiles if info.chained else 0, 4), dtype=np.int32)
-    _check(lib().top_plan_tiles(n_traj, offp, tile_lanes, halo, lanes.ctypes.data, lanes.size,
-                                chain.ctypes.data, chain.size, ctypes.byref(info)))
-    return {f: getattr(info, f) for f, _ in TopPlanInfo._fields_}, lanes, chain
+    _check(lib().top_plan_tiles(n_traj, offp, tile_lanes, halo, tiles_per_round, tail_tile_lanes, allv.ctypes.data,
+                                allv.size, chain.ctypes.data, chain.size, ctypes.byref(info)))
+    lanes = allv[:n_main].reshape(info.n_tiles, tile_lanes)
+    tail = allv[n_main:].reshape(info.tail_tiles, max(info.tail_tile_lanes, 1))
+    return {f: getattr(info, f) for f, _ in TopPlanInfo._fields_}, lanes, chain, tail
 
 
 def top_destroy(h: int) -> None:

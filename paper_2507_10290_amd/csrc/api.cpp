@@ -85,6 +85,18 @@ static bool axis_allowed(const top::Variant& v, const top_options& opt) {
 static int axis_tile_max(const top::Variant& v) {
   return v.num ? top::num_quad_max_tile(v.prec) : top::axis_max_tile(v.prec);
 }
+// The tail of a plan of W-segment tiles in lane form `form` (see make_plan): the tiles of one round
+// on the current device and the lane-per-axis tile width, or zeros where there is no tail (not the
+// one-lane closed form, or the lane-per-axis kernel cannot take the variant and options).
+static void tail_spec(const top::Variant& v, const top_options& opt, int W, int form, int* round, int* tail_W) {
+  *round = 0;
+  *tail_W = 0;
+  if (form != 1 || v.num || !axis_allowed(v, opt)) return;
+  const int r = v.prec == 0 ? top::sweep_resident<float>(v, W) : top::sweep_resident<double>(v, W);
+  if (r <= 0) return;
+  *round = r;
+  *tail_W = top::axis_max_tile(v.prec);
+}
 
 struct Plan {
   int W = 0;
@@ -96,7 +108,14 @@ struct Plan {
   // holds its halo copies (-1: none) and its core lane range [lo, hi); empty when the plan has no
   // halo or its tiles do not meet the conditions (checked by chain_table).
   std::vector<int32_t> chain;
-  size_t table_elems() const { return lanes.size() + chain.size(); }
+  // Tail launch: when the tiles make a last round that holds only a few of them, the trajectories of
+  // those tiles run in a second launch after the main one, one lane per segment and axis, in tiles
+  // of tail_W segments (segment of each lane, -1 idle), instead of taking a whole round of the main
+  // kernel's time (see make_plan).  Empty: no tail.
+  int tail_W = 0, tail_tiles = 0;
+  std::vector<int32_t> tail;
+  size_t table_elems() const { return lanes.size() + chain.size() + tail.size(); }
+  size_t tail_offset() const { return lanes.size() + chain.size(); }
 };
 
 // The chain table of a plan with halo tiles (see Plan::chain), or empty.  A chained epoch relies
@@ -159,25 +178,20 @@ std::vector<int32_t> chain_table(const Plan& pl, const std::vector<int64_t>& off
   return ch;
 }
 
-// Pack whole trajectories of at most W segments into W-lane tiles (first-fit decreasing); split
-// longer ones into tiles whose core segments are flanked by up to `halo` copied neighbours.
-Plan make_plan(const std::vector<int64_t>& off, int W, int halo) {
-  Plan pl;
-  pl.W = W;
-  const int B = (int)off.size() - 1;
-  std::vector<int> shorts, longs;
-  for (int b = 0; b < B; ++b) ((off[b + 1] - off[b]) <= W ? shorts : longs).push_back(b);
-  std::stable_sort(shorts.begin(), shorts.end(), [&](int x, int y) {
+// Trajectories `items` packed into bins of `cap` segments, first-fit in decreasing length (ties
+// in index order).
+static std::vector<std::vector<int>> pack_ffd(std::vector<int> items, const std::vector<int64_t>& off, int cap) {
+  std::stable_sort(items.begin(), items.end(), [&](int x, int y) {
     return (off[x + 1] - off[x]) > (off[y + 1] - off[y]);
   });
   std::vector<int> fill;
   std::vector<std::vector<int>> bins;
   int first_open = 0;  // bins before this index are full to within the smallest length seen
-  for (int b : shorts) {
+  for (int b : items) {
     const int len = (int)(off[b + 1] - off[b]);
     int k = -1;
     for (int i = first_open; i < (int)bins.size(); ++i)
-      if (fill[i] + len <= W) { k = i; break; }
+      if (fill[i] + len <= cap) { k = i; break; }
     if (k < 0) {
       k = (int)bins.size();
       bins.emplace_back();
@@ -185,7 +199,58 @@ Plan make_plan(const std::vector<int64_t>& off, int W, int halo) {
     }
     bins[k].push_back(b);
     fill[k] += len;
-    while (first_open < (int)bins.size() && fill[first_open] == W) ++first_open;
+    while (first_open < (int)bins.size() && fill[first_open] == cap) ++first_open;
+  }
+  return bins;
+}
+
+// Pack whole trajectories of at most W segments into W-lane tiles (first-fit decreasing); split
+// longer ones into tiles whose cores are flanked by up to `halo` copied neighbours.
+//
+// Tail: tiles run in rounds of `round` (the tiles the device holds at once), each round taking about
+// the same time whatever it holds.  When nothing is split and the last round would hold only a few
+// tiles (k, at most an eighth of a round), the trajectories of k tiles go to a tail plan for the
+// lane-per-axis kernel instead: the k whose longest trajectory is shortest (then the least filled),
+// repacked into tiles as wide as that longest trajectory rounded up to 64 (at most tail_W), which
+// spread over the CUs at a few waves each and finish in a fraction of a round (round = 0: no tail).
+Plan make_plan(const std::vector<int64_t>& off, int W, int halo, int round, int tail_W) {
+  Plan pl;
+  pl.W = W;
+  const int B = (int)off.size() - 1;
+  std::vector<int> shorts, longs;
+  for (int b = 0; b < B; ++b) ((off[b + 1] - off[b]) <= W ? shorts : longs).push_back(b);
+  std::vector<std::vector<int>> bins = pack_ffd(shorts, off, W);
+  std::vector<int> tail_items;
+  int tail_w = 0;
+  if (longs.empty() && round > 0 && tail_W > 0 && (int)bins.size() > round) {
+    const int k = (int)bins.size() % round;
+    if (k > 0 && 8 * k <= round) {
+      std::vector<int> order(bins.size());
+      std::vector<int64_t> longest(bins.size(), 0), fill(bins.size(), 0);
+      for (size_t i = 0; i < bins.size(); ++i) {
+        order[i] = (int)i;
+        for (int b : bins[i]) {
+          longest[i] = std::max(longest[i], off[b + 1] - off[b]);
+          fill[i] += off[b + 1] - off[b];
+        }
+      }
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return longest[x] != longest[y] ? longest[x] < longest[y] : fill[x] < fill[y];
+      });
+      int64_t tl = 0;
+      for (int j = 0; j < k; ++j) tl = std::max(tl, longest[order[j]]);
+      if (tl <= tail_W) {
+        tail_w = (int)((tl + 63) / 64 * 64);
+        std::vector<char> moved(bins.size(), 0);
+        for (int j = 0; j < k; ++j) moved[order[j]] = 1;
+        std::vector<std::vector<int>> kept;
+        for (size_t i = 0; i < bins.size(); ++i) {
+          if (moved[i]) tail_items.insert(tail_items.end(), bins[i].begin(), bins[i].end());
+          else kept.push_back(std::move(bins[i]));
+        }
+        bins = std::move(kept);
+      }
+    }
   }
   for (size_t i = 0; i < bins.size(); ++i) {
     std::vector<int32_t> t(W, -1);
@@ -194,6 +259,18 @@ Plan make_plan(const std::vector<int64_t>& off, int W, int halo) {
       for (int64_t s = off[b]; s < off[b + 1]; ++s) t[pos++] = (int32_t)s;
     pl.used += pos;
     pl.lanes.insert(pl.lanes.end(), t.begin(), t.end());
+  }
+  if (!tail_items.empty()) {
+    for (const std::vector<int>& bin : pack_ffd(tail_items, off, tail_w)) {
+      std::vector<int32_t> t(tail_w, -1);
+      int pos = 0;
+      for (int b : bin)
+        for (int64_t s = off[b]; s < off[b + 1]; ++s) t[pos++] = (int32_t)s;
+      pl.used += pos;
+      pl.tail.insert(pl.tail.end(), t.begin(), t.end());
+    }
+    pl.tail_W = tail_w;
+    pl.tail_tiles = (int)(pl.tail.size() / tail_w);
   }
   if (!longs.empty()) pl.halo = halo;
   for (int b : longs) {
@@ -372,15 +449,30 @@ uint64_t offsets_hash(const std::vector<int64_t>& off, std::initializer_list<int
   return h;
 }
 
-uint64_t plan_key(const std::vector<int64_t>& off, int W, int halo, int device) {
-  return offsets_hash(off, {W, halo, device});
+uint64_t plan_key(const std::vector<int64_t>& off, int W, int halo, int round, int tail_W, int device) {
+  return offsets_hash(off, {W, halo, round, tail_W, device});
 }
 
-// The cached plan of this shape, building and uploading it on first use.
-top_status get_plan(const std::vector<int64_t>& off, int W, int halo, std::shared_ptr<PlanEntry>* out) {
+// Copy the tables of plan pl (lane map, chain table, tail lane map) to dst, in that order.
+hipError_t upload_plan(const Plan& pl, int32_t* dst, hipStream_t st, bool async) {
+  auto put = [&](size_t at, const std::vector<int32_t>& v) -> hipError_t {
+    if (v.empty()) return hipSuccess;
+    return async ? hipMemcpyAsync(dst + at, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice, st)
+                 : hipMemcpy(dst + at, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+  };
+  hipError_t e = put(0, pl.lanes);
+  if (e == hipSuccess) e = put(pl.lanes.size(), pl.chain);
+  if (e == hipSuccess) e = put(pl.tail_offset(), pl.tail);
+  return e;
+}
+
+// The cached plan of this shape, building and uploading it on first use (round, tail_W: see
+// make_plan).
+top_status get_plan(const std::vector<int64_t>& off, int W, int halo, int round, int tail_W,
+                    std::shared_ptr<PlanEntry>* out) {
   int dev = 0;
   TOP_HIP(hipGetDevice(&dev));
-  const uint64_t key = plan_key(off, W, halo, dev);
+  const uint64_t key = plan_key(off, W, halo, round, tail_W, dev);
   {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     auto it = g_plans.find(key);
@@ -390,19 +482,15 @@ top_status get_plan(const std::vector<int64_t>& off, int W, int halo, std::share
     }
   }
   auto e = std::make_shared<PlanEntry>();
-  e->plan = make_plan(off, W, halo);
+  e->plan = make_plan(off, W, halo, round, tail_W);
   e->off = off;
   e->device = dev;
-  // the lane map, then the chain table
   const size_t bytes = e->plan.table_elems() * sizeof(int32_t);
   void* q = nullptr;
   hipError_t he = hipMalloc(&q, bytes);
   if (he != hipSuccess) return fail(TOP_E_NOMEM, "hipMalloc(%zu) for the lane map failed", bytes);
   e->dev = static_cast<int32_t*>(q);
-  he = hipMemcpy(e->dev, e->plan.lanes.data(), e->plan.lanes.size() * sizeof(int32_t), hipMemcpyHostToDevice);
-  if (he == hipSuccess && !e->plan.chain.empty())
-    he = hipMemcpy(e->dev + e->plan.lanes.size(), e->plan.chain.data(), e->plan.chain.size() * sizeof(int32_t),
-                   hipMemcpyHostToDevice);
+  he = upload_plan(e->plan, e->dev, nullptr, false);
   if (he != hipSuccess) return fail(TOP_E_HIP, "lane map upload failed: %s", hipGetErrorString(he));
   std::lock_guard<std::mutex> lk(g_plan_mu);
   // keep at most 16 shapes; drop the ones no handle uses any more
@@ -728,6 +816,16 @@ struct top_problem {
                  : v.faces ? top::launch_poly_sweep<R>(v, a, pl.n_tiles, st)
                  : (axis_of(pl) && rec == nullptr) ? top::launch_sweep_axis<R>(v, a, pl.n_tiles, st)
                            : top::launch_sweep<R>(v, a, pl.n_tiles, st);
+    if (e == hipSuccess && pl.tail_tiles > 0) {
+      // the tail's trajectories: the same sweeps, one lane per segment and axis (the plan has a tail
+      // only where that kernel takes the variant; no tape, no checks, nothing split)
+      if (rec != nullptr || a.done != nullptr || chain)
+        return fail(TOP_E_STATE, "a plan with a tail launch cannot record, check or chain");
+      top::SweepArgs<R> t = a;
+      t.lane_seg = lane_map + pl.tail_offset();
+      t.W = pl.tail_W;
+      e = top::launch_sweep_axis<R>(v, t, pl.tail_tiles, st);
+    }
     if (e != hipSuccess) return fail(TOP_E_HIP, "sweep launch failed: %s", hipGetErrorString(e));
     return TOP_OK;
   }
@@ -1463,7 +1561,9 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   int W = 0, halo = 0, form = 0;
   if ((st = choose_plan(v, opt, off, taped, &W, &halo, &form)) != TOP_OK) return st;
   Plan own_plan;
-  if (mem == Mem::kStatic) own_plan = make_plan(off, W, halo);
+  int round = 0, tail_W = 0;
+  tail_spec(v, opt, W, form, &round, &tail_W);
+  if (mem == Mem::kStatic) own_plan = make_plan(off, W, halo, round, tail_W);
   // The workspace must hold this problem's buffers (checked before any device work).
   size_t ws_pad = 0;
   const int64_t n_chunks = count_chunks(seg_offsets, n_traj);
@@ -1545,12 +1645,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     if (e == hipSuccess && !h->own_chunk_traj.empty())
       e = hipMemcpyAsync(const_cast<int32_t*>(h->chunk_traj), h->own_chunk_traj.data(),
                          h->own_chunk_traj.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(h->own_lanes, h->own_plan.lanes.data(), h->own_plan.lanes.size() * sizeof(int32_t),
-                         hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess && !h->own_plan.chain.empty())
-      e = hipMemcpyAsync(h->own_lanes + h->own_plan.lanes.size(), h->own_plan.chain.data(),
-                         h->own_plan.chain.size() * sizeof(int32_t), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = upload_plan(h->own_plan, h->own_lanes, stream, true);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "table upload failed: %s", hipGetErrorString(e)));
   }
   if (opt.check_every > 0) {
@@ -1620,7 +1715,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     hipError_t e = hipMemcpyAsync(h->tape, h->state[0], (size_t)h->nf * ld * R, hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "tape copy failed: %s", hipGetErrorString(e)));
   }
-  if (mem != Mem::kStatic && (st = get_plan(h->off, W, halo, &h->pe)) != TOP_OK) return bail(st);
+  if (mem != Mem::kStatic && (st = get_plan(h->off, W, halo, round, tail_W, &h->pe)) != TOP_OK) return bail(st);
   // the input check's verdict
   int bad = 0;
   {
@@ -1824,12 +1919,14 @@ top_status top_get_plan(const top_problem* h, top_plan_info* info) {
   info->ld = h->ld;
   info->lane_form = h->axis ? 3 : 1;
   info->chained = const_cast<top_problem*>(h)->can_chain() ? 1 : 0;
+  info->tail_tiles = h->plan_ref().tail_tiles;
+  info->tail_tile_lanes = h->plan_ref().tail_W;
   return TOP_OK;
 }
 
 top_status top_plan_tiles(int32_t n_traj, const int64_t* seg_offsets, int32_t tile_lanes, int32_t halo,
-                          int32_t* lanes, int64_t lanes_cap, int32_t* chain, int64_t chain_cap,
-                          top_plan_info* info) {
+                          int32_t tiles_per_round, int32_t tail_tile_lanes, int32_t* lanes, int64_t lanes_cap,
+                          int32_t* chain, int64_t chain_cap, top_plan_info* info) {
   if (n_traj <= 0 || seg_offsets == nullptr || info == nullptr)
     return fail(TOP_E_INVALID, "n_traj > 0, seg_offsets and info are required");
   if (seg_offsets[0] != 0) return fail(TOP_E_INVALID, "seg_offsets[0] must be 0");
@@ -1842,10 +1939,15 @@ top_status top_plan_tiles(int32_t n_traj, const int64_t* seg_offsets, int32_t ti
     return fail(TOP_E_INVALID, "tile_lanes must be a multiple of 64 in [64, 512] (got %d)", tile_lanes);
   if (halo < 1 || 2 * halo >= tile_lanes)
     return fail(TOP_E_INVALID, "halo must be in [1, tile_lanes / 2) (got %d for %d-lane tiles)", halo, tile_lanes);
+  if (tiles_per_round < 0 || (tiles_per_round > 0 && (tail_tile_lanes < 64 || tail_tile_lanes > top::kAxisTileMax ||
+                                                      tail_tile_lanes % 64 != 0)))
+    return fail(TOP_E_INVALID, "tiles_per_round must be >= 0, and with it tail_tile_lanes a multiple of 64 in [64, %d]",
+                top::kAxisTileMax);
   const std::vector<int64_t> off(seg_offsets, seg_offsets + n_traj + 1);
-  const Plan pl = make_plan(off, tile_lanes, halo);
-  if (lanes != nullptr && lanes_cap < (int64_t)pl.lanes.size())
-    return fail(TOP_E_INVALID, "lanes holds %lld entries; the plan has %zu", (long long)lanes_cap, pl.lanes.size());
+  const Plan pl = make_plan(off, tile_lanes, halo, tiles_per_round, tiles_per_round > 0 ? tail_tile_lanes : 0);
+  const size_t n_lanes = pl.lanes.size() + pl.tail.size();
+  if (lanes != nullptr && lanes_cap < (int64_t)n_lanes)
+    return fail(TOP_E_INVALID, "lanes holds %lld entries; the plan has %zu", (long long)lanes_cap, n_lanes);
   if (chain != nullptr && chain_cap < (int64_t)pl.chain.size())
     return fail(TOP_E_INVALID, "chain holds %lld entries; the plan has %zu", (long long)chain_cap, pl.chain.size());
   *info = top_plan_info{};
@@ -1856,7 +1958,12 @@ top_status top_plan_tiles(int32_t n_traj, const int64_t* seg_offsets, int32_t ti
   info->n_seg = S;
   info->used_lanes = pl.used;
   info->chained = pl.chain.empty() ? 0 : 1;
-  if (lanes != nullptr) std::copy(pl.lanes.begin(), pl.lanes.end(), lanes);
+  info->tail_tiles = pl.tail_tiles;
+  info->tail_tile_lanes = pl.tail_W;
+  if (lanes != nullptr) {
+    std::copy(pl.lanes.begin(), pl.lanes.end(), lanes);
+    std::copy(pl.tail.begin(), pl.tail.end(), lanes + pl.lanes.size());
+  }
   if (chain != nullptr) std::copy(pl.chain.begin(), pl.chain.end(), chain);
   return TOP_OK;
 }
@@ -1910,7 +2017,9 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   int probe_dev = 0;
   for (const TuneChoice& c : cands) {
     std::shared_ptr<PlanEntry> cand;
-    s = get_plan(h->off, c.W, c.halo > 0 ? c.halo : 1, &cand);
+    int round = 0, tail_W = 0;
+    tail_spec(h->v, h->opt, c.W, c.form, &round, &tail_W);
+    s = get_plan(h->off, c.W, c.halo > 0 ? c.halo : 1, round, tail_W, &cand);
     if (s != TOP_OK) break;
     const Plan& pl = cand->plan;
     h->probe_plan = &pl;
@@ -1979,7 +2088,10 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s != TOP_OK) return s;
-  s = get_plan(h->off, bestc.W, bestc.halo > 0 ? bestc.halo : std::max(1, std::min(32, bestc.W / 8)), &h->pe);
+  int round = 0, tail_W = 0;
+  tail_spec(h->v, h->opt, bestc.W, bestc.form, &round, &tail_W);
+  s = get_plan(h->off, bestc.W, bestc.halo > 0 ? bestc.halo : std::max(1, std::min(32, bestc.W / 8)), round, tail_W,
+               &h->pe);
   if (s != TOP_OK) return s;
   h->axis = bestc.form == 3;
   h->drop_graphs();

@@ -159,6 +159,9 @@ struct Variant {
 
 template <typename R>
 hipError_t launch_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
+// Tiles of W lanes of that sweep (one lane per segment) the device holds at once, or 0.
+template <typename R>
+int sweep_resident(const Variant& v, int W);
 // the same sweep with one lane per segment and axis (3 W threads per tile of W <= axis_max_tile
 // segments; closed form with s < 2p - 1, no recording, no stopped trajectories).  Float32 tiles go
 // to 320 segments (960 lanes at four waves per SIMD, 128 VGPRs); float64 ones to 128, so that the

@@ -10,4 +10,9 @@ hipError_t launch_sweep<float>(const Variant& v, const SweepArgs<float>& a, int 
   return dispatch_sweep<float, 512, 256>(v, a, n_tiles, st);
 }
 
+template <>
+int sweep_resident<float>(const Variant& v, int W) {
+  return resident_sweep<float, 512, 256>(v, W);
+}
+
 }  // namespace top

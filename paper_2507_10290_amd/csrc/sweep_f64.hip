@@ -9,4 +9,9 @@ hipError_t launch_sweep<double>(const Variant& v, const SweepArgs<double>& a, in
   return dispatch_sweep<double, 256, 256>(v, a, n_tiles, st);
 }
 
+template <>
+int sweep_resident<double>(const Variant& v, int W) {
+  return resident_sweep<double, 256, 256>(v, W);
+}
+
 }  // namespace top

@@ -568,6 +568,39 @@ hipError_t dispatch_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, 
   return hipErrorInvalidValue;
 }
 
+// The (non-recording) kernel instance dispatch_sweep launches for variant v, or nullptr.
+template <typename R, int LB3, int LB4>
+void* sweep_instance(const Variant& v) {
+  if (v.faces || v.num) return nullptr;
+  const bool full = v.s == 2 * v.p - 1;
+#define TOP_SWEEP_I(P_, S_, B_, V_, LB_)                                                      \
+  if (v.p == P_ && v.s == S_ && (v.box != 0) == B_ && (v.vel != 0) == V_)                   \
+    return reinterpret_cast<void*>(sweep_kernel<R, P_, S_, B_, V_, LB_>);
+#define TOP_SWEEP_IPS(P_, S_, LB_)                                                            \
+  TOP_SWEEP_I(P_, S_, true, true, LB_) TOP_SWEEP_I(P_, S_, true, false, LB_)                 \
+  TOP_SWEEP_I(P_, S_, false, true, LB_) TOP_SWEEP_I(P_, S_, false, false, LB_)
+  if (!full) {
+    TOP_SWEEP_IPS(3, 3, LB3) TOP_SWEEP_IPS(3, 4, LB3) TOP_SWEEP_IPS(4, 4, LB4) TOP_SWEEP_IPS(4, 5, LB4)
+  } else {
+    TOP_SWEEP_IPS(3, 5, 256) TOP_SWEEP_IPS(4, 7, 256)
+  }
+#undef TOP_SWEEP_IPS
+#undef TOP_SWEEP_I
+  return nullptr;
+}
+
+// Tiles of W lanes of that instance the device holds at once (0 if the runtime does not say).
+template <typename R, int LB3, int LB4>
+int resident_sweep(const Variant& v, int W) {
+  void* k = sweep_instance<R, LB3, LB4>(v);
+  if (k == nullptr || W <= 0) return 0;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, W, 0) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
 // Largest tile the kernel of this variant accepts.
 inline int max_tile_lanes(const Variant& v) {
   return (v.prec == 0 && v.p == 3 && v.s != 2 * v.p - 1) ? 512 : 256;

@@ -432,3 +432,33 @@ def test_invalid_device_inputs_are_rejected():
     with pytest.raises(TopError, match="TOP_E_STATE"):
         prob.residuals()
     prob.close()
+
+
+def test_tail_launch_gives_the_same_bits():
+    # The batched workload packs into 2,056 tiles of 512 segments; a device that holds 256 at once
+    # would run the last 8 in a round of their own, so their trajectories go to a tail launch with
+    # one lane per segment and axis.  The results are the bits of the lane-per-axis plan (no tail).
+    from paper_2507_10290_amd import TopProblem
+    w = make_config(3)
+    tail = TopProblem.from_workload(w, precision="fp32")
+    ref = TopProblem.from_workload(w, precision="fp32", lane_form=3)
+    try:
+        plan = tail.plan()
+        print(f"[tail] plan {plan}", flush=True)
+        assert plan["lane_form"] == 1 and plan["tail_tiles"] > 0
+        assert plan["tail_tile_lanes"] % 64 == 0 and 64 <= plan["tail_tile_lanes"] <= 320
+        assert ref.plan()["tail_tiles"] == 0
+        for k in (20, 7):
+            tail.iterate(k)
+            ref.iterate(k)
+            torch.cuda.synchronize()
+            assert torch.equal(tail.coeffs(), ref.coeffs()), k
+            assert torch.equal(tail.cost(), ref.cost()), k
+            for x, y in zip(tail.residuals(), ref.residuals()):
+                assert torch.equal(x, y), k
+        assert torch.equal(tail.get_state(), ref.get_state())
+        tail.sync_status()
+        ref.sync_status()
+    finally:
+        tail.close()
+        ref.close()

@@ -30,7 +30,8 @@ def _offsets(lengths):
 def _check_plan(lengths, W, halo):
     off = _offsets(lengths)
     S = int(off[-1])
-    info, lanes, chain = top_plan_tiles(off, W, halo)
+    info, lanes, chain, tail = top_plan_tiles(off, W, halo)
+    assert info["tail_tiles"] == 0 and tail.shape[0] == 0
     assert info["tile_lanes"] == W and info["n_seg"] == S and info["n_traj"] == len(lengths)
     assert lanes.shape == (info["n_tiles"], W)
     assert info["used_lanes"] == int((lanes >= 0).sum())
@@ -227,10 +228,86 @@ def test_argument_errors():
     off = _offsets([100])
     offp = off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))
     info = binding.TopPlanInfo()
-    assert L.top_plan_tiles(1, offp, 64, 8, None, 0, None, 0, ctypes.byref(info)) == 0
+    assert L.top_plan_tiles(1, offp, 64, 8, 0, 0, None, 0, None, 0, ctypes.byref(info)) == 0
     lanes = np.full(info.n_tiles * 64 - 1, 7, dtype=np.int32)
-    assert L.top_plan_tiles(1, offp, 64, 8, lanes.ctypes.data, lanes.size, None, 0, ctypes.byref(info)) == TOP_E_INVALID
+    assert L.top_plan_tiles(1, offp, 64, 8, 0, 0, lanes.ctypes.data, lanes.size, None, 0,
+                            ctypes.byref(info)) == TOP_E_INVALID
     assert (lanes == 7).all()
     chain = np.full(4 * info.n_tiles - 1, 7, dtype=np.int32)
-    assert L.top_plan_tiles(1, offp, 64, 8, None, 0, chain.ctypes.data, chain.size, ctypes.byref(info)) == TOP_E_INVALID
+    assert L.top_plan_tiles(1, offp, 64, 8, 0, 0, None, 0, chain.ctypes.data, chain.size,
+                            ctypes.byref(info)) == TOP_E_INVALID
     assert (chain == 7).all()
+
+
+def _batched_lengths(n=4096):
+    # the batched workload's trajectory lengths: uniform in [8, 512]
+    return [int(x) for x in np.random.Generator(np.random.PCG64(3)).integers(8, 512, size=n, endpoint=True)[:n]]
+
+
+def test_tail_split():
+    # 4,096 trajectories make 2,056 tiles of 512: eight rounds of 256 tiles and a ninth of 8.  With a
+    # tail, the main plan keeps 2,048 of the tiles (in order); the trajectories of the other 8 --
+    # those whose longest trajectory is shortest, then the least filled -- are repacked first-fit
+    # decreasing into tail tiles as wide as that longest trajectory rounded up to 64.
+    lengths = _batched_lengths()
+    off = _offsets(lengths)
+    base, blanes, _, _ = top_plan_tiles(off, 512, 32)
+    info, lanes, chain, tail = top_plan_tiles(off, 512, 32, 256, 320)
+    assert base["n_tiles"] == 2056 and info["n_tiles"] == 2048
+    assert info["used_lanes"] == int((lanes >= 0).sum() + (tail >= 0).sum()) == off[-1]
+    traj_of = np.repeat(np.arange(len(lengths)), lengths)
+    # the kept tiles are base tiles, in order
+    key = lambda row: (max(lengths[b] for b in np.unique(traj_of[row[row >= 0]])), int((row >= 0).sum()))
+    kept, j = [], 0
+    for i in range(base["n_tiles"]):
+        if j < info["n_tiles"] and np.array_equal(blanes[i], lanes[j]):
+            kept.append(i)
+            j += 1
+    assert j == info["n_tiles"]
+    moved = sorted(set(range(base["n_tiles"])) - set(kept))
+    assert len(moved) == 8
+    assert max(key(blanes[i]) for i in moved) <= min(key(blanes[i]) for i in kept)
+    # the tail holds exactly the moved tiles' trajectories, whole and in order
+    msegs = np.concatenate([blanes[i][blanes[i] >= 0] for i in moved])
+    assert np.array_equal(np.sort(tail[tail >= 0]), np.sort(msegs))
+    longest = max(key(blanes[i])[0] for i in moved)
+    assert info["tail_tile_lanes"] == (longest + 63) // 64 * 64 and tail.shape == (info["tail_tiles"], info["tail_tile_lanes"])
+    fill = []
+    for row in tail:
+        n = int((row >= 0).sum())
+        assert (row[:n] >= 0).all() and (row[n:] < 0).all() and not (row[:n] & TOP_HALO_BIT).any()
+        for b in np.unique(traj_of[row[:n]]):
+            seg = row[:n][traj_of[row[:n]] == b]
+            assert len(seg) == lengths[b] and (np.diff(seg) == 1).all()
+        fill.append(n)
+    assert sum(2 * f <= info["tail_tile_lanes"] for f in fill) <= 1   # first fit: at most one half-full tile
+
+
+@pytest.mark.parametrize("case", ["exact", "too_many", "split", "long_tail", "no_round"])
+def test_no_tail_split(case):
+    lengths = _batched_lengths(4080)                       # exactly 2,048 tiles of 512
+    W, halo, rnd, tw = 512, 32, 256, 320
+    if case == "too_many":
+        lengths = _batched_lengths(4096)
+        rnd = 32                                           # 2,056 = 64 rounds of 32 and 8: a quarter round
+    elif case == "split":
+        lengths = _batched_lengths(4096) + [2000]          # a trajectory longer than a tile: halo tiles
+    elif case == "long_tail":
+        lengths = _batched_lengths(4096)
+        tw = 64                                            # the tail's trajectories do not fit its tiles
+    elif case == "no_round":
+        lengths = _batched_lengths(4096)
+        rnd = 0
+    off = _offsets(lengths)
+    base, blanes, _, _ = top_plan_tiles(off, W, halo)
+    info, lanes, _, tail = top_plan_tiles(off, W, halo, rnd, tw)
+    assert info["tail_tiles"] == 0 and tail.shape[0] == 0
+    assert info["n_tiles"] == base["n_tiles"] and np.array_equal(lanes, blanes)
+
+
+def test_tail_argument_errors():
+    off = _offsets([10, 20])
+    for rnd, tw in [(-1, 320), (4, 0), (4, 96), (4, 384)]:
+        with pytest.raises(TopError) as ei:
+            top_plan_tiles(off, 64, 8, rnd, tw)
+        assert ei.value.status == TOP_E_INVALID, (rnd, tw)
