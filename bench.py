@@ -106,6 +106,8 @@ def sweep_kernel_ms(w, d, K, reps=3, precision="fp32"):
     prob = _problem(w, d, precision=precision)
     plan = prob.plan()
     launches = 1 if plan["halo"] == 0 or plan["chained"] else -(-K // plan["halo"])
+    if plan.get("tail_tiles", 0) > 0:
+        launches *= 2                         # each sweep launch is followed by its tail launch
     prob.time_sweeps(K)                       # warm-up
     ms = [prob.time_sweeps(K) for _ in range(reps)]
     prob.close()
@@ -558,13 +560,18 @@ def main():
     kms, launches, plan = sweep_kernel_ms(w, d, K)
     fpu = flops_per_update(w.order, w.n_cont, w.n_samples, True, True)
     bpu = bytes_per_update(w.order, w.n_cont, w.n_samples, True, True)
-    per_launch_ms = kms / launches
+    # with a tail launch the sweep of a step is two kernels (the plan's tiles, then the tail's
+    # lane-per-axis tiles): the roofline takes both, timed together
+    tail = plan.get("tail_tiles", 0) > 0
+    per_launch_ms = kms / (launches // 2 if tail else launches)
     achieved = fpu * w.n_seg * K / (kms * 1e-3)
     sweep_rate = w.n_seg * K / (kms * 1e-3)
     roofline = {"bound": "alu", "achieved": round(achieved / 1e12, 3), "peak": round(PEAK_FP32_NONPACKED / 1e12, 1),
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_NONPACKED, 4), "traffic": stored_traffic(),
-                "kernel": "sweep_kernel<float,3,3,box,vel,512>", "flops_per_segment_update": fpu,
-                "launch_ms": round(per_launch_ms, 4), "launches_per_step": launches,
+                "kernel": "sweep_kernel<float,3,3,box,vel,512>"
+                          + (" + tail sweep_axis_kernel<float,3,3,box,vel,960>" if tail else ""),
+                "flops_per_segment_update": fpu, "launch_ms": round(per_launch_ms, 4), "launches_per_step": launches,
+                "tail_tiles": plan.get("tail_tiles", 0),
                 "frac_of_packed_fp32_peak": round(achieved / PEAK_FP32_PACKED, 4)}
 
     line = {"metric": "CADMM segment-updates/sec and % HBM peak, batched vs plain, fwd+bwd, 1 MI355X",
