@@ -305,10 +305,12 @@ typedef struct top_plan_info {
   int32_t lane_form;         /* lanes per segment of the sweep launches: 1 or 3                */
   int32_t chained;           /* 1: an iterate call of more than halo sweeps runs as one chained
                                 launch (see top_options.chain)                                  */
-  int32_t tail_tiles;        /* tiles of the tail launch that follows each sweep launch, one lane
-                                per segment and axis (0: none): when nothing is split and the
-                                tiles would leave a last round of the device holding only a few of
-                                them, those tiles' trajectories run there instead               */
+  int32_t tail_tiles;        /* tiles of the tail launch that follows each sweep launch (0: none):
+                                when nothing is split and the tiles would leave a last round of
+                                the device holding only a few of them, those tiles' trajectories
+                                run there instead, one lane per segment and axis where that form
+                                takes the variant and options, else in the plan's own form on
+                                tiles of at most half the width; not with a tape or NumericSolve */
   int32_t tail_tile_lanes;   /* segments per tail tile                                          */
 } top_plan_info;
 

@@ -81,21 +81,35 @@ int max_tile(const top::Variant& v, bool taped) {
 static bool axis_allowed(const top::Variant& v, const top_options& opt) {
   return !v.faces && v.s != 2 * v.p - 1 && opt.checkpoint_every == 0 && opt.check_every == 0;
 }
+// The tail launch of a plan (see make_plan): the tiles of one round, the tail tile width, its form.
+struct TailSpec {
+  int round = 0, W = 0, form = 0;
+};
+
 // Largest tile (segments) of that form.
 static int axis_tile_max(const top::Variant& v) {
   return v.num ? top::num_quad_max_tile(v.prec) : top::axis_max_tile(v.prec);
 }
-// The tail of a plan of W-segment tiles in lane form `form` (see make_plan): the tiles of one round
-// on the current device and the lane-per-axis tile width, or zeros where there is no tail (not the
-// one-lane closed form, or the lane-per-axis kernel cannot take the variant and options).
-static void tail_spec(const top::Variant& v, const top_options& opt, int W, int form, int* round, int* tail_W) {
-  *round = 0;
-  *tail_W = 0;
-  if (form != 1 || v.num || !axis_allowed(v, opt)) return;
-  const int r = v.prec == 0 ? top::sweep_resident<float>(v, W) : top::sweep_resident<double>(v, W);
-  if (r <= 0) return;
-  *round = r;
-  *tail_W = top::axis_max_tile(v.prec);
+// The tail of a plan of W-segment tiles in lane form `form` (see make_plan), or none (one lane per
+// segment and axis already, NumericSolve, a tape, or the runtime does not say how many tiles the
+// device holds): the lane-per-axis kernel where it takes the variant and options, with tiles of up
+// to its maximum; else the main kernel itself with tiles of at most W / 2 segments (half the waves).
+static TailSpec tail_spec(const top::Variant& v, const top_options& opt, int W, int form) {
+  TailSpec t;
+  if (form != 1 || v.num || opt.checkpoint_every > 0) return t;
+  const int r = v.faces ? (v.prec == 0 ? top::poly_resident<float>(v, W) : top::poly_resident<double>(v, W))
+                        : (v.prec == 0 ? top::sweep_resident<float>(v, W) : top::sweep_resident<double>(v, W));
+  if (r <= 0) return t;
+  t.round = r;
+  if (axis_allowed(v, opt)) {
+    t.W = top::axis_max_tile(v.prec);
+    t.form = 3;
+  } else {
+    t.W = W / 2 >= 64 ? W / 2 / 64 * 64 : 0;
+    t.form = 1;
+    if (t.W == 0) t.round = 0;
+  }
+  return t;
 }
 
 struct Plan {
@@ -113,6 +127,7 @@ struct Plan {
   // of tail_W segments (segment of each lane, -1 idle), instead of taking a whole round of the main
   // kernel's time (see make_plan).  Empty: no tail.
   int tail_W = 0, tail_tiles = 0;
+  int tail_form = 0;   // 3: one lane per segment and axis; 1: the main kernel's own form, smaller tiles
   std::vector<int32_t> tail;
   size_t table_elems() const { return lanes.size() + chain.size() + tail.size(); }
   size_t tail_offset() const { return lanes.size() + chain.size(); }
@@ -209,11 +224,12 @@ static std::vector<std::vector<int>> pack_ffd(std::vector<int> items, const std:
 //
 // Tail: tiles run in rounds of `round` (the tiles the device holds at once), each round taking about
 // the same time whatever it holds.  When nothing is split and the last round would hold only a few
-// tiles (k, at most an eighth of a round), the trajectories of k tiles go to a tail plan for the
-// lane-per-axis kernel instead: the k whose longest trajectory is shortest (then the least filled),
-// repacked into tiles as wide as that longest trajectory rounded up to 64 (at most tail_W), which
-// spread over the CUs at a few waves each and finish in a fraction of a round (round = 0: no tail).
-Plan make_plan(const std::vector<int64_t>& off, int W, int halo, int round, int tail_W) {
+// tiles (k, at most an eighth of a round), the trajectories of k tiles go to a tail plan instead:
+// the k whose longest trajectory is shortest (then the least filled), repacked into tiles as wide as
+// that longest trajectory rounded up to 64 (at most tail_W), which spread over the CUs with fewer
+// waves each and finish in a fraction of a round (round = 0: no tail).  tail_form says which kernel
+// runs them (3: one lane per segment and axis; 1: the main kernel with the narrower tiles).
+Plan make_plan(const std::vector<int64_t>& off, int W, int halo, int round, int tail_W, int tail_form) {
   Plan pl;
   pl.W = W;
   const int B = (int)off.size() - 1;
@@ -271,6 +287,7 @@ Plan make_plan(const std::vector<int64_t>& off, int W, int halo, int round, int 
     }
     pl.tail_W = tail_w;
     pl.tail_tiles = (int)(pl.tail.size() / tail_w);
+    pl.tail_form = tail_form;
   }
   if (!longs.empty()) pl.halo = halo;
   for (int b : longs) {
@@ -449,8 +466,9 @@ uint64_t offsets_hash(const std::vector<int64_t>& off, std::initializer_list<int
   return h;
 }
 
-uint64_t plan_key(const std::vector<int64_t>& off, int W, int halo, int round, int tail_W, int device) {
-  return offsets_hash(off, {W, halo, round, tail_W, device});
+uint64_t plan_key(const std::vector<int64_t>& off, int W, int halo, int round, int tail_W, int tail_form,
+                  int device) {
+  return offsets_hash(off, {W, halo, round, tail_W, tail_form, device});
 }
 
 // Copy the tables of plan pl (lane map, chain table, tail lane map) to dst, in that order.
@@ -466,13 +484,12 @@ hipError_t upload_plan(const Plan& pl, int32_t* dst, hipStream_t st, bool async)
   return e;
 }
 
-// The cached plan of this shape, building and uploading it on first use (round, tail_W: see
-// make_plan).
-top_status get_plan(const std::vector<int64_t>& off, int W, int halo, int round, int tail_W,
+// The cached plan of this shape, building and uploading it on first use (the tail: see make_plan).
+top_status get_plan(const std::vector<int64_t>& off, int W, int halo, const TailSpec& ts,
                     std::shared_ptr<PlanEntry>* out) {
   int dev = 0;
   TOP_HIP(hipGetDevice(&dev));
-  const uint64_t key = plan_key(off, W, halo, round, tail_W, dev);
+  const uint64_t key = plan_key(off, W, halo, ts.round, ts.W, ts.form, dev);
   {
     std::lock_guard<std::mutex> lk(g_plan_mu);
     auto it = g_plans.find(key);
@@ -482,7 +499,7 @@ top_status get_plan(const std::vector<int64_t>& off, int W, int halo, int round,
     }
   }
   auto e = std::make_shared<PlanEntry>();
-  e->plan = make_plan(off, W, halo, round, tail_W);
+  e->plan = make_plan(off, W, halo, ts.round, ts.W, ts.form);
   e->off = off;
   e->device = dev;
   const size_t bytes = e->plan.table_elems() * sizeof(int32_t);
@@ -817,14 +834,16 @@ struct top_problem {
                  : (axis_of(pl) && rec == nullptr) ? top::launch_sweep_axis<R>(v, a, pl.n_tiles, st)
                            : top::launch_sweep<R>(v, a, pl.n_tiles, st);
     if (e == hipSuccess && pl.tail_tiles > 0) {
-      // the tail's trajectories: the same sweeps, one lane per segment and axis (the plan has a tail
-      // only where that kernel takes the variant; no tape, no checks, nothing split)
-      if (rec != nullptr || a.done != nullptr || chain)
-        return fail(TOP_E_STATE, "a plan with a tail launch cannot record, check or chain");
+      // the tail's trajectories: the same sweeps, with one lane per segment and axis (where that
+      // kernel takes the variant: no checks) or with the main kernel on the tail's narrower tiles
+      if (rec != nullptr || chain || (pl.tail_form == 3 && a.done != nullptr))
+        return fail(TOP_E_STATE, "this plan's tail launch cannot record, chain or check");
       top::SweepArgs<R> t = a;
       t.lane_seg = lane_map + pl.tail_offset();
       t.W = pl.tail_W;
-      e = top::launch_sweep_axis<R>(v, t, pl.tail_tiles, st);
+      e = pl.tail_form == 3 ? top::launch_sweep_axis<R>(v, t, pl.tail_tiles, st)
+        : v.faces           ? top::launch_poly_sweep<R>(v, t, pl.tail_tiles, st)
+                            : top::launch_sweep<R>(v, t, pl.tail_tiles, st);
     }
     if (e != hipSuccess) return fail(TOP_E_HIP, "sweep launch failed: %s", hipGetErrorString(e));
     return TOP_OK;
@@ -1561,9 +1580,8 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
   int W = 0, halo = 0, form = 0;
   if ((st = choose_plan(v, opt, off, taped, &W, &halo, &form)) != TOP_OK) return st;
   Plan own_plan;
-  int round = 0, tail_W = 0;
-  tail_spec(v, opt, W, form, &round, &tail_W);
-  if (mem == Mem::kStatic) own_plan = make_plan(off, W, halo, round, tail_W);
+  const TailSpec ts = tail_spec(v, opt, W, form);
+  if (mem == Mem::kStatic) own_plan = make_plan(off, W, halo, ts.round, ts.W, ts.form);
   // The workspace must hold this problem's buffers (checked before any device work).
   size_t ws_pad = 0;
   const int64_t n_chunks = count_chunks(seg_offsets, n_traj);
@@ -1715,7 +1733,7 @@ static top_status create_impl(int32_t n_traj, const int64_t* seg_offsets, const 
     hipError_t e = hipMemcpyAsync(h->tape, h->state[0], (size_t)h->nf * ld * R, hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return bail(fail(TOP_E_HIP, "tape copy failed: %s", hipGetErrorString(e)));
   }
-  if (mem != Mem::kStatic && (st = get_plan(h->off, W, halo, round, tail_W, &h->pe)) != TOP_OK) return bail(st);
+  if (mem != Mem::kStatic && (st = get_plan(h->off, W, halo, ts, &h->pe)) != TOP_OK) return bail(st);
   // the input check's verdict
   int bad = 0;
   {
@@ -1944,7 +1962,7 @@ top_status top_plan_tiles(int32_t n_traj, const int64_t* seg_offsets, int32_t ti
     return fail(TOP_E_INVALID, "tiles_per_round must be >= 0, and with it tail_tile_lanes a multiple of 64 in [64, %d]",
                 top::kAxisTileMax);
   const std::vector<int64_t> off(seg_offsets, seg_offsets + n_traj + 1);
-  const Plan pl = make_plan(off, tile_lanes, halo, tiles_per_round, tiles_per_round > 0 ? tail_tile_lanes : 0);
+  const Plan pl = make_plan(off, tile_lanes, halo, tiles_per_round, tiles_per_round > 0 ? tail_tile_lanes : 0, 3);
   const size_t n_lanes = pl.lanes.size() + pl.tail.size();
   if (lanes != nullptr && lanes_cap < (int64_t)n_lanes)
     return fail(TOP_E_INVALID, "lanes holds %lld entries; the plan has %zu", (long long)lanes_cap, n_lanes);
@@ -2017,9 +2035,7 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   int probe_dev = 0;
   for (const TuneChoice& c : cands) {
     std::shared_ptr<PlanEntry> cand;
-    int round = 0, tail_W = 0;
-    tail_spec(h->v, h->opt, c.W, c.form, &round, &tail_W);
-    s = get_plan(h->off, c.W, c.halo > 0 ? c.halo : 1, round, tail_W, &cand);
+    s = get_plan(h->off, c.W, c.halo > 0 ? c.halo : 1, tail_spec(h->v, h->opt, c.W, c.form), &cand);
     if (s != TOP_OK) break;
     const Plan& pl = cand->plan;
     h->probe_plan = &pl;
@@ -2088,10 +2104,8 @@ top_status top_tune(top_problem* h, int32_t k_probe) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (s != TOP_OK) return s;
-  int round = 0, tail_W = 0;
-  tail_spec(h->v, h->opt, bestc.W, bestc.form, &round, &tail_W);
-  s = get_plan(h->off, bestc.W, bestc.halo > 0 ? bestc.halo : std::max(1, std::min(32, bestc.W / 8)), round, tail_W,
-               &h->pe);
+  s = get_plan(h->off, bestc.W, bestc.halo > 0 ? bestc.halo : std::max(1, std::min(32, bestc.W / 8)),
+               tail_spec(h->v, h->opt, bestc.W, bestc.form), &h->pe);
   if (s != TOP_OK) return s;
   h->axis = bestc.form == 3;
   h->drop_graphs();

@@ -179,6 +179,9 @@ hipError_t launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
 // the same launch for a general polytope corridor (v.faces = kFaces)
 template <typename R>
 hipError_t launch_poly_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);
+// Tiles of W lanes of that sweep the device holds at once, or 0.
+template <typename R>
+int poly_resident(const Variant& v, int W);
 // the same launch with the NumericSolve local update (v.num = 1)
 template <typename R>
 hipError_t launch_numeric_sweep(const Variant& v, const SweepArgs<R>& a, int n_tiles, hipStream_t st);

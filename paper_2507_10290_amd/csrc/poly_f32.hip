@@ -8,4 +8,9 @@ hipError_t launch_poly_sweep<float>(const Variant& v, const SweepArgs<float>& a,
   return dispatch_poly_sweep<float>(v, a, n_tiles, st);
 }
 
+template <>
+int poly_resident<float>(const Variant& v, int W) {
+  return resident_poly<float>(v, W);
+}
+
 }  // namespace top

@@ -8,4 +8,9 @@ hipError_t launch_poly_sweep<double>(const Variant& v, const SweepArgs<double>& 
   return dispatch_poly_sweep<double>(v, a, n_tiles, st);
 }
 
+template <>
+int poly_resident<double>(const Variant& v, int W) {
+  return resident_poly<double>(v, W);
+}
+
 }  // namespace top

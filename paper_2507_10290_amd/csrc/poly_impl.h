@@ -348,4 +348,36 @@ hipError_t dispatch_poly_sweep(const Variant& v, const SweepArgs<R>& a, int n_ti
   return hipErrorInvalidValue;
 }
 
+// Tiles of W lanes of the instance dispatch_poly_sweep launches for v that the device holds at
+// once (0 if the runtime does not say).
+template <typename R>
+int resident_poly(const Variant& v, int W) {
+  if (v.faces != kFaces || v.box || W <= 0 || (W & 63) != 0) return 0;
+  constexpr bool hl3 = std::is_same<R, float>::value;
+  void* k = nullptr;
+  size_t lds = 0;
+#define TOP_POLY_RES(P_, S_, V_)                                                              \
+  if (k == nullptr && v.p == P_ && v.s == S_ && (v.vel != 0) == V_) {                       \
+    constexpr bool HL_ = hl3 && P_ == 3;                                                    \
+    constexpr int NH_ = 2 * P_ * (2 * P_ + 1) / 2;                                          \
+    if (W > (HL_ ? 512 : 256)) return 0;                                                    \
+    lds = HL_ ? (size_t)3 * NH_ * 512 * sizeof(R) : 0;                                      \
+    k = reinterpret_cast<void*>(poly_sweep_kernel<R, P_, S_, V_, HL_ ? 512 : 256, HL_, HL_ ? 2 : 1>); \
+  }
+  TOP_POLY_RES(3, 3, true) TOP_POLY_RES(3, 3, false)
+  TOP_POLY_RES(3, 4, true) TOP_POLY_RES(3, 4, false)
+  TOP_POLY_RES(4, 4, true) TOP_POLY_RES(4, 4, false)
+  TOP_POLY_RES(4, 5, true) TOP_POLY_RES(4, 5, false)
+  TOP_POLY_RES(3, 5, true) TOP_POLY_RES(3, 5, false)
+  TOP_POLY_RES(4, 7, true) TOP_POLY_RES(4, 7, false)
+#undef TOP_POLY_RES
+  if (k == nullptr) return 0;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (lds > 0 && hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, W, lds) != hipSuccess) return 0;
+  return per_cu * cus;
+}
+
 }  // namespace top

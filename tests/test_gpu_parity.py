@@ -462,3 +462,38 @@ def test_tail_launch_gives_the_same_bits():
     finally:
         tail.close()
         ref.close()
+
+
+@pytest.mark.parametrize("case", ["polytope", "checks"])
+def test_one_lane_tail_gives_the_same_bits(case):
+    # Where one lane per axis is not available (polytope corridors, residual checks) the tail runs the
+    # plan's own kernel on tiles of half the width; 64-segment tiles (no tail: half of them is too
+    # narrow) give the reference bits.
+    from paper_2507_10290_amd import TopProblem
+    kw = {}
+    if case == "polytope":
+        w = make_config(5)
+    else:
+        w = make_config(3)
+        kw = dict(check_every=10, adapt_rho=True)
+    tail = TopProblem.from_workload(w, precision="fp32", **kw)
+    ref = TopProblem.from_workload(w, precision="fp32", tile_lanes=64, **kw)
+    try:
+        plan = tail.plan()
+        print(f"[tail] {case} plan {plan}", flush=True)
+        assert plan["lane_form"] == 1 and plan["tail_tiles"] > 0 and plan["tail_tile_lanes"] <= plan["tile_lanes"] // 2
+        assert ref.plan()["tail_tiles"] == 0
+        for k in (20, 10):
+            tail.iterate(k)
+            ref.iterate(k)
+            torch.cuda.synchronize()
+            assert torch.equal(tail.coeffs(), ref.coeffs()), k
+            assert torch.equal(tail.cost(), ref.cost()), k
+        if case == "checks":
+            for x, y in zip(tail.convergence(), ref.convergence()):
+                assert torch.equal(x, y)
+        tail.sync_status()
+        ref.sync_status()
+    finally:
+        tail.close()
+        ref.close()
