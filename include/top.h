@@ -310,7 +310,8 @@ typedef struct top_plan_info {
                                 the device holding only a few of them, those tiles' trajectories
                                 run there instead, one lane per segment and axis where that form
                                 takes the variant and options, else in the plan's own form on
-                                tiles of at most half the width; not with a tape or NumericSolve */
+                                tiles of at most half the width; not with a tape, residual
+                                checks or NumericSolve                                          */
   int32_t tail_tile_lanes;   /* segments per tail tile                                          */
 } top_plan_info;
 
