@@ -498,9 +498,10 @@ def main():
                     help="skip the autotuning of the batched workload's plan (keep the default plan)")
     ap.add_argument("--counters-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="print the markdown summary of two rocprofv3 counter runs and exit (no GPU)")
-    ap.add_argument("--leg", choices=["fwd_bwd", "septic"],
-                    help="run one extra leg alone (the differentiation workload's forward and backward, or "
-                         "the 65,536-segment septic solve), print its figures and exit; for profilers")
+    ap.add_argument("--leg", choices=["fwd_bwd", "septic", "numeric"],
+                    help="run one extra leg alone (the differentiation workload's forward and backward, "
+                         "the 65,536-segment septic solve, or NumericSolve on 256 batched trajectories in "
+                         "both lane forms), print its figures and exit; for profilers")
     ap.add_argument("--tile-lanes", type=int, default=0,
                     help="with --leg: an explicit tile width for that leg's handles (0: the default plan)")
     ap.add_argument("--solve-config", type=int, nargs="+", metavar="I",
@@ -540,6 +541,20 @@ def main():
     if a.leg == "septic":
         w2 = make_config(2)
         print(json.dumps({"septic_65536": septic_leg(w2, _dev_inputs(w2, dev))}), flush=True)
+        return
+    if a.leg == "numeric":
+        # one solve each with one lane per segment and with four (the default), K = 50
+        wn = make_config(3, n_traj=256)
+        dn = _dev_inputs(wn, dev)
+        out = {}
+        for form in (1, 3):
+            prob = _problem(wn, dn, precision="fp32", numeric=True, lbfgs_iters=10, lane_form=form)
+            prob.iterate(50)
+            prob.cost()
+            out[f"lane_form_{form}"] = prob.plan()
+            prob.close()
+        torch.cuda.synchronize()
+        print(json.dumps({"numeric": out}), flush=True)
         return
     w = make_config(3)
     K = w.iters
