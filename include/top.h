@@ -326,11 +326,13 @@ top_status top_get_plan(const top_problem* h, top_plan_info* info);
  *   halo         1 <= halo < tile_lanes / 2: segment copies on each side a split trajectory's tile
  *                keeps, and the sweeps per launch
  *   tiles_per_round  tiles the device holds at once (top_create asks the runtime), or 0 for no tail
- *   tail_tile_lanes  segments per tail tile, a multiple of 64 in [64, 320] (ignored when
- *                tiles_per_round is 0).  When no trajectory is split and the last round would hold
- *                at most tiles_per_round / 8 tiles, those tiles' trajectories are repacked
- *                (first-fit decreasing) into tail tiles of this width, run by a second launch with
- *                one lane per segment and axis
+ *   tail_tile_lanes  widest tail tile, a multiple of 64 in [64, 320] (ignored when
+ *                tiles_per_round is 0).  When no trajectory is split and the tiles would leave a
+ *                last round of k <= tiles_per_round / 8 tiles, the trajectories of the k tiles whose
+ *                longest trajectory is shortest (then the least filled) are repacked, first-fit
+ *                decreasing, into tail tiles as wide as that longest trajectory rounded up to 64
+ *                (none if that exceeds tail_tile_lanes), for a second launch (top_create runs it
+ *                with one lane per segment and axis where that form takes the variant)
  *   lanes        [host] int32 [n_tiles][tile_lanes] then [tail_tiles][tail_tile_lanes], or NULL: per
  *                lane its segment (global index), | TOP_HALO_BIT for a halo copy, -1 for an idle
  *                lane.  Trajectories of at most tile_lanes segments share tiles, packed first-fit
