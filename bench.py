@@ -246,7 +246,7 @@ def fwd_bwd(w, d, K, m, reps=3, **kw):
 def septic_leg(w2, d2):
     """The 65,536-segment septic trajectory: tuned plan, whole solves, and the sweep launches alone."""
     pt = _problem(w2, d2, precision="fp32")
-    pt.tune(32)
+    pt.tune(96)   # probes of several epochs, so that halo widths are compared with their boundaries
     pt.close()
     sec2 = time_steps(lambda: solve_step(w2, d2, w2.iters), 2, 1)
     ph2 = phase_ms(w2, d2, w2.iters)
