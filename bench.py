@@ -513,7 +513,7 @@ def main():
         return
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the batched sweep has no cross-GPU exchange "
-              "(trajectories shard by count; see the design notes). Run with --gpus 1.", file=sys.stderr)
+              "(across GPUs the trajectories would shard by segment count). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
